@@ -1,0 +1,291 @@
+"""ctypes binding of the plain FP64 CPU oracle (``kt_oracle.c``).
+
+TEST INFRASTRUCTURE: only the tests, the smoke check and the CPU-baseline leg
+of the benchmark import this package.  It never imports the HIP library and
+the HIP library never imports it.
+
+Arrays are arrays of structures: ``q`` is (ncell, 15) with the component
+order of Sec. 3.1 (T^{tau mu}, pi^{tt,tx,ty,te,xx,xy,xe,yy,ye,ee}, Pi), ``u``
+is (ncell, 4); the cell index runs x fastest, eta slowest.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kt_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+NQ = 15
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP contraction off, OpenMP over cells)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                        "-Wall", "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("neta", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("deta", C.c_double),
+                ("dtau", C.c_double), ("cartesian", C.c_int32), ("periodic", C.c_int32 * 3),
+                ("theta", C.c_double), ("eta_s", C.c_double), ("zeta_coef", C.c_double),
+                ("taupipi", C.c_double), ("regulate", C.c_int32), ("xi0", C.c_double),
+                ("rho_max", C.c_double), ("e_floor", C.c_double), ("newton_tol", C.c_double),
+                ("newton_max", C.c_int32), ("regulate_bulk", C.c_int32),
+                ("m2_delta", C.c_double), ("floor_resets_q", C.c_int32)]
+
+
+class _EOS(C.Structure):
+    _fields_ = [("conformal", C.c_int32), ("a_sb", C.c_double), ("n", C.c_int32),
+                ("ln_e0", C.c_double), ("dln", C.c_double),
+                ("p", C.POINTER(C.c_double)), ("cs2", C.POINTER(C.c_double)),
+                ("T", C.POINTER(C.c_double))]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("newton_iters", C.c_int64), ("n_recover", C.c_int64), ("n_floor", C.c_int64),
+                ("n_clamp", C.c_int64), ("n_fallback", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int32)
+        P, E = C.POINTER(_Params), C.POINTER(_EOS)
+        L.ora_tmunu.argtypes = [P, E, C.c_double, C.c_int64, dp, dp, dp, dp, dp]
+        L.ora_recover.argtypes = [P, E, C.c_double, C.c_int64, dp, dp, dp, ip, ip]
+        L.ora_regulate.argtypes = [P, E, C.c_double, C.c_int64, dp, dp, dp, dp]
+        L.ora_eos_eval.argtypes = [E, C.c_int64, dp, dp, dp, dp]
+        L.ora_init.argtypes = [P, E, C.c_double, dp, dp, dp, dp]
+        L.ora_rhs.argtypes = [P, E, C.c_double, dp, dp, dp, dp, dp]
+        L.ora_step.argtypes = [P, E, dp, dp, dp, dp, dp, C.c_int32, C.POINTER(_Stats)]
+        L.ora_step.restype = C.c_int
+        L.ora_kinematics.argtypes = [C.c_double, C.c_int32, dp, dp, dp]
+        L.ora_second_order.argtypes = [C.c_double, C.c_int32, dp, dp, dp, dp]
+        L.ora_gpi.argtypes = [C.c_double, C.c_int32, dp, dp, dp]
+        L.ora_minmod3.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.ora_minmod3.restype = C.c_double
+        L.ora_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    if a is None:
+        return None
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+@dataclass
+class Physics:
+    """Grid and physics parameters of one run (the oracle's own copy)."""
+    nx: int
+    ny: int
+    neta: int
+    dx: float
+    dy: float
+    deta: float
+    dtau: float
+    cartesian: bool = False
+    periodic: tuple = (False, False, False)
+    theta: float = 1.0
+    eta_s: float = 0.0
+    zeta_coef: float = 0.0
+    taupipi: float = 10.0 / 7.0
+    regulate: bool = True
+    xi0: float = 0.1
+    rho_max: float = 1.0
+    e_floor: float = 1e-7 / 0.1973269804
+    newton_tol: float = 1e-12
+    newton_max: int = 50
+    regulate_bulk: bool = True
+    m2_delta: float = 1e-3
+    floor_resets_q: bool = True
+
+    @classmethod
+    def from_config(cls, grid, cfg: dict):
+        keys = cls.__dataclass_fields__.keys()
+        kw = {k: v for k, v in cfg.items() if k in keys}
+        return cls(nx=grid.nx, ny=grid.ny, neta=grid.neta, dx=grid.dx, dy=grid.dy,
+                   deta=grid.deta, **kw)
+
+    def c(self) -> _Params:
+        return _Params(self.nx, self.ny, self.neta, self.dx, self.dy, self.deta, self.dtau,
+                       int(self.cartesian), (C.c_int32 * 3)(*[int(b) for b in self.periodic]),
+                       self.theta, self.eta_s, self.zeta_coef, self.taupipi, int(self.regulate),
+                       self.xi0, self.rho_max, self.e_floor, self.newton_tol, self.newton_max,
+                       int(self.regulate_bulk), self.m2_delta, int(self.floor_resets_q))
+
+    @property
+    def ncells(self):
+        return self.nx * self.ny * self.neta
+
+
+class EOSRef:
+    """Holds the C view of an EOS description (keeps the arrays alive)."""
+
+    def __init__(self, eos):
+        self.eos = eos
+        if eos.conformal:
+            self._arrs = ()
+            self.c = _EOS(1, eos.a_sb, 0, 0.0, 0.0, None, None, None)
+        else:
+            self._arrs = tuple(np.ascontiguousarray(a, dtype=np.float64) for a in (eos.p, eos.cs2, eos.T))
+            self.c = _EOS(0, eos.a_sb, len(self._arrs[0]), eos.ln_e0, eos.dln_e,
+                          *[_dp(a) for a in self._arrs])
+
+
+def eos_eval(eos, e):
+    ref = EOSRef(eos)
+    e = np.ascontiguousarray(e, dtype=np.float64).ravel()
+    p, c2, T = np.empty_like(e), np.empty_like(e), np.empty_like(e)
+    lib().ora_eos_eval(C.byref(ref.c), e.size, _dp(e), _dp(p), _dp(c2), _dp(T))
+    return p, c2, T
+
+
+def aos_from_prims(prims):
+    """(ncell,) e, (ncell,4) u, (ncell,10) pi, (ncell,) Pi from component-first arrays."""
+    n = prims.e.size
+    e = np.ascontiguousarray(prims.e.reshape(n), dtype=np.float64)
+    u = np.ascontiguousarray(prims.u.reshape(4, n).T, dtype=np.float64)
+    pi = np.ascontiguousarray(prims.pi.reshape(10, n).T, dtype=np.float64)
+    Pi = np.ascontiguousarray(prims.Pi.reshape(n), dtype=np.float64)
+    return e, u, pi, Pi
+
+
+def tmunu(phys: Physics, eos, tau, e, u, pi, Pi):
+    ref = EOSRef(eos)
+    n = e.shape[0]
+    q = np.empty((n, NQ))
+    P = phys.c()
+    lib().ora_tmunu(C.byref(P), C.byref(ref.c), tau, n, _dp(e), _dp(u), _dp(pi), _dp(Pi), _dp(q))
+    return q
+
+
+def recover(phys: Physics, eos, tau, q):
+    ref = EOSRef(eos)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    n = q.shape[0]
+    e = np.empty(n)
+    u = np.empty((n, 4))
+    it = np.empty(n, np.int32)
+    fl = np.empty(n, np.int32)
+    P = phys.c()
+    lib().ora_recover(C.byref(P), C.byref(ref.c), tau, n, _dp(q), _dp(e), _dp(u), _ip(it), _ip(fl))
+    return e, u, it, fl
+
+
+def regulate(phys: Physics, eos, tau, q, e, u):
+    ref = EOSRef(eos)
+    q = np.array(q, dtype=np.float64, order="C")
+    fac = np.empty(q.shape[0])
+    P = phys.c()
+    lib().ora_regulate(C.byref(P), C.byref(ref.c), tau, q.shape[0], _dp(q),
+                       _dp(np.ascontiguousarray(e)), _dp(np.ascontiguousarray(u)), _dp(fac))
+    return q, fac
+
+
+def kinematics(tau, cartesian, u, du):
+    out = np.empty(53)
+    lib().ora_kinematics(tau, int(cartesian), _dp(np.ascontiguousarray(u, float)),
+                         _dp(np.ascontiguousarray(du, float).ravel()), _dp(out))
+    return dict(theta=out[0], sigma=out[1:17].reshape(4, 4), omega=out[17:33].reshape(4, 4),
+                Du_lo=out[33:37], Delta=out[37:53].reshape(4, 4))
+
+
+def second_order(tau, cartesian, u, du, pi16):
+    out = np.empty(65)
+    lib().ora_second_order(tau, int(cartesian), _dp(np.ascontiguousarray(u, float)),
+                           _dp(np.ascontiguousarray(du, float).ravel()),
+                           _dp(np.ascontiguousarray(pi16, float).ravel()), _dp(out))
+    return dict(I1=out[0:16].reshape(4, 4), I2=out[16:32].reshape(4, 4),
+                I3=out[32:48].reshape(4, 4), I4=out[48:64].reshape(4, 4), pi_sigma=out[64])
+
+
+def gpi(tau, cartesian, u, pi16):
+    out = np.empty(16)
+    lib().ora_gpi(tau, int(cartesian), _dp(np.ascontiguousarray(u, float)),
+                  _dp(np.ascontiguousarray(pi16, float).ravel()), _dp(out))
+    return out.reshape(4, 4)
+
+
+def minmod3(x, y, z):
+    return lib().ora_minmod3(float(x), float(y), float(z))
+
+
+def num_threads() -> int:
+    return int(lib().ora_num_threads())
+
+
+class Simulation:
+    """Oracle state: q, e, u, u_prev (AoS) and tau; steps in place."""
+
+    def __init__(self, phys: Physics, eos, tau0: float, q: np.ndarray):
+        self.phys = phys
+        self.eos_ref = EOSRef(eos)
+        self.tau = float(tau0)
+        n = phys.ncells
+        self.q = np.array(q, dtype=np.float64, order="C").reshape(n, NQ)
+        self.e = np.empty(n)
+        self.u = np.empty((n, 4))
+        self.up = np.empty((n, 4))
+        self.step_count = 0
+        self.stats = _Stats()
+        self._P = phys.c()
+        lib().ora_init(C.byref(self._P), C.byref(self.eos_ref.c), self.tau, _dp(self.q),
+                       _dp(self.e), _dp(self.u), _dp(self.up))
+
+    @classmethod
+    def from_primitives(cls, phys: Physics, eos, prims):
+        e, u, pi, Pi = aos_from_prims(prims)
+        q = tmunu(phys, eos, prims.tau0, e, u, pi, Pi)
+        return cls(phys, eos, prims.tau0, q)
+
+    def step(self, n: int = 1):
+        tau = C.c_double(self.tau)
+        rc = lib().ora_step(C.byref(self._P), C.byref(self.eos_ref.c), C.byref(tau), _dp(self.q),
+                            _dp(self.e), _dp(self.u), _dp(self.up), int(n), C.byref(self.stats))
+        if rc != 0:
+            raise MemoryError("oracle step could not allocate its work arrays")
+        self.tau = tau.value
+        self.step_count += n
+        return self
+
+    def rhs(self):
+        out = np.empty_like(self.q)
+        lib().ora_rhs(C.byref(self._P), C.byref(self.eos_ref.c), self.tau, _dp(self.q),
+                      _dp(self.e), _dp(self.u), _dp(self.up), _dp(out))
+        return out
+
+    # component-first views for comparisons
+    def shape(self):
+        return (self.phys.neta, self.phys.ny, self.phys.nx)
+
+    def fields(self):
+        s = self.shape()
+        return dict(e=self.e.reshape(s).copy(),
+                    u=self.u.T.reshape((4,) + s).copy(),
+                    up=self.up.T.reshape((4,) + s).copy(),
+                    q=self.q.T.reshape((NQ,) + s).copy())
