@@ -1,0 +1,141 @@
+"""Benchmark: Heun steps of the 128^3 non-conformal viscous hot-spot event (FP64).
+
+One step is one full Heun step of the KT scheme (two stages, two recoveries)
+over the whole 128^3 grid.  Prints one JSON line:
+  value        cell-updates/s (128^3 cells x steps / seconds), inputs resident in HBM
+  roofline     the KT stage kernel: algorithmic bytes per launch / mean launch time
+               (HIP events on the library's stream, recorded in the timed region)
+  cpu_baseline the FP64 CPU oracle on a bounded sample of the same event
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--copy-probe]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+METRIC = "cell-updates/s per Heun step (128^3 viscous), % HBM peak; learned vs Newton"
+# algorithmic values moved per cell (8 bytes each in FP64):
+#   stage 1 reads q^n (15), u^n (4), u^{n-1} (4), e^n (1) and writes q* (15)            = 39
+#   stage 2 reads q* (15), u* (4), e* (1), u^n (4), q^n (15) and writes q^{n+1} (15)     = 54
+#   one Heun step moves 103 values when recovery is fused with the stages
+STAGE_VALUES = (39, 54)
+STEP_VALUES = 103
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of known size (for counter scaling)")
+    ap.add_argument("--n", type=int, default=128, help="grid cells per axis")
+    return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+    n = 256 * 1024 * 1024 // 8          # 256 MiB of doubles
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                      "launches": 3}), flush=True)
+
+
+def cpu_baseline(w, budget_s):
+    import oracle
+    phys = oracle.Physics.from_config(w.grid, w.config)
+    t0 = time.perf_counter()
+    sim = oracle.Simulation.from_primitives(phys, w.eos, w.prims)
+    t_init = time.perf_counter() - t0
+    steps = 0
+    t1 = time.perf_counter()
+    while steps < 1 or (time.perf_counter() - t1 < budget_s and steps < 5):
+        sim.step(1)
+        steps += 1
+    dt = time.perf_counter() - t1
+    return {"value": w.grid.ncells * steps / dt, "unit": "cell-updates/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d Heun step(s) of the same %dx%dx%d event from its initial state "
+                      "(%.1f s, plus %.1f s initial recovery)" % (steps, w.grid.nx, w.grid.ny,
+                                                                  w.grid.neta, dt, t_init)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr, flush=True)
+        sys.exit(2)
+    import torch
+    if args.copy_probe:
+        copy_probe()
+        return
+    from paper_1608_06577_amd import inputs as I
+    from paper_1608_06577_amd import kt
+
+    w = I.workload_hotspot(nx=args.n, ny=args.n, neta=args.n)
+    ncell = w.grid.ncells
+    solver = kt.Solver(w.grid, w.config, w.eos, w.prims, device="cuda:0")
+    print("bench: %s, warmup %d steps" % (w.name, args.warmup), file=sys.stderr, flush=True)
+    solver.profile(True)
+    solver.step(args.warmup)
+    solver.profile_read()          # discard warm-up timings, keeps the event pool
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    solver.step(args.steps)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / args.steps
+    prof = solver.profile_read()
+    obs = solver.observables()
+    print("bench: timed %d steps, %.3f ms/step, stage %.3f ms/launch, recover %.3f ms/launch"
+          % (args.steps, ms, prof["stage_ms"] / max(1, prof["stage_launches"]),
+             prof["recover_ms"] / max(1, prof["recover_launches"])), file=sys.stderr, flush=True)
+    value = ncell / (ms * 1e-3)
+    stage_avg_s = prof["stage_ms"] / prof["stage_launches"] * 1e-3
+    stage_bytes = 8.0 * ncell * sum(STAGE_VALUES) / len(STAGE_VALUES)
+    achieved = stage_bytes / stage_avg_s / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "stage_kernel (KT flux + sources + Euler/Heun update)",
+            "bytes_per_launch": stage_bytes, "mean_launch_ms": stage_avg_s * 1e3}
+    rec = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": [w.grid.nx, w.grid.ny, w.grid.neta],
+                   "dx_fm": w.grid.dx, "deta": w.grid.deta, "tau0": w.tau0,
+                   "dtau": w.config["dtau"], "eta_over_s": w.config["eta_s"],
+                   "zeta_over_s": "0.1 (1/3 - c_s^2)", "eos": "tabulated, 4096 nodes",
+                   "precision": "fp64", "inversion_start": "conformal closed form",
+                   "step_hbm_frac": STEP_VALUES * 8.0 * value / (HBM_PEAK_GBS * 1e9),
+                   "paper_context_ms_per_step": {"gtx980ti_fp32_128cube": 244.45}},
+        "roofline": roof,
+        "diagnostics": {k: obs[k] for k in ("tau", "n_nan", "n_floor", "n_clamp", "n_fallback",
+                                            "e_max", "cfl")},
+    }
+    solver.close()
+    if not args.no_cpu:
+        print("bench: CPU oracle baseline (bounded sample)", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * kt.h -- C ABI of the MI355X Kurganov-Tadmor step library.
+ *
+ * One Kurganov-Tadmor (KT) semi-discrete step with Heun (two-stage SSP
+ * Runge-Kutta) time integration of (3+1)d second-order viscous hydrodynamics
+ * in Milne coordinates (tau, x, y, eta_s), for T^{tau mu}, the shear stress
+ * pi^{mu nu} and the bulk pressure Pi, with per-cell recovery of the energy
+ * density e and the flow u^mu.  Bazow, Heinz & Strickland, arXiv:1608.06577:
+ * equations of motion in Sec. 2.4 and App. B, numerical scheme in Sec. 3.1,
+ * regulator in Sec. 3.2, lattice and boundary conditions in Sec. 4.1, program
+ * flow of one time step in Sec. 4.3.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units: fm-based natural units; e, p in fm^-4, T in fm^-1, tau in fm/c,
+ *        x, y in fm, eta_s dimensionless.
+ * Layout: every field is a separate device array (structure of arrays) over
+ *        the physical cells only, nx*ny*neta doubles, x fastest and eta_s
+ *        slowest: cell (i, j, k) is element (k*ny + j)*nx + i.  Ghost cells
+ *        are not stored: the boundary conditions of Sec. 4.1 (copy of the
+ *        outermost layer) or periodic wrap are applied by index.
+ * Components of the evolved vector q (Sec. 3.1, Eq. qComponents), in order:
+ *        0..3   T^{tau tau}, T^{tau x}, T^{tau y}, T^{tau eta}
+ *        4..13  pi^{tau tau}, pi^{tau x}, pi^{tau y}, pi^{tau eta}, pi^{xx},
+ *               pi^{xy}, pi^{x eta}, pi^{yy}, pi^{y eta}, pi^{eta eta}
+ *        14     Pi
+ *        u^mu is contravariant: (u^tau, u^x, u^y, u^eta), u^eta in fm^-1.
+ * Ownership: the caller owns every device buffer (workspace, inputs,
+ *        outputs) and every host array; the library keeps pointers into the
+ *        workspace only, which must outlive the context.
+ * Streams: all device work is ordered on the stream given to kt_init.
+ *        kt_init and kt_observables synchronise that stream; nothing else
+ *        blocks.
+ * Errors: every call returns a kt_status and never aborts.  Argument errors
+ *        are detected before any device work.  Device faults surface as
+ *        KT_E_HIP at the next synchronising call.  kt_last_error(ctx)
+ *        (kt_last_error(NULL) for failures without a context) gives a
+ *        message.  Numerical events (Newton fallbacks, velocity clamps, cells
+ *        at the energy floor, non-finite values) are counts in kt_obs, not
+ *        errors.  A context is not thread safe.
+ */
+#ifndef KT_H
+#define KT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kt_ctx kt_ctx;
+
+typedef enum {
+    KT_OK = 0,
+    KT_E_ARG = 1,          /* invalid argument */
+    KT_E_ALLOC = 2,        /* workspace too small */
+    KT_E_HIP = 3,          /* HIP runtime or device error */
+    KT_E_STATE = 4,        /* call not valid in the context's state */
+    KT_E_UNSUPPORTED = 5   /* valid request this build does not implement */
+} kt_status;
+
+enum { KT_FP64 = 0, KT_MIXED = 1 };
+enum { KT_MILNE = 0, KT_CARTESIAN = 1 };       /* Cartesian: metric diag(1,-1,-1,-1), no geometric sources (Sec. 5.1) */
+enum { KT_BC_OUTFLOW = 0, KT_BC_PERIODIC = 1 };
+
+/* Equation of state (Sec. 2.3).  conformal != 0: p = e/3, c_s^2 = 1/3,
+ * T = (e/a_sb)^{1/4}.  Otherwise a table on n >= 2 ln-uniform nodes
+ * e_i = exp(ln_e0 + i*dln_e) with p_i, cs2_i, T_i (host arrays, read during
+ * kt_init only).  Between nodes p/e, T/e^{1/4} and c_s^2 are interpolated
+ * linearly in ln e; outside the table the end node's p/e, T/e^{1/4}, c_s^2
+ * are kept. */
+typedef struct {
+    int32_t conformal;
+    double a_sb;
+    int32_t n;
+    double ln_e0, dln_e;
+    const double *p, *cs2, *T;
+} kt_eos;
+
+/* Grid, time step and physics of one event. */
+typedef struct {
+    int32_t nx, ny, neta;          /* physical cells, each >= 1 */
+    double dx, dy, deta;           /* cell sizes, > 0 */
+    double tau0, dtau;             /* initial time and step, > 0 */
+    int32_t coords;                /* KT_MILNE or KT_CARTESIAN */
+    int32_t bc[3];                 /* per axis x, y, eta: KT_BC_OUTFLOW or KT_BC_PERIODIC */
+    double theta;                  /* generalized minmod parameter in [1, 2] (Sec. 3.1) */
+    double eta_over_s;             /* eta/s >= 0; 0 = ideal, pi not evolved */
+    double zeta_coef;              /* zeta/s = zeta_coef (1/3 - c_s^2) >= 0; 0 = Pi not evolved */
+    double taupipi;                /* tau_pipi / tau_pi (10/7 near the conformal limit, Sec. 2.2) */
+    int32_t regulate;              /* apply the regulator of Sec. 3.2 */
+    int32_t regulate_bulk;         /* the regulator factor also rescales Pi */
+    double xi0, rho_max;           /* regulator constants (0.1 and 1 in Sec. 3.2) */
+    double e_floor;                /* energy-density floor, > 0 */
+    double m2_delta;               /* velocity clamp margin of the inversion, in (0, 1) */
+    int32_t floor_resets_q;        /* a cell put on the floor gets q = (e_floor,0,0,0; 0; 0) */
+    double newton_tol;             /* stop when |f(e)| <= newton_tol * E, then one more step */
+    int32_t newton_max;            /* Newton iterations before the bisection fallback */
+    int32_t precision;             /* KT_FP64 (KT_MIXED: KT_E_UNSUPPORTED in this build) */
+} kt_params;
+
+/* Initial data on the device.  Either q[0..14] (conserved form; all 15
+ * non-null) or the primitives e, u[4], pi[10] and Pi (all non-null) are
+ * given; from primitives the library forms T^{tau mu} with Eqs. Ttt, Tti of
+ * Sec. 2.4.  u_prev (nullable) is the previous-step flow for resuming a run;
+ * when null u^{-1} = u^0 (Sec. 4.3). */
+typedef struct {
+    const double *q[15];
+    const double *e;
+    const double *u[4];
+    const double *pi[10];
+    const double *Pi;
+    const double *u_prev[4];
+} kt_init_state;
+
+/* Device destinations for kt_observables; every entry may be null. */
+typedef struct {
+    double *e;
+    double *u[4];
+    double *q[15];
+    double *u_prev[4];
+} kt_fields;
+
+/* Diagnostics of the current state (all reductions are deterministic). */
+typedef struct {
+    double tau;
+    int64_t step;
+    double energy;                 /* sum T^{tau tau} * (tau) dx dy deta  (tau only in Milne) */
+    double momentum[3];            /* same for T^{tau x}, T^{tau y}, T^{tau eta} */
+    double e_max, T_max;
+    double v_max;                  /* max over cells and axes of |u^i / u^tau| (eta: times tau) */
+    double cfl;                    /* dtau * max_i |v^i| / d_i */
+    double norm_err;               /* max |u.u - 1| */
+    double pi_transverse;          /* max |pi^{mu nu} u_nu| / sqrt(pi:pi) (tetrad components) */
+    double pi_trace;               /* max |pi^mu_mu| / sqrt(pi:pi) */
+    int64_t n_nan;                 /* cells with a non-finite value in q, e or u */
+    /* recovery counters accumulated since kt_init */
+    int64_t newton_iters_cells, n_recover_cells;
+    int64_t newton_iters_faces, n_recover_faces;
+    int64_t n_floor, n_clamp, n_fallback;
+} kt_obs;
+
+/* Device workspace needed for p and eos (bytes, multiple of 256), 0 if the
+ * arguments are invalid. */
+size_t kt_workspace_bytes(const kt_params *p, const kt_eos *eos);
+
+/* Create a context: copy the EOS into the workspace, form q^0 (from
+ * primitives if given), recover (e^0, u^0) at tau0 (Sec. 2.4, Eqs. eInferred,
+ * utInferred, uiInferred), set u^{-1}.  d_ws: device memory of ws_bytes >=
+ * kt_workspace_bytes(p, eos), 256-byte aligned.  Synchronises stream.
+ * Errors: KT_E_ARG (sizes, spacings, theta outside [1,2], tau0 <= 0 in
+ * Milne, dtau <= 0, e_floor <= 0, table with n < 2, null pointers),
+ * KT_E_ALLOC (workspace too small), KT_E_UNSUPPORTED (precision), KT_E_HIP. */
+kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0,
+                  void *d_ws, size_t ws_bytes, hipStream_t stream, kt_ctx **out);
+
+/* Enqueue n_steps >= 0 full Heun steps (Sec. 3.1, Eqs. step1-finalStep with
+ * s = 2; order of Sec. 4.3): stage 1 at tau^n, recovery and regulation of q*
+ * and stage 2 at tau^{n+1}, Heun average, recovery and regulation of
+ * q^{n+1}.  Asynchronous. */
+kt_status kt_step(kt_ctx *c, int32_t n_steps);
+
+/* Standalone inversion of n cells at time tau (Sec. 2.4 and Sec. 3.2):
+ * in[0..8] = device arrays T^{tau tau}, T^{tau x}, T^{tau y}, T^{tau eta},
+ * pi^{tau tau}, pi^{tau x}, pi^{tau y}, pi^{tau eta}, Pi (Pi may be null = 0).
+ * Outputs e_out[n], u_out[4][n]; iters_out and flags_out (bit 1 floor,
+ * 2 clamp, 4 bisection fallback) may be null.  Uses the context's EOS and
+ * guards; Newton starts from the conformal closed form.  Asynchronous. */
+kt_status kt_recover(kt_ctx *c, int64_t n, double tau, const double *const in[9],
+                     double *e_out, double *const u_out[4], int32_t *iters_out,
+                     int32_t *flags_out);
+
+/* Diagnostics into *host_out (nullable) and, if dev_out is non-null, copies
+ * of the current fields into the given device arrays.  Synchronises. */
+kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch of kt_step.  Kernel classes: 0 = KT stage (flux + sources +
+ * update), 1 = cell recovery and regulator.  kt_profile_enable(c, 1) starts
+ * recording (events are pooled, created on first use); kt_profile_read
+ * synchronises the stream, returns the totals since the last read and
+ * resets them. */
+typedef struct {
+    double ms[4];                  /* summed launch durations per class */
+    int64_t launches[4];
+} kt_profile;
+
+kt_status kt_profile_enable(kt_ctx *c, int32_t on);
+kt_status kt_profile_read(kt_ctx *c, kt_profile *out);
+
+/* Release the context (not the workspace).  Null is allowed. */
+void kt_destroy(kt_ctx *c);
+
+/* Last error message of c, or of the calling thread when c is null. */
+const char *kt_last_error(const kt_ctx *c);
+
+const char *kt_status_string(kt_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KT_H */

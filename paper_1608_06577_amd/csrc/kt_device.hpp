@@ -1,0 +1,360 @@
+// kt_device.hpp -- device functions of the KT/Heun step for gfx950.
+//
+// Bazow, Heinz & Strickland, arXiv:1608.06577.  The tensor algebra of
+// Sec. 2.4 / App. A / App. B is expanded here for the diagonal Milne metric
+// g_{mu nu} = diag(1, -1, -1, -g33), g33 = tau^2 (1 in Cartesian mode), whose
+// only Christoffel symbols are Gamma^eta_{tau eta} = 1/tau and
+// Gamma^tau_{eta eta} = tau.  Everything is FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ktd {
+
+// evolved components (Sec. 3.1, Eq. qComponents)
+enum : int {
+    NQ = 15,
+    TT = 0, TX = 1, TY = 2, TE = 3,
+    PTT = 4, PTX = 5, PTY = 6, PTE = 7, PXX = 8, PXY = 9, PXE = 10, PYY = 11, PYE = 12, PEE = 13,
+    BPI = 14
+};
+
+// recovery flags
+enum : int { F_FLOOR = 1, F_CLAMP = 2, F_FALLBACK = 4 };
+
+// counters accumulated on the device
+enum : int {
+    C_ITERS_CELLS = 0, C_REC_CELLS, C_ITERS_FACES, C_REC_FACES, C_FLOOR, C_CLAMP, C_FALLBACK,
+    C_COUNT
+};
+
+struct Eos {
+    int conformal;
+    double inv_a;          // 1 / a_sb
+    int n;
+    double ln_e0, inv_dln;
+    const double *tab;     // per node: p/e, T/e^{1/4}, c_s^2
+};
+
+struct Phys {
+    int nx, ny, neta;
+    long long ncell, stride;   // cells; distance between component arrays
+    double inv_dx, inv_dy, inv_deta;
+    double dtau, inv_dtau;
+    int periodic[3];
+    double theta;
+    double eta_s, zeta_coef, taupipi;
+    int shear, bulk;
+    int regulate, regulate_bulk, floor_reset;
+    double xi0, rho_max;
+    double e_floor, m2_delta, newton_tol;
+    int newton_max;
+};
+
+__device__ __forceinline__ int pi_index(int m, int n)
+{
+    // symmetric 4x4 -> position in q
+    const int a = m < n ? m : n, b = m < n ? n : m;
+    return a == 0 ? PTT + b : (a == 1 ? PXX + (b - 1) : (a == 2 ? PYY + (b - 2) : PEE));
+}
+
+// ------------------------------------------------------------------ EOS ---
+// Table: p/e, T/e^{1/4}, c_s^2 linear in ln e between bracketing nodes;
+// end-node values outside the table.
+__device__ __forceinline__ void eos_eval(const Eos &E, double e, double &p, double &cs2, double &T)
+{
+    if (E.conformal) {
+        p = e * (1.0 / 3.0);
+        cs2 = 1.0 / 3.0;
+        T = e > 0.0 ? sqrt(sqrt(e * E.inv_a)) : 0.0;
+        return;
+    }
+    const double x = (log(e) - E.ln_e0) * E.inv_dln;
+    int i;
+    double t;
+    if (!(x >= 0.0)) {
+        i = 0;
+        t = 0.0;
+    } else if (x >= (double)(E.n - 1)) {
+        i = E.n - 2;
+        t = 1.0;
+    } else {
+        i = (int)x;
+        if (i > E.n - 2) i = E.n - 2;
+        t = x - (double)i;
+    }
+    const double *a = E.tab + 3 * i;
+    const double r = a[0] + t * (a[3] - a[0]);
+    const double s = a[1] + t * (a[4] - a[1]);
+    cs2 = a[2] + t * (a[5] - a[2]);
+    p = r * e;
+    T = s * sqrt(sqrt(e));
+}
+
+__device__ __forceinline__ double eos_p(const Eos &E, double e)
+{
+    double p, c, T;
+    eos_eval(E, e, p, c, T);
+    return p;
+}
+
+// ------------------------------------------------------------- recovery ---
+// Inversion of Sec. 2.4 (e = E - M^2/(E + P(e)), u^tau, u^i) solved by
+// Newton-Raphson (Sec. 3.2).  Guards: E <= e_floor, E + p(e_floor) + Pi <= 0
+// or non-finite M^2 give the floor state; M^2 is clamped to
+// (1 - m2_delta) W min(E - e_floor, W); conformal EOS without bulk uses the
+// closed form sqrt(4E^2 - 3M^2) - E; otherwise Newton from the conformal
+// value, iterates clamped to [e_floor, E], one extra step after
+// |f| <= tol E, bisection if not converged.
+template <bool CART>
+__device__ __forceinline__ int recover(const Phys &P, const Eos &E, double tau, double Ttt,
+                                       double Ttx, double Tty, double Tte, double ptt,
+                                       double ptx, double pty, double pte, double Pi,
+                                       double &e, double u[4], int &iters)
+{
+    const double ef = P.e_floor;
+    const double g33 = CART ? 1.0 : tau * tau;
+    const double EE = Ttt - ptt;
+    double Mx = Ttx - ptx, My = Tty - pty, Me = Tte - pte;
+    double M2 = Mx * Mx + My * My + g33 * (Me * Me);
+    const double W = EE + eos_p(E, ef) + Pi;
+    iters = 0;
+    if (!(EE > ef) || !(W > 0.0) || !(M2 == M2) || !(M2 < INFINITY)) {
+        e = ef;
+        u[0] = 1.0;
+        u[1] = u[2] = u[3] = 0.0;
+        return F_FLOOR;
+    }
+    int flags = 0;
+    const double M2max = (1.0 - P.m2_delta) * W * fmin(EE - ef, W);
+    if (M2 > M2max) {
+        const double s = sqrt(M2max / M2);
+        Mx *= s;
+        My *= s;
+        Me *= s;
+        M2 = M2max;
+        flags |= F_CLAMP;
+    }
+    const double econf = sqrt(4.0 * EE * EE - 3.0 * M2) - EE;
+    double x;
+    if (E.conformal && !P.bulk) {
+        x = fmax(econf, ef);
+    } else {
+        x = fmin(fmax(econf, ef), EE);
+        bool done = false;
+        int n = 0;
+        while (n < P.newton_max) {
+            double p, cs2, T;
+            eos_eval(E, x, p, cs2, T);
+            const double A = EE + p + Pi;
+            const double f = x - EE + M2 / A;
+            const double df = 1.0 - M2 * cs2 / (A * A);
+            const bool conv = fabs(f) <= P.newton_tol * EE;
+            x = fmin(fmax(x - f / df, ef), EE);
+            ++n;
+            if (conv) {
+                done = true;
+                break;
+            }
+        }
+        iters = n;
+        if (!done) {
+            double lo = ef, hi = EE;
+            for (int k = 0; k < 200; ++k) {
+                const double mid = 0.5 * (lo + hi);
+                const double f = mid - EE + M2 / (EE + eos_p(E, mid) + Pi);
+                x = mid;
+                if (fabs(f) <= P.newton_tol * EE || hi - lo <= 4e-16 * hi) break;
+                if (f < 0.0) lo = mid; else hi = mid;
+            }
+            flags |= F_FALLBACK;
+        }
+    }
+    const double Pc = eos_p(E, x) + Pi;
+    const double ut = sqrt((EE + Pc) / (x + Pc));
+    const double inv = 1.0 / ((x + Pc) * ut);
+    u[0] = ut;
+    u[1] = Mx * inv;
+    u[2] = My * inv;
+    u[3] = Me * inv;
+    e = x;
+    return flags;
+}
+
+// ------------------------------------------------------------ regulator ---
+// Sec. 3.2: rho = max( |Pi^{mu nu}| / (rho_max sqrt(e^2 + 3 P0^2)),
+//                      |pi^mu_mu| / (xi0 rho_max |Pi^{mu nu}|),
+//                      max_l |pi^{l mu} u_mu| / (xi0 rho_max |Pi^{mu nu}|) ),
+// |X| = sqrt(X^{mu nu} X_{mu nu}), Pi^{mu nu} = Pi Delta^{mu nu} + pi^{mu nu},
+// the eta row of pi.u taken in the tetrad (times sqrt(g33)); pi (and Pi
+// when regulate_bulk) are multiplied by tanh(rho)/rho.
+template <bool CART>
+__device__ __forceinline__ double regulate(const Phys &P, double tau, double q[NQ], double e,
+                                           double p0, const double u[4])
+{
+    const double g33 = CART ? 1.0 : tau * tau;
+    const double glo[4] = {1.0, -1.0, -1.0, -g33};
+    const double ghi[4] = {1.0, -1.0, -1.0, -1.0 / g33};
+    const double Pi = P.bulk ? q[BPI] : 0.0;
+    double BB = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+        for (int n = m; n < 4; ++n) {
+            const double B = Pi * ((m == n ? ghi[m] : 0.0) - u[m] * u[n]) + q[pi_index(m, n)];
+            BB += (m == n ? 1.0 : 2.0) * glo[m] * glo[n] * B * B;
+        }
+    }
+    const double nB = sqrt(fmax(BB, 0.0));
+    double rho = nB / (P.rho_max * sqrt(e * e + 3.0 * p0 * p0));
+    if (nB > 0.0) {
+        const double tr = q[PTT] - q[PXX] - q[PYY] - g33 * q[PEE];
+        const double lim = 1.0 / (P.xi0 * P.rho_max * nB);
+        rho = fmax(rho, fabs(tr) * lim);
+        const double ul[4] = {u[0], -u[1], -u[2], -g33 * u[3]};
+        double r3 = 0.0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            double w = 0.0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) w += q[pi_index(l, m)] * ul[m];
+            w = fabs(w);
+            if (l == 3) w *= sqrt(g33);
+            r3 = fmax(r3, w);
+        }
+        rho = fmax(rho, r3 * lim);
+    }
+    const double fac = rho > 0.0 ? tanh(rho) / rho : 1.0;
+#pragma unroll
+    for (int c = PTT; c <= PEE; ++c) q[c] *= fac;
+    if (P.regulate_bulk) q[BPI] *= fac;
+    return fac;
+}
+
+// ---------------------------------------------------------------- minmod --
+// generalized minmod of Sec. 3.1 on undivided differences; sgn(0) = 0.
+__device__ __forceinline__ double mm2(double x, double y)
+{
+    return (copysign(0.5, x) + copysign(0.5, y)) * fmin(fabs(x), fabs(y));
+}
+
+__device__ __forceinline__ double slope(double qm, double q0, double qp, double theta)
+{
+    return mm2(theta * (q0 - qm), mm2(0.5 * (qp - qm), theta * (qp - q0)));
+}
+
+// ------------------------------------------------- relaxation sources ----
+// Right-hand side J of the dissipative components (App. B):
+//   S_pi + G_pi = [2 (eta/tau_pi) sigma - pi/tau_pi - I_pi - G^{mu nu}] / u^tau + pi d_i v^i
+//   S_Pi        = [-(zeta/tau_Pi) theta - Pi/tau_Pi - I_Pi] / u^tau + Pi d_i v^i
+// with I_pi = I1 + (4/3) I2 - I3 + (tau_pipi/tau_pi) I4 - (6/5) Pi sigma,
+//      I_Pi = (2/3) Pi theta - (8/5)(1/3 - c_s^2) pi:sigma  (Sec. 2.2, 2.4),
+// G^{mu nu} = u^a Gamma^mu_{ab} pi^{b nu} + (mu <-> nu).
+// du[a][m] = partial_a u^m (a: tau, x, y, eta).
+template <bool CART>
+__device__ __forceinline__ void relaxation_sources(const Phys &P, double tau, const double q[NQ],
+                                                   double e, double p0, double cs2, double T,
+                                                   const double u[4], const double du[4][4],
+                                                   double divv, double J[NQ])
+{
+    const double g33 = CART ? 1.0 : tau * tau;
+    const double inv_tau = 1.0 / tau;
+    const double glo[4] = {1.0, -1.0, -1.0, -g33};
+    const double ghi[4] = {1.0, -1.0, -1.0, -1.0 / g33};
+    // covariant derivative C[a][m] = u^m_{;a}
+    double C[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) C[a][m] = du[a][m];
+    if (!CART) {
+        C[3][0] += tau * u[3];          // Gamma^tau_{eta eta} u^eta
+        C[0][3] += u[3] * inv_tau;      // Gamma^eta_{tau eta} u^eta
+        C[3][3] += u[0] * inv_tau;      // Gamma^eta_{eta tau} u^tau
+    }
+    const double th = C[0][0] + C[1][1] + C[2][2] + C[3][3];
+    double Du[4], Dl[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        Du[m] = u[0] * C[0][m] + u[1] * C[1][m] + u[2] * C[2][m] + u[3] * C[3][m];
+        Dl[m] = glo[m] * Du[m];
+    }
+    // sigma^{mn}, omega^{mn} from nabla^m u^n = g^{mm} C[m][n] - u^m D u^n
+    double sg[4][4], om[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const double a = ghi[m] * C[m][n] - u[m] * Du[n];
+            const double b = ghi[n] * C[n][m] - u[n] * Du[m];
+            const double Dmn = (m == n ? ghi[m] : 0.0) - u[m] * u[n];
+            sg[m][n] = 0.5 * (a + b) - th * (1.0 / 3.0) * Dmn;
+            om[m][n] = 0.5 * (a - b);
+        }
+    double pi[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) pi[m][n] = q[pi_index(m, n)];
+    const double Pi = P.bulk ? q[BPI] : 0.0;
+    // a^m = pi^{m l} D u_l ; b^{mn} = pi^{m l} g_ll omega^{n l} ; c^{mn} = pi^{m l} g_ll sigma^{n l}
+    double av[4], bm[4][4], cm[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        av[m] = pi[m][0] * Dl[0] + pi[m][1] * Dl[1] + pi[m][2] * Dl[2] + pi[m][3] * Dl[3];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            double sb = 0.0, sc = 0.0;
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                sb += pi[m][l] * glo[l] * om[n][l];
+                sc += pi[m][l] * glo[l] * sg[n][l];
+            }
+            bm[m][n] = sb;
+            cm[m][n] = sc;
+        }
+    }
+    const double pis = cm[0][0] * glo[0] + cm[1][1] * glo[1] + cm[2][2] * glo[2] + cm[3][3] * glo[3];
+    const double inv_ut = 1.0 / u[0];
+
+    if (P.shear) {
+        const double inv_tpi = T / (5.0 * P.eta_s);
+        const double eta_tpi = (e + p0) * 0.2;
+        // u^a Gamma^m_{ab}: h[m][b]
+        const double h03 = CART ? 0.0 : tau * u[3];
+        const double h30 = CART ? 0.0 : u[3] * inv_tau;
+        const double h33 = CART ? 0.0 : u[0] * inv_tau;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = m; n < 4; ++n) {
+                const double I1 = u[n] * av[m] + u[m] * av[n];
+                const double I3 = bm[m][n] + bm[n][m];
+                const double I4 = 0.5 * (cm[m][n] + cm[n][m])
+                                - ((m == n ? ghi[m] : 0.0) - u[m] * u[n]) * pis * (1.0 / 3.0);
+                const double Ipi = I1 + (4.0 / 3.0) * th * pi[m][n] - I3 + P.taupipi * I4
+                                 - 1.2 * Pi * sg[m][n];
+                double G = 0.0;
+                if (!CART) {
+                    // sum_b h[m][b] pi^{b n} + h[n][b] pi^{b m}
+                    const double hm = (m == 0 ? h03 * pi[3][n] : 0.0)
+                                    + (m == 3 ? h30 * pi[0][n] + h33 * pi[3][n] : 0.0);
+                    const double hn = (n == 0 ? h03 * pi[3][m] : 0.0)
+                                    + (n == 3 ? h30 * pi[0][m] + h33 * pi[3][m] : 0.0);
+                    G = hm + hn;
+                }
+                const double rhs = 2.0 * eta_tpi * sg[m][n] - pi[m][n] * inv_tpi - Ipi - G;
+                J[pi_index(m, n)] = rhs * inv_ut + pi[m][n] * divv;
+            }
+    }
+    if (P.bulk) {
+        const double d = 1.0 / 3.0 - cs2;
+        const double inv_tPi = 15.0 * d * T / P.zeta_coef;
+        const double zeta_tPi = 15.0 * d * d * (e + p0);
+        const double IPi = (2.0 / 3.0) * Pi * th - 1.6 * d * pis;
+        J[BPI] = (-zeta_tPi * th - Pi * inv_tPi - IPi) * inv_ut + Pi * divv;
+    }
+}
+
+}  // namespace ktd

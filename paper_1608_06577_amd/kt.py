@@ -1,0 +1,292 @@
+"""ctypes binding of ``libkt.so`` (the C ABI declared in ``include/kt.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of the library.  PyTorch supplies device memory (the workspace and the field
+tensors) and the stream.  Importing this module does not load the library;
+the first use does, and raises if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkt.so")
+
+KT_OK, KT_E_ARG, KT_E_ALLOC, KT_E_HIP, KT_E_STATE, KT_E_UNSUPPORTED = range(6)
+KT_FP64, KT_MIXED = 0, 1
+KT_MILNE, KT_CARTESIAN = 0, 1
+KT_BC_OUTFLOW, KT_BC_PERIODIC = 0, 1
+NQ = 15
+
+_dp = C.POINTER(C.c_double)
+
+
+class KtEos(C.Structure):
+    _fields_ = [("conformal", C.c_int32), ("a_sb", C.c_double), ("n", C.c_int32),
+                ("ln_e0", C.c_double), ("dln_e", C.c_double),
+                ("p", _dp), ("cs2", _dp), ("T", _dp)]
+
+
+class KtParams(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("neta", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("deta", C.c_double),
+                ("tau0", C.c_double), ("dtau", C.c_double), ("coords", C.c_int32),
+                ("bc", C.c_int32 * 3), ("theta", C.c_double), ("eta_over_s", C.c_double),
+                ("zeta_coef", C.c_double), ("taupipi", C.c_double), ("regulate", C.c_int32),
+                ("regulate_bulk", C.c_int32), ("xi0", C.c_double), ("rho_max", C.c_double),
+                ("e_floor", C.c_double), ("m2_delta", C.c_double), ("floor_resets_q", C.c_int32),
+                ("newton_tol", C.c_double), ("newton_max", C.c_int32), ("precision", C.c_int32)]
+
+
+class KtInitState(C.Structure):
+    _fields_ = [("q", C.c_void_p * 15), ("e", C.c_void_p), ("u", C.c_void_p * 4),
+                ("pi", C.c_void_p * 10), ("Pi", C.c_void_p), ("u_prev", C.c_void_p * 4)]
+
+
+class KtFields(C.Structure):
+    _fields_ = [("e", C.c_void_p), ("u", C.c_void_p * 4), ("q", C.c_void_p * 15),
+                ("u_prev", C.c_void_p * 4)]
+
+
+class KtObs(C.Structure):
+    _fields_ = [("tau", C.c_double), ("step", C.c_int64), ("energy", C.c_double),
+                ("momentum", C.c_double * 3), ("e_max", C.c_double), ("T_max", C.c_double),
+                ("v_max", C.c_double), ("cfl", C.c_double), ("norm_err", C.c_double),
+                ("pi_transverse", C.c_double), ("pi_trace", C.c_double), ("n_nan", C.c_int64),
+                ("newton_iters_cells", C.c_int64), ("n_recover_cells", C.c_int64),
+                ("newton_iters_faces", C.c_int64), ("n_recover_faces", C.c_int64),
+                ("n_floor", C.c_int64), ("n_clamp", C.c_int64), ("n_fallback", C.c_int64)]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if name == "momentum" else v
+        return d
+
+
+class KtProfile(C.Structure):
+    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4)]
+
+
+class KtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("kt status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+#: every function the C ABI exports (the names declared in include/kt.h)
+EXPORTS = ("kt_workspace_bytes", "kt_init", "kt_step", "kt_recover", "kt_observables",
+           "kt_profile_enable", "kt_profile_read", "kt_destroy", "kt_last_error",
+           "kt_status_string")
+
+
+def lib():
+    """Load libkt.so; raises if the library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libkt.so is missing: run __graft_entry__.build() first (%s)" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        L.kt_workspace_bytes.argtypes = [C.POINTER(KtParams), C.POINTER(KtEos)]
+        L.kt_workspace_bytes.restype = C.c_size_t
+        L.kt_init.argtypes = [C.POINTER(KtParams), C.POINTER(KtEos), C.POINTER(KtInitState),
+                              C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]
+        L.kt_step.argtypes = [C.c_void_p, C.c_int32]
+        L.kt_recover.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p * 9, C.c_void_p,
+                                 C.c_void_p * 4, C.c_void_p, C.c_void_p]
+        L.kt_observables.argtypes = [C.c_void_p, C.POINTER(KtObs), C.POINTER(KtFields)]
+        L.kt_destroy.argtypes = [C.c_void_p]
+        L.kt_destroy.restype = None
+        L.kt_last_error.argtypes = [C.c_void_p]
+        L.kt_last_error.restype = C.c_char_p
+        L.kt_status_string.argtypes = [C.c_int]
+        L.kt_status_string.restype = C.c_char_p
+        L.kt_profile_enable.argtypes = [C.c_void_p, C.c_int32]
+        L.kt_profile_read.argtypes = [C.c_void_p, C.POINTER(KtProfile)]
+        for f in ("kt_init", "kt_step", "kt_recover", "kt_observables", "kt_profile_enable",
+                  "kt_profile_read"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status, ctx=None):
+    if status != KT_OK:
+        msg = lib().kt_last_error(ctx).decode(errors="replace")
+        raise KtError(status, msg)
+
+
+def make_params(grid, config: dict, tau0: float) -> KtParams:
+    per = config.get("periodic", (False, False, False))
+    return KtParams(
+        grid.nx, grid.ny, grid.neta, grid.dx, grid.dy, grid.deta, tau0, config["dtau"],
+        KT_CARTESIAN if config.get("cartesian", False) else KT_MILNE,
+        (C.c_int32 * 3)(*[KT_BC_PERIODIC if b else KT_BC_OUTFLOW for b in per]),
+        config.get("theta", 1.0), config.get("eta_s", 0.0), config.get("zeta_coef", 0.0),
+        config.get("taupipi", 10.0 / 7.0), int(config.get("regulate", True)),
+        int(config.get("regulate_bulk", True)), config.get("xi0", 0.1),
+        config.get("rho_max", 1.0), config["e_floor"], config.get("m2_delta", 1e-3),
+        int(config.get("floor_resets_q", True)), config.get("newton_tol", 1e-12),
+        int(config.get("newton_max", 50)), KT_MIXED if config.get("mixed", False) else KT_FP64)
+
+
+class EosHost:
+    """Host-side C view of an EOS description (keeps the arrays alive)."""
+
+    def __init__(self, eos):
+        if eos.conformal:
+            self._arrs = ()
+            self.c = KtEos(1, eos.a_sb, 0, 0.0, 0.0, None, None, None)
+        else:
+            self._arrs = tuple(np.ascontiguousarray(a, dtype=np.float64) for a in (eos.p, eos.cs2, eos.T))
+            self.c = KtEos(0, eos.a_sb, len(self._arrs[0]), eos.ln_e0, eos.dln_e,
+                           *[a.ctypes.data_as(_dp) for a in self._arrs])
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def workspace_bytes(grid, config, eos, tau0=1.0) -> int:
+    p = make_params(grid, config, tau0)
+    e = EosHost(eos)
+    return int(lib().kt_workspace_bytes(C.byref(p), C.byref(e.c)))
+
+
+class Solver:
+    """One event advanced by the HIP library.
+
+    prims: ``inputs.Primitives`` (numpy, component-first) or a dict of device
+    tensors ``e, u, pi, Pi``; alternatively ``q`` = (15, neta, ny, nx) device
+    tensor of conserved components.
+    """
+
+    def __init__(self, grid, config: dict, eos, prims=None, q=None, tau0=None, u_prev=None,
+                 device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.grid = grid
+        self.config = dict(config)
+        if tau0 is None:
+            tau0 = prims.tau0 if prims is not None and hasattr(prims, "tau0") else 1.0
+        self.params = make_params(grid, config, tau0)
+        self.eos_host = EosHost(eos)
+        L = lib()
+        nbytes = int(L.kt_workspace_bytes(C.byref(self.params), C.byref(self.eos_host.c)))
+        if nbytes == 0:
+            _check(KT_E_ARG)
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            if self.ws.data_ptr() % 256:
+                raise RuntimeError("workspace is not 256-byte aligned")
+            st = KtInitState()
+            keep = []
+            shape = grid.shape
+
+            def dev(a):
+                t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(self.device) \
+                    if isinstance(a, np.ndarray) else a.contiguous()
+                assert t.dtype == torch.float64 and tuple(t.shape[-3:]) == shape
+                keep.append(t)
+                return t
+
+            if q is not None:
+                qd = dev(q)
+                for c in range(NQ):
+                    st.q[c] = qd[c].data_ptr()
+            else:
+                get = (lambda k: prims[k]) if isinstance(prims, dict) else (lambda k: getattr(prims, k))
+                e, u, pi, Pi = dev(get("e")), dev(get("u")), dev(get("pi")), dev(get("Pi"))
+                st.e = e.data_ptr()
+                st.Pi = Pi.data_ptr()
+                for m in range(4):
+                    st.u[m] = u[m].data_ptr()
+                for c in range(10):
+                    st.pi[c] = pi[c].data_ptr()
+            if u_prev is not None:
+                upd = dev(u_prev)
+                for m in range(4):
+                    st.u_prev[m] = upd[m].data_ptr()
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            ctx = C.c_void_p()
+            _check(L.kt_init(C.byref(self.params), C.byref(self.eos_host.c), C.byref(st),
+                             C.c_void_p(self.ws.data_ptr()), nbytes, C.c_void_p(stream),
+                             C.byref(ctx)))
+            self.ctx = ctx
+            del keep
+
+    # ------------------------------------------------------------------
+    def step(self, n: int = 1):
+        _check(lib().kt_step(self.ctx, int(n)), self.ctx)
+        return self
+
+    def observables(self) -> dict:
+        o = KtObs()
+        _check(lib().kt_observables(self.ctx, C.byref(o), None), self.ctx)
+        return o.as_dict()
+
+    def fields(self, which=("e", "u", "q", "u_prev")) -> dict:
+        torch = self.torch
+        shape = self.grid.shape
+        out = {}
+        f = KtFields()
+        with torch.cuda.device(self.device):
+            if "e" in which:
+                out["e"] = torch.empty(shape, dtype=torch.float64, device=self.device)
+                f.e = out["e"].data_ptr()
+            if "u" in which:
+                out["u"] = torch.empty((4,) + shape, dtype=torch.float64, device=self.device)
+                for m in range(4):
+                    f.u[m] = out["u"][m].data_ptr()
+            if "u_prev" in which:
+                out["u_prev"] = torch.empty((4,) + shape, dtype=torch.float64, device=self.device)
+                for m in range(4):
+                    f.u_prev[m] = out["u_prev"][m].data_ptr()
+            if "q" in which:
+                out["q"] = torch.empty((NQ,) + shape, dtype=torch.float64, device=self.device)
+                for c in range(NQ):
+                    f.q[c] = out["q"][c].data_ptr()
+            _check(lib().kt_observables(self.ctx, None, C.byref(f)), self.ctx)
+        return out
+
+    def recover(self, ins, tau: float, with_iters=True):
+        """ins: 9 device tensors (T^{tau mu}, pi^{tau mu}, Pi) of equal length n."""
+        torch = self.torch
+        n = ins[0].numel()
+        arr = (C.c_void_p * 9)(*[t.data_ptr() if t is not None else None for t in ins])
+        e = torch.empty(n, dtype=torch.float64, device=self.device)
+        u = torch.empty((4, n), dtype=torch.float64, device=self.device)
+        it = torch.empty(n, dtype=torch.int32, device=self.device) if with_iters else None
+        fl = torch.empty(n, dtype=torch.int32, device=self.device) if with_iters else None
+        uarr = (C.c_void_p * 4)(*[u[m].data_ptr() for m in range(4)])
+        _check(lib().kt_recover(self.ctx, n, float(tau), arr, C.c_void_p(e.data_ptr()), uarr,
+                                _ptr(it), _ptr(fl)), self.ctx)
+        return e, u, it, fl
+
+    def profile(self, on: bool):
+        _check(lib().kt_profile_enable(self.ctx, int(on)), self.ctx)
+
+    def profile_read(self) -> dict:
+        """Summed kernel times (ms) and launch counts per class since the last read."""
+        p = KtProfile()
+        _check(lib().kt_profile_read(self.ctx, C.byref(p)), self.ctx)
+        return dict(stage_ms=p.ms[0], stage_launches=p.launches[0],
+                    recover_ms=p.ms[1], recover_launches=p.launches[1])
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().kt_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,219 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Error measures (the same everywhere):
+* e: max over cells of |e_gpu - e_ora| / max(e_ora, 1e-6 max e_ora);
+* u: max over cells and components of |u_gpu - u_ora| / u^tau_ora, the eta
+  component multiplied by tau (tetrad component);
+* q: per component, max |q_gpu - q_ora| / max |q_ora| of that component.
+The FP64 bar after 100 steps is 1e-9 in e and u.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_06577_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def kt():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1608_06577_amd import kt as K
+    K.lib()
+    return K
+
+
+def e_err(e, er):
+    return float(np.max(np.abs(e - er) / np.maximum(er, 1e-6 * er.max())))
+
+
+def u_err(u, ur, tau):
+    s = np.array([1.0, 1.0, 1.0, tau]).reshape((4,) + (1,) * (u.ndim - 1))
+    return float(np.max(np.abs(u - ur) * s / ur[0:1]))
+
+
+def q_err(q, qr):
+    out = []
+    for c in range(15):
+        m = np.abs(qr[c]).max()
+        out.append(0.0 if m == 0 else float(np.abs(q[c] - qr[c]).max() / m))
+    return np.array(out)
+
+
+def run_pair(kt, w, nsteps, report=None):
+    phys = oracle.Physics.from_config(w.grid, w.config)
+    sim = oracle.Simulation.from_primitives(phys, w.eos, w.prims)
+    gpu = kt.Solver(w.grid, w.config, w.eos, w.prims)
+    if nsteps:
+        sim.step(nsteps)
+        gpu.step(nsteps)
+    f = {k: v.cpu().numpy() for k, v in gpu.fields().items()}
+    r = sim.fields()
+    errs = dict(e=e_err(f["e"], r["e"]), u=u_err(f["u"], r["u"], sim.tau),
+                q=q_err(f["q"], r["q"]).max(), up=u_err(f["u_prev"], r["up"], sim.tau))
+    if report:
+        print(report, nsteps, "steps:", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    return errs, gpu, sim, f, r
+
+
+# ---------------------------------------------------------------- recovery --
+
+def test_recover_matches_oracle(kt):
+    import torch
+    from tests.test_oracle_algebra import pack_pi, random_state
+    tau = 0.9
+    eos = I.eos_c1_table()
+    w = I.workload_hotspot(nx=4, ny=4, neta=4)
+    cfg = dict(w.config)
+    phys = oracle.Physics.from_config(w.grid, cfg)
+    e, u, pi, Pi = random_state(tau, 3000, u_scale=1.5)
+    q = oracle.tmunu(phys, eos, tau, e, u, pack_pi(pi), Pi)
+    # guard cases: below floor, NaN, |M| > E, E + P + Pi < 0, near the light cone
+    extra = np.zeros((5, 15))
+    extra[0, 0] = 0.3 * cfg["e_floor"]
+    extra[1, 0] = np.nan
+    extra[2, 0], extra[2, 1] = 2.0, 3.0
+    extra[3, 0], extra[3, 14] = 1.0, -5.0
+    extra[4, 0], extra[4, 2] = 10.0, -9.9999
+    q = np.concatenate([q, extra])
+    eo, uo, ito, flo = oracle.recover(phys, eos, tau, q)
+    gpu = kt.Solver(w.grid, cfg, eos, w.prims)
+    ins = [torch.tensor(q[:, k], device="cuda") for k in (0, 1, 2, 3, 4, 5, 6, 7, 14)]
+    eg, ug, itg, flg = gpu.recover(ins, tau)
+    eg, ug = eg.cpu().numpy(), ug.cpu().numpy().T
+    assert np.array_equal(flg.cpu().numpy(), flo)
+    assert np.max(np.abs(eg - eo) / eo) < 1e-13
+    assert np.max(np.abs(ug - uo) / uo[:, :1]) < 1e-12
+    # same start and stopping rule: iteration counts agree except where |f| sits
+    # at the tolerance within rounding
+    d = np.abs(itg.cpu().numpy() - ito)
+    assert d.max() <= 1 and np.mean(d == 0) > 0.99
+
+
+def test_init_matches_oracle(kt):
+    w = I.workload_hotspot(nx=20, ny=17, neta=6, dx=0.8, deta=0.8)
+    errs, gpu, sim, f, r = run_pair(kt, w, 0)
+    assert errs["q"] < 1e-14 and errs["e"] < 1e-14 and errs["u"] < 1e-14
+    w = I.workload_gubser_viscous(n=12, neta=3)
+    errs, *_ = run_pair(kt, w, 0)
+    assert errs["q"] < 1e-13 and errs["e"] < 1e-13 and errs["u"] < 1e-13
+
+
+# --------------------------------------------------------------- one step ---
+
+@pytest.mark.parametrize("case", ["milne_viscous_bulk", "milne_ideal", "cartesian_viscous",
+                                  "periodic_all"])
+def test_one_and_five_steps_match_oracle(kt, case):
+    """Ragged grid (several 64x4 tiles plus tails), smooth random state."""
+    g = I.Grid(71, 37, 9, 0.15, 0.2, 0.12)
+    cart = case == "cartesian_viscous"
+    if case == "milne_ideal":
+        cfg = I.default_config(eta_s=0.0, periodic=(False, False, True))
+        eos = I.eos_conformal()
+    elif case == "periodic_all":
+        cfg = I.default_config(eta_s=0.2, zeta_coef=0.1, periodic=(True, True, True), theta=1.8)
+        eos = I.eos_c1_table()
+    else:
+        cfg = I.default_config(eta_s=0.2, zeta_coef=0.1, cartesian=cart,
+                               periodic=(False, False, True), theta=1.4)
+        eos = I.eos_c1_table()
+    prims = I.random_smooth_fields(g, 0.7, seed=9, cartesian=cart, e_mean=6.0,
+                                   pi_rel=0.0 if case == "milne_ideal" else 0.05,
+                                   Pi_rel=0.0 if case == "milne_ideal" else 0.02)
+    w = I.Workload(case, g, 0.7, 5, cfg, eos, prims)
+    for n in (1, 5):
+        errs, *_ = run_pair(kt, w, n, report=case)
+        assert errs["q"] < 1e-12 and errs["e"] < 1e-12 and errs["u"] < 1e-12, errs
+        assert errs["up"] < 1e-12
+
+
+def test_zero_steps_and_tiny_grids(kt):
+    for (nx, ny, ne) in ((1, 1, 1), (1, 5, 3), (7, 1, 1), (3, 2, 1)):
+        g = I.Grid(nx, ny, ne, 0.2, 0.2, 0.2)
+        cfg = I.default_config(eta_s=0.2, zeta_coef=0.1)
+        prims = I.random_smooth_fields(g, 1.0, seed=nx * 7 + ny, e_mean=4.0)
+        w = I.Workload("tiny", g, 1.0, 3, cfg, I.eos_c1_table(), prims)
+        for n in (0, 3):
+            errs, *_ = run_pair(kt, w, n)
+            assert errs["q"] < 1e-12 and errs["e"] < 1e-12 and errs["u"] < 1e-12, (nx, ny, ne, errs)
+
+
+# ---------------------------------------------------------- full workloads --
+
+def test_gubser_viscous_32cube_100_steps(kt):
+    """Conformal viscous Gubser flow on the 32^3 grid (dx = 0.1 fm, periodic in
+    eta, theta = 1.8, eta/s = 0.2): 100 Heun steps."""
+    w = I.workload_gubser_viscous(n=32, n_steps=100)
+    errs, gpu, sim, f, r = run_pair(kt, w, 100, report="gubser32")
+    assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9, errs
+    obs = gpu.observables()
+    assert obs["n_nan"] == 0 and obs["step"] == 100
+    assert abs(obs["tau"] - sim.tau) < 1e-12
+
+
+def test_hotspot_small_grid_100_steps(kt):
+    """The non-conformal viscous hot-spot event (shear + bulk, tabulated EOS,
+    regulator, floor and clamp active) on a coarser 56x52x24 grid."""
+    w = I.workload_hotspot(nx=56, ny=52, neta=24, dx=0.4, deta=0.5, n_hot=60, seed=3)
+    errs, gpu, sim, f, r = run_pair(kt, w, 100, report="hotspot56")
+    obs = gpu.observables()
+    assert obs["n_floor"] > 0 and obs["n_nan"] == 0
+    assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9, errs
+
+
+def test_hotspot_128_against_oracle_samples(kt):
+    """The full 128^3 event: GPU fields after 50/100/200 steps against oracle
+    samples written by tests/golden/make_hotspot_golden.py."""
+    path = os.path.join(ROOT, "tests", "golden", "hotspot_128_fp64.npz")
+    if not os.path.exists(path):
+        pytest.skip("oracle samples not generated")
+    gold = np.load(path)
+    w = I.workload_hotspot()
+    import hashlib
+    sha = hashlib.sha256(np.ascontiguousarray(w.prims.e).tobytes()).digest()
+    assert np.array_equal(np.frombuffer(sha, np.uint8), gold["input_sha"])
+    gpu = kt.Solver(w.grid, w.config, w.eos, w.prims)
+    idx = gold["idx"]
+    done = 0
+    for s in (50, 100, 200):
+        gpu.step(s - done)
+        done = s
+        f = gpu.fields(("e", "u", "q"))
+        e = f["e"].reshape(-1)[idx].cpu().numpy()
+        u = f["u"].reshape(4, -1)[:, idx].cpu().numpy()
+        er = gold["e_%d" % s]
+        ur = gold["u_%d" % s].T
+        tau = float(gold["tau_%d" % s])
+        ee = float(np.max(np.abs(e - er) / np.maximum(er, 1e-6 * gold["emax_%d" % s])))
+        eu = u_err(u, ur, tau)
+        print("hotspot128 step %d: e %.2e u %.2e" % (s, ee, eu), flush=True)
+        if s <= 100:
+            assert ee <= 1e-9 and eu <= 1e-9, (s, ee, eu)
+        else:
+            assert ee <= 1e-6 and eu <= 1e-6, (s, ee, eu)
+
+
+# --------------------------------------------------------------- properties --
+
+def test_periodic_cartesian_conservation_on_gpu(kt):
+    """Sum T^{t nu} over a periodic Cartesian box is conserved to rounding
+    (flux form of Sec. 3.1); holds at any size."""
+    import torch
+    g = I.Grid(96, 80, 24, 0.1, 0.12, 0.15)
+    cfg = I.default_config(dtau=0.01, cartesian=True, periodic=(True, True, True),
+                           eta_s=0.2, zeta_coef=0.1, theta=1.5)
+    prims = I.random_smooth_fields(g, 1.0, seed=21, cartesian=True, e_mean=5.0)
+    gpu = kt.Solver(g, cfg, I.eos_c1_table(), prims)
+    q0 = gpu.fields(("q",))["q"][:4].sum(dim=(1, 2, 3))
+    gpu.step(50)
+    q1 = gpu.fields(("q",))["q"]
+    scale = q1[:4].abs().sum().item()
+    d = (q1[:4].sum(dim=(1, 2, 3)) - q0).abs().max().item()
+    assert d <= 1e-13 * scale
+    torch.cuda.synchronize()
