@@ -8,6 +8,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace ktd {
@@ -23,18 +24,21 @@ enum : int {
 // recovery flags
 enum : int { F_FLOOR = 1, F_CLAMP = 2, F_FALLBACK = 4 };
 
-// counters accumulated on the device
+// counters, one slot row per wavefront
 enum : int {
     C_ITERS_CELLS = 0, C_REC_CELLS, C_ITERS_FACES, C_REC_FACES, C_FLOOR, C_CLAMP, C_FALLBACK,
     C_COUNT
 };
+
+// EOS node layout: p/e, T/e^{1/4}, c_s^2, 1/e_i
+constexpr int EOS_W = 4;
 
 struct Eos {
     int conformal;
     double inv_a;          // 1 / a_sb
     int n;
     double ln_e0, inv_dln;
-    const double *tab;     // per node: p/e, T/e^{1/4}, c_s^2
+    const double *tab;     // n nodes of EOS_W doubles
 };
 
 struct Phys {
@@ -48,11 +52,11 @@ struct Phys {
     int shear, bulk;
     int regulate, regulate_bulk, floor_reset;
     double xi0, rho_max;
-    double e_floor, m2_delta, newton_tol;
+    double e_floor, p_floor, m2_delta, newton_tol;
     int newton_max;
 };
 
-__device__ __forceinline__ int pi_index(int m, int n)
+__host__ __device__ __forceinline__ int pi_index(int m, int n)
 {
     // symmetric 4x4 -> position in q
     const int a = m < n ? m : n, b = m < n ? n : m;
@@ -60,9 +64,65 @@ __device__ __forceinline__ int pi_index(int m, int n)
 }
 
 // ------------------------------------------------------------------ EOS ---
-// Table: p/e, T/e^{1/4}, c_s^2 linear in ln e between bracketing nodes;
-// end-node values outside the table.
-__device__ __forceinline__ void eos_eval(const Eos &E, double e, double &p, double &cs2, double &T)
+// Table nodes e_i = exp(ln_e0 + i dln): p/e, T/e^{1/4}, c_s^2 linear in
+// ln e between the bracketing nodes, end-node values outside the table.
+// The bracket is found from a single-precision log2; the weight
+// t = ln(e/e_i)/dln comes from ln(1+z), z = e/e_i - 1, |z| < 2 dln, by its
+// series to z^8 (truncation below 1e-18 for dln <= 0.01), so no
+// double-precision logarithm is evaluated.
+__host__ __device__ __forceinline__ void eos_locate(const Eos &E, double e, int &i, double &t)
+{
+    const float lf = log2f((float)e);
+    const double x = ((double)lf * 0.6931471805599453 - E.ln_e0) * E.inv_dln;
+    if (!(x > -0.5)) {                 // below the table (or not a number)
+        i = 0;
+        t = 0.0;
+        return;
+    }
+    if (x > (double)(E.n - 1) + 0.5) {
+        i = E.n - 2;
+        t = 1.0;
+        return;
+    }
+    i = (int)floor(x);
+    i = i < 0 ? 0 : (i > E.n - 2 ? E.n - 2 : i);
+    const double z = fma(e, E.tab[EOS_W * i + 3], -1.0);
+    // ln(1+z) = z - z^2/2 + z^3/3 - ... - z^8/8
+    double l = -1.0 / 8.0;
+    l = fma(l, z, 1.0 / 7.0);
+    l = fma(l, z, -1.0 / 6.0);
+    l = fma(l, z, 1.0 / 5.0);
+    l = fma(l, z, -1.0 / 4.0);
+    l = fma(l, z, 1.0 / 3.0);
+    l = fma(l, z, -1.0 / 2.0);
+    l = fma(l, z, 1.0);
+    t = l * z * E.inv_dln;
+    if (t < 0.0) {
+        if (i > 0) { i -= 1; t += 1.0; } else t = 0.0;
+    } else if (t >= 1.0) {
+        if (i < E.n - 2) { i += 1; t -= 1.0; } else t = 1.0;
+    }
+}
+
+// p and c_s^2
+__host__ __device__ __forceinline__ void eos_pc(const Eos &E, double e, double &p, double &cs2)
+{
+    if (E.conformal) {
+        p = e * (1.0 / 3.0);
+        cs2 = 1.0 / 3.0;
+        return;
+    }
+    int i;
+    double t;
+    eos_locate(E, e, i, t);
+    const double *a = E.tab + EOS_W * i;
+    p = (a[0] + t * (a[EOS_W] - a[0])) * e;
+    cs2 = a[2] + t * (a[EOS_W + 2] - a[2]);
+}
+
+// p, c_s^2 and T
+__host__ __device__ __forceinline__ void eos_full(const Eos &E, double e, double &p, double &cs2,
+                                                  double &T)
 {
     if (E.conformal) {
         p = e * (1.0 / 3.0);
@@ -70,58 +130,48 @@ __device__ __forceinline__ void eos_eval(const Eos &E, double e, double &p, doub
         T = e > 0.0 ? sqrt(sqrt(e * E.inv_a)) : 0.0;
         return;
     }
-    const double x = (log(e) - E.ln_e0) * E.inv_dln;
     int i;
     double t;
-    if (!(x >= 0.0)) {
-        i = 0;
-        t = 0.0;
-    } else if (x >= (double)(E.n - 1)) {
-        i = E.n - 2;
-        t = 1.0;
-    } else {
-        i = (int)x;
-        if (i > E.n - 2) i = E.n - 2;
-        t = x - (double)i;
-    }
-    const double *a = E.tab + 3 * i;
-    const double r = a[0] + t * (a[3] - a[0]);
-    const double s = a[1] + t * (a[4] - a[1]);
-    cs2 = a[2] + t * (a[5] - a[2]);
-    p = r * e;
-    T = s * sqrt(sqrt(e));
+    eos_locate(E, e, i, t);
+    const double *a = E.tab + EOS_W * i;
+    p = (a[0] + t * (a[EOS_W] - a[0])) * e;
+    cs2 = a[2] + t * (a[EOS_W + 2] - a[2]);
+    T = (a[1] + t * (a[EOS_W + 1] - a[1])) * sqrt(sqrt(e));
 }
 
-__device__ __forceinline__ double eos_p(const Eos &E, double e)
+__host__ __device__ __forceinline__ double eos_p(const Eos &E, double e)
 {
-    double p, c, T;
-    eos_eval(E, e, p, c, T);
+    double p, c;
+    eos_pc(E, e, p, c);
     return p;
 }
 
 // ------------------------------------------------------------- recovery ---
-// Inversion of Sec. 2.4 (e = E - M^2/(E + P(e)), u^tau, u^i) solved by
+// Inversion of Sec. 2.4 (e = E - M^2/(E + P(e)), u^tau, u^i) by
 // Newton-Raphson (Sec. 3.2).  Guards: E <= e_floor, E + p(e_floor) + Pi <= 0
 // or non-finite M^2 give the floor state; M^2 is clamped to
 // (1 - m2_delta) W min(E - e_floor, W); conformal EOS without bulk uses the
-// closed form sqrt(4E^2 - 3M^2) - E; otherwise Newton from the conformal
-// value, iterates clamped to [e_floor, E], one extra step after
-// |f| <= tol E, bisection if not converged.
+// closed form sqrt(4E^2 - 3M^2) - E; otherwise Newton from e_start (<= 0:
+// the conformal value), iterates clamped to [e_floor, E], one extra step
+// after |f| <= tol E, bisection if not converged.  Returns the flags;
+// p_out is p(e) of the equilibrium EOS at the result.
 template <bool CART>
 __device__ __forceinline__ int recover(const Phys &P, const Eos &E, double tau, double Ttt,
                                        double Ttx, double Tty, double Tte, double ptt,
                                        double ptx, double pty, double pte, double Pi,
-                                       double &e, double u[4], int &iters)
+                                       double e_start, double &e, double &p_out, double u[4],
+                                       int &iters)
 {
     const double ef = P.e_floor;
     const double g33 = CART ? 1.0 : tau * tau;
     const double EE = Ttt - ptt;
     double Mx = Ttx - ptx, My = Tty - pty, Me = Tte - pte;
     double M2 = Mx * Mx + My * My + g33 * (Me * Me);
-    const double W = EE + eos_p(E, ef) + Pi;
+    const double W = EE + P.p_floor + Pi;
     iters = 0;
     if (!(EE > ef) || !(W > 0.0) || !(M2 == M2) || !(M2 < INFINITY)) {
         e = ef;
+        p_out = P.p_floor;
         u[0] = 1.0;
         u[1] = u[2] = u[3] = 0.0;
         return F_FLOOR;
@@ -136,17 +186,18 @@ __device__ __forceinline__ int recover(const Phys &P, const Eos &E, double tau, 
         M2 = M2max;
         flags |= F_CLAMP;
     }
-    const double econf = sqrt(4.0 * EE * EE - 3.0 * M2) - EE;
-    double x;
+    double x, p;
     if (E.conformal && !P.bulk) {
-        x = fmax(econf, ef);
+        x = fmax(sqrt(4.0 * EE * EE - 3.0 * M2) - EE, ef);
+        p = x * (1.0 / 3.0);
     } else {
-        x = fmin(fmax(econf, ef), EE);
+        x = e_start > 0.0 ? e_start : sqrt(4.0 * EE * EE - 3.0 * M2) - EE;
+        x = fmin(fmax(x, ef), EE);
         bool done = false;
         int n = 0;
+        double cs2;
         while (n < P.newton_max) {
-            double p, cs2, T;
-            eos_eval(E, x, p, cs2, T);
+            eos_pc(E, x, p, cs2);
             const double A = EE + p + Pi;
             const double f = x - EE + M2 / A;
             const double df = 1.0 - M2 * cs2 / (A * A);
@@ -170,8 +221,9 @@ __device__ __forceinline__ int recover(const Phys &P, const Eos &E, double tau, 
             }
             flags |= F_FALLBACK;
         }
+        p = eos_p(E, x);
     }
-    const double Pc = eos_p(E, x) + Pi;
+    const double Pc = p + Pi;
     const double ut = sqrt((EE + Pc) / (x + Pc));
     const double inv = 1.0 / ((x + Pc) * ut);
     u[0] = ut;
@@ -179,6 +231,7 @@ __device__ __forceinline__ int recover(const Phys &P, const Eos &E, double tau, 
     u[2] = My * inv;
     u[3] = Me * inv;
     e = x;
+    p_out = p;
     return flags;
 }
 
@@ -251,11 +304,11 @@ __device__ __forceinline__ double slope(double qm, double q0, double qp, double 
 // with I_pi = I1 + (4/3) I2 - I3 + (tau_pipi/tau_pi) I4 - (6/5) Pi sigma,
 //      I_Pi = (2/3) Pi theta - (8/5)(1/3 - c_s^2) pi:sigma  (Sec. 2.2, 2.4),
 // G^{mu nu} = u^a Gamma^mu_{ab} pi^{b nu} + (mu <-> nu).
-// du[a][m] = partial_a u^m (a: tau, x, y, eta).
+// C[a][m] = partial_a u^m on entry (a: tau, x, y, eta); q holds pi and Pi.
 template <bool CART>
 __device__ __forceinline__ void relaxation_sources(const Phys &P, double tau, const double q[NQ],
                                                    double e, double p0, double cs2, double T,
-                                                   const double u[4], const double du[4][4],
+                                                   const double u[4], double C[4][4],
                                                    double divv, double J[NQ])
 {
     const double g33 = CART ? 1.0 : tau * tau;
@@ -263,11 +316,6 @@ __device__ __forceinline__ void relaxation_sources(const Phys &P, double tau, co
     const double glo[4] = {1.0, -1.0, -1.0, -g33};
     const double ghi[4] = {1.0, -1.0, -1.0, -1.0 / g33};
     // covariant derivative C[a][m] = u^m_{;a}
-    double C[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int m = 0; m < 4; ++m) C[a][m] = du[a][m];
     if (!CART) {
         C[3][0] += tau * u[3];          // Gamma^tau_{eta eta} u^eta
         C[0][3] += u[3] * inv_tau;      // Gamma^eta_{tau eta} u^eta
@@ -280,72 +328,81 @@ __device__ __forceinline__ void relaxation_sources(const Phys &P, double tau, co
         Du[m] = u[0] * C[0][m] + u[1] * C[1][m] + u[2] * C[2][m] + u[3] * C[3][m];
         Dl[m] = glo[m] * Du[m];
     }
-    // sigma^{mn}, omega^{mn} from nabla^m u^n = g^{mm} C[m][n] - u^m D u^n
-    double sg[4][4], om[4][4];
+    // sigma (10) and omega (6) from nabla^m u^n = g^{mm} C[m][n] - u^m D u^n
+    double sg[10], om[6];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
+        for (int n = m; n < 4; ++n) {
             const double a = ghi[m] * C[m][n] - u[m] * Du[n];
             const double b = ghi[n] * C[n][m] - u[n] * Du[m];
             const double Dmn = (m == n ? ghi[m] : 0.0) - u[m] * u[n];
-            sg[m][n] = 0.5 * (a + b) - th * (1.0 / 3.0) * Dmn;
-            om[m][n] = 0.5 * (a - b);
+            sg[pi_index(m, n) - PTT] = 0.5 * (a + b) - th * (1.0 / 3.0) * Dmn;
         }
-    double pi[4][4];
+    // antisymmetric part, stored for m < n in the order (01, 02, 03, 12, 13, 23)
+    {
+        int k = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = m + 1; n < 4; ++n) {
+                const double a = ghi[m] * C[m][n] - u[m] * Du[n];
+                const double b = ghi[n] * C[n][m] - u[n] * Du[m];
+                om[k++] = 0.5 * (a - b);
+            }
+    }
+    auto SG = [&](int m, int n) -> double { return sg[pi_index(m, n) - PTT]; };
+    auto OM = [&](int m, int n) -> double {
+        if (m == n) return 0.0;
+        const int a = m < n ? m : n, b = m < n ? n : m;
+        const int k = a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
+        return m < n ? om[k] : -om[k];
+    };
+    auto PI = [&](int m, int n) -> double { return q[pi_index(m, n)]; };
+    const double Pi = P.bulk ? q[BPI] : 0.0;
+    double pis = 0.0;   // pi^{mu nu} sigma_{mu nu}
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) pi[m][n] = q[pi_index(m, n)];
-    const double Pi = P.bulk ? q[BPI] : 0.0;
-    // a^m = pi^{m l} D u_l ; b^{mn} = pi^{m l} g_ll omega^{n l} ; c^{mn} = pi^{m l} g_ll sigma^{n l}
-    double av[4], bm[4][4], cm[4][4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        av[m] = pi[m][0] * Dl[0] + pi[m][1] * Dl[1] + pi[m][2] * Dl[2] + pi[m][3] * Dl[3];
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            double sb = 0.0, sc = 0.0;
-#pragma unroll
-            for (int l = 0; l < 4; ++l) {
-                sb += pi[m][l] * glo[l] * om[n][l];
-                sc += pi[m][l] * glo[l] * sg[n][l];
-            }
-            bm[m][n] = sb;
-            cm[m][n] = sc;
-        }
-    }
-    const double pis = cm[0][0] * glo[0] + cm[1][1] * glo[1] + cm[2][2] * glo[2] + cm[3][3] * glo[3];
+        for (int n = m; n < 4; ++n)
+            pis += (m == n ? 1.0 : 2.0) * glo[m] * glo[n] * PI(m, n) * SG(m, n);
     const double inv_ut = 1.0 / u[0];
 
     if (P.shear) {
+        double av[4];   // a^m = pi^{m l} D u_l
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            av[m] = PI(m, 0) * Dl[0] + PI(m, 1) * Dl[1] + PI(m, 2) * Dl[2] + PI(m, 3) * Dl[3];
         const double inv_tpi = T / (5.0 * P.eta_s);
         const double eta_tpi = (e + p0) * 0.2;
-        // u^a Gamma^m_{ab}: h[m][b]
-        const double h03 = CART ? 0.0 : tau * u[3];
-        const double h30 = CART ? 0.0 : u[3] * inv_tau;
-        const double h33 = CART ? 0.0 : u[0] * inv_tau;
+        const double h03 = CART ? 0.0 : tau * u[3];     // u^a Gamma^tau_{a eta}
+        const double h30 = CART ? 0.0 : u[3] * inv_tau; // u^a Gamma^eta_{a tau}
+        const double h33 = CART ? 0.0 : u[0] * inv_tau; // u^a Gamma^eta_{a eta}
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int n = m; n < 4; ++n) {
+                double I3 = 0.0, c4 = 0.0;
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    // pi^{m l} g_ll omega^{n l} + (m <-> n);  pi^{m l} g_ll sigma^{n l} + (m <-> n)
+                    I3 += glo[l] * (PI(m, l) * OM(n, l) + PI(n, l) * OM(m, l));
+                    c4 += glo[l] * (PI(m, l) * SG(n, l) + PI(n, l) * SG(m, l));
+                }
                 const double I1 = u[n] * av[m] + u[m] * av[n];
-                const double I3 = bm[m][n] + bm[n][m];
-                const double I4 = 0.5 * (cm[m][n] + cm[n][m])
-                                - ((m == n ? ghi[m] : 0.0) - u[m] * u[n]) * pis * (1.0 / 3.0);
-                const double Ipi = I1 + (4.0 / 3.0) * th * pi[m][n] - I3 + P.taupipi * I4
-                                 - 1.2 * Pi * sg[m][n];
+                const double I4 = 0.5 * c4 - ((m == n ? ghi[m] : 0.0) - u[m] * u[n]) * pis * (1.0 / 3.0);
+                const double s = SG(m, n), pmn = PI(m, n);
+                const double Ipi = I1 + (4.0 / 3.0) * th * pmn - I3 + P.taupipi * I4 - 1.2 * Pi * s;
                 double G = 0.0;
                 if (!CART) {
-                    // sum_b h[m][b] pi^{b n} + h[n][b] pi^{b m}
-                    const double hm = (m == 0 ? h03 * pi[3][n] : 0.0)
-                                    + (m == 3 ? h30 * pi[0][n] + h33 * pi[3][n] : 0.0);
-                    const double hn = (n == 0 ? h03 * pi[3][m] : 0.0)
-                                    + (n == 3 ? h30 * pi[0][m] + h33 * pi[3][m] : 0.0);
+                    const double hm = (m == 0 ? h03 * PI(3, n) : 0.0)
+                                    + (m == 3 ? h30 * PI(0, n) + h33 * PI(3, n) : 0.0);
+                    const double hn = (n == 0 ? h03 * PI(3, m) : 0.0)
+                                    + (n == 3 ? h30 * PI(0, m) + h33 * PI(3, m) : 0.0);
                     G = hm + hn;
                 }
-                const double rhs = 2.0 * eta_tpi * sg[m][n] - pi[m][n] * inv_tpi - Ipi - G;
-                J[pi_index(m, n)] = rhs * inv_ut + pi[m][n] * divv;
+                const double rhs = 2.0 * eta_tpi * s - pmn * inv_tpi - Ipi - G;
+                J[pi_index(m, n)] = rhs * inv_ut + pmn * divv;
             }
     }
     if (P.bulk) {

@@ -33,16 +33,57 @@ using namespace ktd;
 
 namespace {
 
-constexpr int BX = 64, BY = 4;   // one wavefront per row of x
+constexpr int BX = 64;     // one wavefront along x; 63 cells are output per wave
+constexpr int XOUT = BX - 1;
+constexpr int BY = 4;      // rows of y per block (one wavefront each)
+constexpr int KC = 4;      // consecutive eta planes per thread (eta faces carried)
 
 // ------------------------------------------------------------------ grid --
 
 struct Fields {       // base pointers; component c of an array is base + c * stride
     const double *q;
     const double *e;
+    const double *p;
     const double *u;
     const double *up;
+    const double *vf;     // face speeds: v^-, v^+ per face, x, y and eta face arrays (see FaceGeo)
 };
+
+// Face arrays: the x faces of row (j,k) are i = 0..nx (face i lies between
+// cells i-1 and i), likewise for y and eta; each face holds v^- and v^+ of
+// its axis.  Offsets into Fields::vf, in doubles.
+struct FaceGeo {
+    long long nfx, nfy, nfe;          // faces per axis
+    long long ox, oy, oe;             // offsets of the three arrays (v^- block then v^+ block)
+};
+
+// Cell and face indices are 32-bit; a load adds the byte offset idx*8 to a
+// per-component base pointer that is uniform across the wavefront (kept in
+// scalar registers), so no 64-bit address is formed per lane.
+typedef uint32_t idx_t;
+
+__device__ __forceinline__ double ld(const double *base, idx_t i)
+{
+    return *(const double *)((const char *)base + (size_t)(i << 3));
+}
+
+__device__ __forceinline__ void st(double *base, idx_t i, double v)
+{
+    *(double *)((char *)base + (size_t)(i << 3)) = v;
+}
+
+__host__ __device__ __forceinline__ idx_t fidx_x(int nx, int ny, int i, int j, int k)
+{
+    return ((idx_t)k * ny + j) * (idx_t)(nx + 1) + i;
+}
+__host__ __device__ __forceinline__ idx_t fidx_y(int nx, int ny, int i, int j, int k)
+{
+    return ((idx_t)k * (ny + 1) + j) * (idx_t)nx + i;
+}
+__host__ __device__ __forceinline__ idx_t fidx_e(int nx, int ny, int i, int j, int k)
+{
+    return ((idx_t)k * ny + j) * (idx_t)nx + i;
+}
 
 __device__ __forceinline__ int wrap(int v, int n, int periodic)
 {
@@ -51,140 +92,174 @@ __device__ __forceinline__ int wrap(int v, int n, int periodic)
     return v;
 }
 
-__device__ __forceinline__ long long lin(const Phys &P, int i, int j, int k)
-{
-    return ((long long)k * P.ny + j) * P.nx + i;
-}
+// compiler-level fence between phases of a kernel
+__device__ __forceinline__ void phase_fence() { __builtin_amdgcn_sched_barrier(0); }
 
-// neighbour of (i,j,k) at offset o along axis d
-__device__ __forceinline__ long long nb(const Phys &P, int i, int j, int k, int d, int o)
-{
-    if (d == 0) return lin(P, wrap(i + o, P.nx, P.periodic[0]), j, k);
-    if (d == 1) return lin(P, i, wrap(j + o, P.ny, P.periodic[1]), k);
-    return lin(P, i, j, wrap(k + o, P.neta, P.periodic[2]));
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
+// counters: lane 0 of each wave adds the wave's totals to its own slot row
+__device__ __forceinline__ void slot_add(unsigned long long *slots, long long wave, int which,
+                                         long long v)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
-__device__ __forceinline__ void count_add(unsigned long long *ctr, int which, long long v)
-{
-    const long long s = wave_sum(v);
-    if ((threadIdx.x & 63) == 0 && s != 0) atomicAdd(ctr + which, (unsigned long long)s);
+    if ((threadIdx.x & 63) == 0 && v != 0) slots[wave * C_COUNT + which] += (unsigned long long)v;
 }
 
 // ------------------------------------------------------------ KT flux ----
-
-// H along axis d through the face between cells o and o+1 (o = -1: i-1/2,
-// o = 0: i+1/2) of cell (i,j,k), accumulated into acc with sign sgn/h.
-template <bool CART>
-__device__ __forceinline__ void face_flux(const Phys &P, const Eos &E, double tau,
-                                          const double *__restrict__ q, int i, int j, int k,
-                                          int d, int o, double w, double acc[NQ], int &iters)
+// One face between the cells s1 (left) and s2 (right) with outer neighbours
+// s0 and s3 (Sec. 3.1): minmod slopes, half-cell extrapolations
+// q^- = q_L + slope_L/2 and q^+ = q_R - slope_R/2, the inversion of both
+// (face_speeds_kernel; Sec. 3.1 last paragraph), the local speed
+// a = max(|v^-|, |v^+|) and H = (v^+ q^+ + v^- q^-)/2 - a (q^+ - q^-)/2.
+__device__ __forceinline__ double face_H(const double *q, idx_t co, double theta, idx_t s0, idx_t s1,
+                                         idx_t s2, idx_t s3, double vm, double vp, double a)
 {
-    const long long s0 = nb(P, i, j, k, d, o - 1), s1 = nb(P, i, j, k, d, o);
-    const long long s2 = nb(P, i, j, k, d, o + 1), s3 = nb(P, i, j, k, d, o + 2);
-    double qm[NQ], qp[NQ];
+    const double a0 = ld(q, co + s0), a1 = ld(q, co + s1), a2 = ld(q, co + s2), a3 = ld(q, co + s3);
+    const double qm = a1 + 0.5 * slope(a0, a1, a2, theta);
+    const double qp = a2 - 0.5 * slope(a1, a2, a3, theta);
+    return 0.5 * (vp * qp + vm * qm) - 0.5 * a * (qp - qm);
+}
+
+// inversion of the two reconstructed states of one face; returns v^-, v^+ along d
+template <bool CART>
+__device__ __forceinline__ void face_invert(const Phys &P, const Eos &E, double tau,
+                                            const double *__restrict__ q, const double *__restrict__ e,
+                                            idx_t s0, idx_t s1, idx_t s2, idx_t s3,
+                                            int d, double &vm, double &vp, int &iters)
+{
+    const idx_t SS = (idx_t)P.stride;
+    double m[9], p[9];
 #pragma unroll
-    for (int c = 0; c < NQ; ++c) {
-        const double *qc = q + c * P.stride;
-        const double a0 = qc[s0], a1 = qc[s1], a2 = qc[s2], a3 = qc[s3];
-        qm[c] = a1 + 0.5 * slope(a0, a1, a2, P.theta);   // q^- : left side of the face
-        qp[c] = a2 - 0.5 * slope(a1, a2, a3, P.theta);   // q^+ : right side of the face
+    for (int n = 0; n < 9; ++n) {
+        const int c = n < 8 ? n : BPI;
+        const idx_t co = (idx_t)c * SS;
+        const double a0 = ld(q, co + s0), a1 = ld(q, co + s1), a2 = ld(q, co + s2), a3 = ld(q, co + s3);
+        m[n] = a1 + 0.5 * slope(a0, a1, a2, P.theta);
+        p[n] = a2 - 0.5 * slope(a1, a2, a3, P.theta);
     }
-    const double Pim = P.bulk ? qm[BPI] : 0.0, Pip = P.bulk ? qp[BPI] : 0.0;
-    double em, ep, um[4], upl[4];
-    int im, ip;
-    recover<CART>(P, E, tau, qm[TT], qm[TX], qm[TY], qm[TE], qm[PTT], qm[PTX], qm[PTY], qm[PTE],
-                  Pim, em, um, im);
-    recover<CART>(P, E, tau, qp[TT], qp[TX], qp[TY], qp[TE], qp[PTT], qp[PTX], qp[PTY], qp[PTE],
-                  Pip, ep, upl, ip);
-    iters += im + ip;
-    const double vm = um[d + 1] / um[0], vp = upl[d + 1] / upl[0];
-    const double a = fmax(fabs(vm), fabs(vp));
-#pragma unroll
-    for (int c = 0; c < NQ; ++c) {
-        const double H = 0.5 * (vp * qp[c] + vm * qm[c]) - 0.5 * a * (qp[c] - qm[c]);
-        acc[c] += w * H;
+    double ee, pe, u[4];
+    int it;
+    recover<CART>(P, E, tau, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], P.bulk ? m[8] : 0.0,
+                  ld(e, s1), ee, pe, u, it);
+    vm = u[d + 1] / u[0];
+    iters += it;
+    recover<CART>(P, E, tau, p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7], P.bulk ? p[8] : 0.0,
+                  ld(e, s2), ee, pe, u, it);
+    vp = u[d + 1] / u[0];
+    iters += it;
+}
+
+// face speeds of every face of the grid at tau (thread per (i,j,k) in
+// [0,nx] x [0,ny] x [0,neta]: the x face at i, the y face at j, the eta face at k)
+template <bool CART>
+__global__ __launch_bounds__(256) void face_speeds_kernel(Phys P, Eos E, FaceGeo G, double tau,
+                                                          const double *q, const double *e,
+                                                          double *vf, unsigned long long *slots)
+{
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int j = blockIdx.y * 4 + threadIdx.y;
+    const int k = blockIdx.z;
+    const long long wave = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x * 4
+                         + (long long)blockIdx.x * 4 + threadIdx.y;
+    const idx_t plane = (idx_t)P.nx * P.ny;
+    int iters = 0, nf = 0;
+    if (i <= P.nx && j < P.ny && k < P.neta) {   // x face i (between cells i-1 and i) of row (j, k)
+        const idx_t r = (idx_t)k * plane + (idx_t)j * P.nx;
+        double vm, vp;
+        face_invert<CART>(P, E, tau, q, e, r + wrap(i - 2, P.nx, P.periodic[0]),
+                          r + wrap(i - 1, P.nx, P.periodic[0]), r + wrap(i, P.nx, P.periodic[0]),
+                          r + wrap(i + 1, P.nx, P.periodic[0]), 0, vm, vp, iters);
+        const idx_t f = fidx_x(P.nx, P.ny, i, j, k);
+        st(vf + G.ox, f, vm);
+        st(vf + G.ox + G.nfx, f, vp);
+        nf += 2;
     }
+    if (i < P.nx && j <= P.ny && k < P.neta) {
+        const idx_t b = (idx_t)k * plane + i;
+        double vm, vp;
+        face_invert<CART>(P, E, tau, q, e, b + (idx_t)wrap(j - 2, P.ny, P.periodic[1]) * P.nx,
+                          b + (idx_t)wrap(j - 1, P.ny, P.periodic[1]) * P.nx,
+                          b + (idx_t)wrap(j, P.ny, P.periodic[1]) * P.nx,
+                          b + (idx_t)wrap(j + 1, P.ny, P.periodic[1]) * P.nx, 1, vm, vp, iters);
+        const idx_t f = fidx_y(P.nx, P.ny, i, j, k);
+        st(vf + G.oy, f, vm);
+        st(vf + G.oy + G.nfy, f, vp);
+        nf += 2;
+    }
+    if (i < P.nx && j < P.ny && k <= P.neta) {
+        const idx_t b = (idx_t)j * P.nx + i;
+        double vm, vp;
+        face_invert<CART>(P, E, tau, q, e, b + (idx_t)wrap(k - 2, P.neta, P.periodic[2]) * plane,
+                          b + (idx_t)wrap(k - 1, P.neta, P.periodic[2]) * plane,
+                          b + (idx_t)wrap(k, P.neta, P.periodic[2]) * plane,
+                          b + (idx_t)wrap(k + 1, P.neta, P.periodic[2]) * plane, 2, vm, vp, iters);
+        const idx_t f = fidx_e(P.nx, P.ny, i, j, k);
+        st(vf + G.oe, f, vm);
+        st(vf + G.oe + G.nfe, f, vp);
+        nf += 2;
+    }
+    slot_add(slots, wave, C_ITERS_FACES, iters);
+    slot_add(slots, wave, C_REC_FACES, nf);
 }
 
 // A^{i nu} = T^{i nu} - v^i T^{tau nu} of one cell for axis i = d+1 (Eqs. Ttt-Tij):
 //   A^{i tau} = P v^i + pi^{i tau} - v^i pi^{tau tau}
 //   A^{i j}   = -P g^{ij} + pi^{ij} - v^i pi^{tau j}
 template <bool CART>
-__device__ __forceinline__ void nonadvective_row(const Phys &P, const Eos &E, double tau,
-                                                 const Fields &F, long long s, int d,
-                                                 double A[4])
+__device__ __forceinline__ void nonadvective_row(const Phys &P, double tau, const Fields &F,
+                                                 idx_t SS, idx_t s, int d, double A[4])
 {
-    const long long S = P.stride;
-    const double e = F.e[s];
-    const double Pc = eos_p(E, e) + (P.bulk ? F.q[BPI * S + s] : 0.0);
-    const double v = F.u[(d + 1) * S + s] / F.u[s];
+    const double Pc = ld(F.p, s) + (P.bulk ? ld(F.q, (idx_t)(BPI) * SS + s) : 0.0);
+    const double v = ld(F.u, (idx_t)((d + 1)) * SS + s) / ld(F.u, s);
     const int ii = d + 1;
-    double pr[4], p0[4];
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-        pr[n] = P.shear ? F.q[pi_index(ii, n) * S + s] : 0.0;
-        p0[n] = P.shear ? F.q[pi_index(0, n) * S + s] : 0.0;
-    }
     const double gii = ii == 3 ? (CART ? -1.0 : -1.0 / (tau * tau)) : -1.0;
-    A[0] = Pc * v + pr[0] - v * p0[0];
+    A[0] = Pc * v;
 #pragma unroll
-    for (int n = 1; n < 4; ++n) A[n] = (n == ii ? -Pc * gii : 0.0) + pr[n] - v * p0[n];
+    for (int n = 1; n < 4; ++n) A[n] = n == ii ? -Pc * gii : 0.0;
+    if (P.shear) {
+        A[0] += ld(F.q, (idx_t)pi_index(ii, 0) * SS + s) - v * ld(F.q, (idx_t)(PTT) * SS + s);
+#pragma unroll
+        for (int n = 1; n < 4; ++n)
+            A[n] += ld(F.q, (idx_t)pi_index(ii, n) * SS + s) - v * ld(F.q, (idx_t)pi_index(0, n) * SS + s);
+    }
 }
 
-// C[q] at one cell (Sec. 3.1, Eq. semiDiscreteKT with J of App. B)
+// sources J of one cell (App. B): S_c + G_c for T^{tau nu}, relaxation terms for pi and Pi
 template <bool CART>
-__device__ __forceinline__ void cell_rhs(const Phys &P, const Eos &E, double tau, const Fields &F,
-                                         int i, int j, int k, double out[NQ], int &fiters)
+__device__ __forceinline__ void cell_sources(const Phys &P, const Eos &E, double tau, const Fields &F,
+                                             idx_t SS, idx_t s, idx_t sxm, idx_t sxp, idx_t sym,
+                                             idx_t syp, idx_t szm, idx_t szp, double J[NQ])
 {
-    const long long S = P.stride;
-    const long long s = lin(P, i, j, k);
-    const double invh[3] = {P.inv_dx, P.inv_dy, P.inv_deta};
-#pragma unroll
-    for (int c = 0; c < NQ; ++c) out[c] = 0.0;
-    // flux divergence
-    for (int d = 0; d < 3; ++d) {
-        face_flux<CART>(P, E, tau, F.q, i, j, k, d, -1, invh[d], out, fiters);
-        face_flux<CART>(P, E, tau, F.q, i, j, k, d, 0, -invh[d], out, fiters);
-    }
-    // cell state
     double q[NQ];
 #pragma unroll
-    for (int c = 0; c < NQ; ++c) q[c] = F.q[c * S + s];
+    for (int c = 0; c < NQ; ++c) q[c] = ld(F.q, (idx_t)(c) * SS + s);
     if (!P.shear)
         for (int c = PTT; c <= PEE; ++c) q[c] = 0.0;
-    const double e = F.e[s];
-    double u[4], du[4][4];
+    const double invh[3] = {P.inv_dx, P.inv_dy, P.inv_deta};
+    double u[4], C[4][4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        u[m] = F.u[m * S + s];
-        du[0][m] = (u[m] - F.up[m * S + s]) * P.inv_dtau;
+        u[m] = ld(F.u, (idx_t)(m) * SS + s);
+        C[0][m] = (u[m] - ld(F.up, (idx_t)(m) * SS + s)) * P.inv_dtau;
     }
-    double p0, cs2, T;
-    eos_eval(E, e, p0, cs2, T);
-    const double Pi = P.bulk ? q[BPI] : 0.0;
-    const double Pc = p0 + Pi;
     // central differences (Sec. 3.1): d_i u^m, d_i v^i, S_c = -d_i A^{i nu}
     double divv = 0.0, Sc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const long long sp = nb(P, i, j, k, d, 1), sm = nb(P, i, j, k, d, -1);
+        const idx_t sp = d == 0 ? sxp : (d == 1 ? syp : szp);
+        const idx_t sm = d == 0 ? sxm : (d == 1 ? sym : szm);
         const double hh = 0.5 * invh[d];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) du[d + 1][m] = (F.u[m * S + sp] - F.u[m * S + sm]) * hh;
-        divv += (F.u[(d + 1) * S + sp] / F.u[sp] - F.u[(d + 1) * S + sm] / F.u[sm]) * hh;
+        for (int m = 0; m < 4; ++m) C[d + 1][m] = (ld(F.u, (idx_t)(m) * SS + sp) - ld(F.u, (idx_t)(m) * SS + sm)) * hh;
+        divv += (ld(F.u, (idx_t)((d + 1)) * SS + sp) / ld(F.u, sp) - ld(F.u, (idx_t)((d + 1)) * SS + sm) / ld(F.u, sm)) * hh;
         double Ap[4], Am[4];
-        nonadvective_row<CART>(P, E, tau, F, sp, d, Ap);
-        nonadvective_row<CART>(P, E, tau, F, sm, d, Am);
+        nonadvective_row<CART>(P, tau, F, SS, sp, d, Ap);
+        nonadvective_row<CART>(P, tau, F, SS, sm, d, Am);
 #pragma unroll
         for (int n = 0; n < 4; ++n) Sc[n] -= (Ap[n] - Am[n]) * hh;
     }
+    const double e = ld(F.e, s);
+    const double p0 = ld(F.p, s);
+    const double Pc = p0 + (P.bulk ? q[BPI] : 0.0);
     // geometric source of the conservation law (App. B): G^tau = -(T^tt + tau^2 T^ee)/tau,
     // G^x = -T^tx/tau, G^y = -T^ty/tau, G^eta = -3 T^te/tau, with
     // tau^2 T^ee = tau^2 v^eta (T^te - pi^te) + P + tau^2 pi^ee.
@@ -192,88 +267,176 @@ __device__ __forceinline__ void cell_rhs(const Phys &P, const Eos &E, double tau
         const double inv_tau = 1.0 / tau, t2 = tau * tau;
         const double ve = u[3] / u[0];
         const double t2Tee = t2 * (ve * (q[TE] - q[PTE]) + q[PEE]) + Pc;
-        out[TT] += Sc[0] - (q[TT] + t2Tee) * inv_tau;
-        out[TX] += Sc[1] - q[TX] * inv_tau;
-        out[TY] += Sc[2] - q[TY] * inv_tau;
-        out[TE] += Sc[3] - 3.0 * q[TE] * inv_tau;
+        J[TT] = Sc[0] - (q[TT] + t2Tee) * inv_tau;
+        J[TX] = Sc[1] - q[TX] * inv_tau;
+        J[TY] = Sc[2] - q[TY] * inv_tau;
+        J[TE] = Sc[3] - 3.0 * q[TE] * inv_tau;
     } else {
 #pragma unroll
-        for (int n = 0; n < 4; ++n) out[n] += Sc[n];
+        for (int n = 0; n < 4; ++n) J[n] = Sc[n];
     }
-    if (P.shear || P.bulk) {
-        double J[NQ];
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) J[c] = 0.0;
-        relaxation_sources<CART>(P, tau, q, e, p0, cs2, T, u, du, divv, J);
-        for (int c = PTT; c < NQ; ++c) out[c] += J[c];
+    for (int c = PTT; c < NQ; ++c) J[c] = 0.0;
+    if (P.shear || P.bulk) {
+        double pe, cs2, T;
+        eos_full(E, e, pe, cs2, T);
+        relaxation_sources<CART>(P, tau, q, e, p0, cs2, T, u, C, divv, J);
     }
-    if (!P.shear)
-        for (int c = PTT; c <= PEE; ++c) out[c] = 0.0;
-    if (!P.bulk) out[BPI] = 0.0;
 }
 
-// stage 1: out = q + dtau C[q];  stage 2: out = (qn + q + dtau C[q]) / 2 (out may alias qn)
+// One Euler stage for a 63 x BY x KC block of cells (Sec. 3.1, Eq.
+// semiDiscreteKT): C[q] = -sum_d (H_{+1/2} - H_{-1/2})/d_d + J, then
+//   stage 1: out = q + dtau C[q];  stage 2: out = (qn + q + dtau C[q]) / 2.
+// Face speeds come from face_speeds_kernel.  x faces: lane l computes the
+// face on the left of its cell and takes the right one from lane l+1; eta
+// faces: the top face of plane k is the bottom face of plane k+1 (kept in
+// LDS per thread); y faces: two per cell.
 template <bool CART, bool STAGE2>
-__global__ __launch_bounds__(BX *BY) void stage_kernel(Phys P, Eos E, double tau, Fields F,
-                                                         const double *qn, double *out,
-                                                         unsigned long long *ctr)
+__global__ __launch_bounds__(BX *BY) void stage_kernel(Phys P, Eos E, FaceGeo G, double tau,
+                                                         Fields F, const double *qn, double *out)
 {
-    const int i = blockIdx.x * BX + threadIdx.x;
+    __shared__ double Hb[NQ][BX * BY];   // eta face below the current plane
+    const int lane = threadIdx.x;
+    const int tid = threadIdx.y * BX + lane;
+    const int i = blockIdx.x * XOUT + lane;   // this lane's cell (x)
     const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
-    const bool active = i < P.nx && j < P.ny;
-    int fiters = 0;
-    if (active) {
-        double C[NQ];
-        cell_rhs<CART>(P, E, tau, F, i, j, k, C, fiters);
-        const long long s = lin(P, i, j, k);
-        const long long S = P.stride;
+    const int k0 = blockIdx.z * KC;
+    const idx_t plane = (idx_t)P.nx * P.ny;
+    // lanes outside the grid compute on clamped cells; their results are not stored
+    const int ic = i < P.nx ? i : P.nx - 1;
+    const int jc = j < P.ny ? j : P.ny - 1;
+    const int ifc = i <= P.nx ? i : P.nx;     // x face index of this lane
+    const bool out_ok = lane < XOUT && i < P.nx && j < P.ny;
+    const int xm2 = wrap(i - 2, P.nx, P.periodic[0]), xm1 = wrap(i - 1, P.nx, P.periodic[0]);
+    const int x0 = wrap(i, P.nx, P.periodic[0]), xp1 = wrap(i + 1, P.nx, P.periodic[0]);
+    const int xcm = wrap(ic - 1, P.nx, P.periodic[0]), xcp = wrap(ic + 1, P.nx, P.periodic[0]);
+    const int ym2 = wrap(jc - 2, P.ny, P.periodic[1]), ym1 = wrap(jc - 1, P.ny, P.periodic[1]);
+    const int yp1 = wrap(jc + 1, P.ny, P.periodic[1]), yp2 = wrap(jc + 2, P.ny, P.periodic[1]);
+    const double *vfx = F.vf + G.ox, *vfy = F.vf + G.oy, *vfe = F.vf + G.oe;
+#pragma unroll 1
+    for (int kk = 0; kk < KC; ++kk) {
+        const int k = k0 + kk;
+        if (k >= P.neta) break;    // uniform over the block
+        // component stride, opaque per iteration: keeps the compiler from hoisting
+        // the 60+ per-component stencil offsets out of the loop into registers
+        idx_t SS = (idx_t)P.stride;
+        asm volatile("" : "+s"(SS));
+        const idx_t kp = (idx_t)k * plane;
+        const idx_t rowc = kp + (idx_t)jc * P.nx;
+        const idx_t s = rowc + ic;
+        const int zm1 = wrap(k - 1, P.neta, P.periodic[2]), zp1 = wrap(k + 1, P.neta, P.periodic[2]);
+        const idx_t col = (idx_t)jc * P.nx + ic;
+        double acc[NQ];
+        cell_sources<CART>(P, E, tau, F, SS, s, rowc + xcm, rowc + xcp, kp + (idx_t)ym1 * P.nx + ic,
+                           kp + (idx_t)yp1 * P.nx + ic, col + (idx_t)zm1 * plane,
+                           col + (idx_t)zp1 * plane, acc);
+        phase_fence();
+        // x: face between x-1 and x (this lane); the right face comes from lane+1
+        {
+            const idx_t f = fidx_x(P.nx, P.ny, ifc, jc, k);
+            const double vm = ld(vfx, f), vp = ld(vfx + G.nfx, f);
+            const double a = fmax(fabs(vm), fabs(vp));
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) {
-            const double qs = F.q[c * S + s] + P.dtau * C[c];
-            out[c * S + s] = STAGE2 ? 0.5 * (qn[c * S + s] + qs) : qs;
+            for (int c = 0; c < NQ; ++c) {
+                const double H = face_H(F.q, (idx_t)c * SS, P.theta, rowc + xm2, rowc + xm1, rowc + x0,
+                                        rowc + xp1, vm, vp, a);
+                acc[c] += (H - __shfl_down(H, 1)) * P.inv_dx;
+            }
+        }
+        phase_fence();
+        // y: both faces of the cell
+        {
+            const idx_t base = kp + ic;
+            const idx_t r0 = base + (idx_t)ym2 * P.nx, r1 = base + (idx_t)ym1 * P.nx;
+            const idx_t r2 = base + (idx_t)jc * P.nx, r3 = base + (idx_t)yp1 * P.nx;
+            const idx_t r4 = base + (idx_t)yp2 * P.nx;
+            const idx_t f0 = fidx_y(P.nx, P.ny, ic, jc, k), f1 = fidx_y(P.nx, P.ny, ic, jc + 1, k);
+            const double vm0 = ld(vfy, f0), vp0 = ld(vfy + G.nfy, f0);
+            const double vm1 = ld(vfy, f1), vp1 = ld(vfy + G.nfy, f1);
+            const double a0 = fmax(fabs(vm0), fabs(vp0)), a1 = fmax(fabs(vm1), fabs(vp1));
+#pragma unroll
+            for (int c = 0; c < NQ; ++c)
+                acc[c] += (face_H(F.q, (idx_t)c * SS, P.theta, r0, r1, r2, r3, vm0, vp0, a0)
+                         - face_H(F.q, (idx_t)c * SS, P.theta, r1, r2, r3, r4, vm1, vp1, a1)) * P.inv_dy;
+        }
+        phase_fence();
+        // eta: bottom face (computed at the first plane, carried afterwards) and top face
+        {
+            const int zp2 = wrap(k + 2, P.neta, P.periodic[2]);
+            if (kk == 0) {
+                const int zm2 = wrap(k - 2, P.neta, P.periodic[2]);
+                const idx_t f = fidx_e(P.nx, P.ny, ic, jc, k);
+                const double vm = ld(vfe, f), vp = ld(vfe + G.nfe, f);
+                const double a = fmax(fabs(vm), fabs(vp));
+#pragma unroll
+                for (int c = 0; c < NQ; ++c)
+                    Hb[c][tid] = face_H(F.q, (idx_t)c * SS, P.theta, col + (idx_t)zm2 * plane,
+                                        col + (idx_t)zm1 * plane, col + kp, col + (idx_t)zp1 * plane,
+                                        vm, vp, a);
+            }
+            const idx_t f = fidx_e(P.nx, P.ny, ic, jc, k + 1);
+            const double vm = ld(vfe, f), vp = ld(vfe + G.nfe, f);
+            const double a = fmax(fabs(vm), fabs(vp));
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) {
+                const double H = face_H(F.q, (idx_t)c * SS, P.theta, col + (idx_t)zm1 * plane, col + kp,
+                                        col + (idx_t)zp1 * plane, col + (idx_t)zp2 * plane, vm, vp, a);
+                acc[c] += (Hb[c][tid] - H) * P.inv_deta;
+                Hb[c][tid] = H;
+            }
+        }
+        if (!P.shear)
+            for (int c = PTT; c <= PEE; ++c) acc[c] = 0.0;
+        if (!P.bulk) acc[BPI] = 0.0;
+        if (out_ok) {
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) {
+                const double qs = ld(F.q, (idx_t)(c) * SS + s) + P.dtau * acc[c];
+                st(out, (idx_t)(c) * SS + s, STAGE2 ? 0.5 * (ld(qn, (idx_t)(c) * SS + s) + qs) : qs);
+            }
         }
     }
-    count_add(ctr, C_ITERS_FACES, fiters);
-    count_add(ctr, C_REC_FACES, active ? 6 * 2 : 0);
 }
 
-// recovery of every cell at tau, then the regulator and the floor reset
+// recovery of every cell at tau (warm start: the cell's previous e), then
+// the regulator and the floor reset; writes e, p(e) and u
 template <bool CART>
 __global__ __launch_bounds__(256) void recover_kernel(Phys P, Eos E, double tau, double *q,
-                                                      double *e_out, double *u_out,
-                                                      int do_regulate,
-                                                      unsigned long long *ctr)
+                                                      double *e_io, double *p_out, double *u_out,
+                                                      int do_regulate, int warm,
+                                                      unsigned long long *slots)
 {
-    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long S = P.stride;
+    const idx_t s = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long wave = s >> 6;
+    const idx_t SS = (idx_t)P.stride;
     int it = 0, fl = 0;
-    if (s < P.ncell) {
+    const bool valid = (long long)s < P.ncell;
+    if (valid) {
         double qc[NQ];
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) qc[c] = q[c * S + s];
+        for (int c = 0; c < NQ; ++c) qc[c] = ld(q, (idx_t)(c) * SS + s);
         const double Pi = P.bulk ? qc[BPI] : 0.0;
-        double e, u[4];
+        double e, p0, u[4];
         fl = recover<CART>(P, E, tau, qc[TT], qc[TX], qc[TY], qc[TE], qc[PTT], qc[PTX], qc[PTY],
-                           qc[PTE], Pi, e, u, it);
-        e_out[s] = e;
+                           qc[PTE], Pi, warm ? ld(e_io, s) : -1.0, e, p0, u, it);
+        st(e_io, s, e);
+        st(p_out, s, p0);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) u_out[m * S + s] = u[m];
+        for (int m = 0; m < 4; ++m) st(u_out, (idx_t)(m) * SS + s, u[m]);
         if ((fl & F_FLOOR) && P.floor_reset) {
 #pragma unroll
-            for (int c = 0; c < NQ; ++c) q[c * S + s] = c == TT ? P.e_floor : 0.0;
+            for (int c = 0; c < NQ; ++c) st(q, (idx_t)(c) * SS + s, c == TT ? P.e_floor : 0.0);
         } else if (do_regulate && P.regulate && P.shear) {
-            const double p0 = eos_p(E, e);
             regulate<CART>(P, tau, qc, e, p0, u);
 #pragma unroll
-            for (int c = PTT; c < NQ; ++c) q[c * S + s] = qc[c];
+            for (int c = PTT; c < NQ; ++c) st(q, (idx_t)(c) * SS + s, qc[c]);
         }
     }
-    count_add(ctr, C_ITERS_CELLS, it);
-    count_add(ctr, C_REC_CELLS, s < P.ncell ? 1 : 0);
-    count_add(ctr, C_FLOOR, (fl & F_FLOOR) ? 1 : 0);
-    count_add(ctr, C_CLAMP, (fl & F_CLAMP) ? 1 : 0);
-    count_add(ctr, C_FALLBACK, (fl & F_FALLBACK) ? 1 : 0);
+    slot_add(slots, wave, C_ITERS_CELLS, it);
+    slot_add(slots, wave, C_REC_CELLS, valid ? 1 : 0);
+    slot_add(slots, wave, C_FLOOR, (fl & F_FLOOR) ? 1 : 0);
+    slot_add(slots, wave, C_CLAMP, (fl & F_CLAMP) ? 1 : 0);
+    slot_add(slots, wave, C_FALLBACK, (fl & F_FALLBACK) ? 1 : 0);
 }
 
 // T^{tau mu} from primitives (Sec. 2.4, Eqs. Ttt, Tti): (e+P) u^tau u^mu - P g^{tau mu} + pi^{tau mu}
@@ -286,20 +449,20 @@ struct PrimPtrs {
 
 __global__ __launch_bounds__(256) void tmunu_kernel(Phys P, Eos E, PrimPtrs in, double *q)
 {
-    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= P.ncell) return;
-    const long long S = P.stride;
-    const double e = in.e[s];
-    const double Pi = in.Pi[s];
+    const idx_t s = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((long long)s >= P.ncell) return;
+    const idx_t SS = (idx_t)P.stride;
+    const double e = ld(in.e, s);
+    const double Pi = ld(in.Pi, s);
     const double Pc = eos_p(E, e) + Pi;
-    const double ut = in.u[0][s];
+    const double ut = ld(in.u[0], s);
     const double w = (e + Pc) * ut;
 #pragma unroll
     for (int m = 0; m < 4; ++m)   // pi^{tau m} are the first four of the ten
-        q[m * S + s] = w * in.u[m][s] - (m == 0 ? Pc : 0.0) + in.pi[m][s];
+        st(q, (idx_t)(m) * SS + s, w * ld(in.u[m], s) - (m == 0 ? Pc : 0.0) + ld(in.pi[m], s));
 #pragma unroll
-    for (int c = 0; c < 10; ++c) q[(PTT + c) * S + s] = in.pi[c][s];
-    q[BPI * S + s] = Pi;
+    for (int c = 0; c < 10; ++c) st(q, (idx_t)((PTT + c)) * SS + s, ld(in.pi[c], s));
+    st(q, (idx_t)(BPI) * SS + s, Pi);
 }
 
 struct RecIn {
@@ -317,15 +480,34 @@ __global__ __launch_bounds__(256) void recover_standalone_kernel(Phys P, Eos E, 
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const double Pi = (P.bulk && R.in[8]) ? R.in[8][s] : 0.0;
-    double e, u[4];
+    double e, p, u[4];
     int it;
     const int fl = recover<CART>(P, E, tau, R.in[0][s], R.in[1][s], R.in[2][s], R.in[3][s],
-                                 R.in[4][s], R.in[5][s], R.in[6][s], R.in[7][s], Pi, e, u, it);
+                                 R.in[4][s], R.in[5][s], R.in[6][s], R.in[7][s], Pi, -1.0, e, p,
+                                 u, it);
     R.e[s] = e;
 #pragma unroll
     for (int m = 0; m < 4; ++m) R.u[m][s] = u[m];
     if (R.iters) R.iters[s] = it;
     if (R.flags) R.flags[s] = fl;
+}
+
+// sum of the counter slots (deterministic: one thread per counter)
+__global__ void slots_reduce_kernel(const unsigned long long *slots, long long nwaves,
+                                    unsigned long long *out)
+{
+    __shared__ unsigned long long part[C_COUNT][64];
+    const int c = threadIdx.y, l = threadIdx.x;
+    unsigned long long v = 0;
+    if (c < C_COUNT)
+        for (long long w = l; w < nwaves; w += 64) v += slots[w * C_COUNT + c];
+    if (c < C_COUNT) part[c][l] = v;
+    __syncthreads();
+    if (c < C_COUNT && l == 0) {
+        unsigned long long t = 0;
+        for (int k = 0; k < 64; ++k) t += part[c][k];
+        out[c] = t;
+    }
 }
 
 // ---------------------------------------------------------- observables --
@@ -378,7 +560,7 @@ __global__ __launch_bounds__(OBS_THREADS) void obs_partial_kernel(Phys P, Eos E,
         acc[O_MY] += qc[TY];
         acc[O_ME] += qc[TE];
         double p0, cs2, T;
-        eos_eval(E, ec, p0, cs2, T);
+        eos_full(E, ec, p0, cs2, T);
         acc[O_EMAX] = fmax(acc[O_EMAX], ec);
         acc[O_TMAX] = fmax(acc[O_TMAX], T);
         double cfl = 0.0, vmax = 0.0;
@@ -465,10 +647,13 @@ struct kt_ctx {
     Eos E;
     hipStream_t stream;
     double *ws;
-    double *q, *qs, *e, *u[3];   // u[cur], u[prev], u[star] by index below
+    double *q, *qs, *e, *p, *u[3];   // u[cur], u[prev], u[star] by index below
     int ucur, uprev, ustar;
     double *tab;
-    unsigned long long *ctr;
+    unsigned long long *slots, *ctr;
+    long long nwaves;
+    double *vf;
+    FaceGeo G;
     double *partial, *obs;
     double tau;
     long long step;
@@ -528,8 +713,38 @@ static long long cell_stride(const kt_params *p)
 }
 
 struct Layout {
-    size_t q, qs, u, e, tab, ctr, partial, obs, total;
+    size_t q, qs, u, e, p, vf, tab, slots, ctr, partial, obs, total;
+    long long nwaves;
+    FaceGeo G;
 };
+
+static FaceGeo face_geo(const kt_params *p)
+{
+    FaceGeo G;
+    G.nfx = (long long)(p->nx + 1) * p->ny * p->neta;
+    G.nfy = (long long)p->nx * (p->ny + 1) * p->neta;
+    G.nfe = (long long)p->nx * p->ny * (p->neta + 1);
+    G.ox = 0;
+    G.oy = 2 * G.nfx;
+    G.oe = G.oy + 2 * G.nfy;
+    return G;
+}
+
+static long long face_waves(const kt_params *p)
+{
+    return (long long)((p->nx + 1 + 63) / 64) * ((p->ny + 1 + 3) / 4) * (p->neta + 1) * 4;
+}
+
+static long long stage_waves(const kt_params *p)
+{
+    return (long long)((p->nx + XOUT - 1) / XOUT) * ((p->ny + BY - 1) / BY) * ((p->neta + KC - 1) / KC) * BY;
+}
+
+static long long recover_waves(const kt_params *p)
+{
+    const long long n = (long long)p->nx * p->ny * p->neta;
+    return (n + 255) / 256 * 4;
+}
 
 static Layout layout(const kt_params *p, const kt_eos *eos)
 {
@@ -540,7 +755,14 @@ static Layout layout(const kt_params *p, const kt_eos *eos)
     L.qs = off; off += 15 * S;
     L.u = off;  off += 12 * S;
     L.e = off;  off += S;
-    L.tab = off; off += round_up((size_t)(eos->conformal ? 1 : eos->n) * 3 * sizeof(double), 256);
+    L.p = off;  off += S;
+    L.G = face_geo(p);
+    L.vf = off; off += round_up((size_t)(L.G.oe + 2 * L.G.nfe) * sizeof(double), 256);
+    L.tab = off; off += round_up((size_t)(eos->conformal ? 1 : eos->n) * EOS_W * sizeof(double), 256);
+    const long long sw = stage_waves(p), rw = recover_waves(p), fw = face_waves(p);
+    L.nwaves = sw > rw ? sw : rw;
+    L.nwaves = L.nwaves > fw ? L.nwaves : fw;
+    L.slots = off; off += round_up((size_t)L.nwaves * C_COUNT * sizeof(unsigned long long), 256);
     L.ctr = off; off += 256;
     L.partial = off; off += round_up((size_t)OBS_BLOCKS * O_COUNT * sizeof(double), 256);
     L.obs = off; off += 256;
@@ -552,7 +774,9 @@ static const char *check_args(const kt_params *p, const kt_eos *eos)
 {
     if (!p || !eos) return "null params or eos";
     if (p->nx < 1 || p->ny < 1 || p->neta < 1) return "grid sizes must be >= 1";
-    if ((long long)p->nx * p->ny * p->neta > (1LL << 31)) return "grid too large";
+    if ((long long)(p->nx + 1) * (p->ny + 1) * (p->neta + 1) * 15 * 8 >= (1LL << 32))
+        return "grid too large: each field array is addressed with 32-bit byte offsets "
+               "(15 components x cells x 8 B must stay below 4 GiB)";
     if (!(p->dx > 0) || !(p->dy > 0) || !(p->deta > 0)) return "cell sizes must be > 0";
     if (!(p->dtau > 0)) return "dtau must be > 0";
     if (p->coords != KT_MILNE && p->coords != KT_CARTESIAN) return "coords must be KT_MILNE or KT_CARTESIAN";
@@ -602,22 +826,38 @@ static hipError_t launch(K kernel, dim3 g, dim3 b, hipStream_t st, A... args)
 
 static dim3 cells_grid(const Phys &P)
 {
-    return dim3((P.nx + BX - 1) / BX, (P.ny + BY - 1) / BY, P.neta);
+    return dim3((P.nx + XOUT - 1) / XOUT, (P.ny + BY - 1) / BY, (P.neta + KC - 1) / KC);
 }
 
 static dim3 linear_grid(long long n) { return dim3((unsigned)((n + 255) / 256)); }
 
-static kt_status run_recover(kt_ctx *c, double tau, double *q, double *u_out, int regulate)
+static kt_status run_recover(kt_ctx *c, double tau, double *q, double *u_out, int regulate,
+                             int warm)
 {
     const bool cart = c->prm.coords == KT_CARTESIAN;
     hipError_t e = prof_mark(c, 1, true);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
     e = cart ? launch(recover_kernel<true>, linear_grid(c->P.ncell), dim3(256), c->stream,
-                                 c->P, c->E, tau, q, c->e, u_out, regulate, c->ctr)
-                        : launch(recover_kernel<false>, linear_grid(c->P.ncell), dim3(256), c->stream,
-                                 c->P, c->E, tau, q, c->e, u_out, regulate, c->ctr);
+                      c->P, c->E, tau, q, c->e, c->p, u_out, regulate, warm, c->slots)
+             : launch(recover_kernel<false>, linear_grid(c->P.ncell), dim3(256), c->stream,
+                      c->P, c->E, tau, q, c->e, c->p, u_out, regulate, warm, c->slots);
     if (e == hipSuccess) e = prof_mark(c, 1, false);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "recover kernel: %s", hipGetErrorString(e));
+    return KT_OK;
+}
+
+static kt_status run_faces(kt_ctx *c, double tau, const double *q)
+{
+    const bool cart = c->prm.coords == KT_CARTESIAN;
+    hipError_t e = prof_mark(c, 2, true);
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
+    const dim3 g((c->P.nx + 1 + 63) / 64, (c->P.ny + 1 + 3) / 4, c->P.neta + 1), b(64, 4);
+    e = cart ? launch(face_speeds_kernel<true>, g, b, c->stream, c->P, c->E, c->G, tau, q,
+                      (const double *)c->e, c->vf, c->slots)
+             : launch(face_speeds_kernel<false>, g, b, c->stream, c->P, c->E, c->G, tau, q,
+                      (const double *)c->e, c->vf, c->slots);
+    if (e == hipSuccess) e = prof_mark(c, 2, false);
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "face kernel: %s", hipGetErrorString(e));
     return KT_OK;
 }
 
@@ -628,15 +868,15 @@ static kt_status run_stage(kt_ctx *c, bool stage2, double tau, const Fields &F, 
     hipError_t e = prof_mark(c, 0, true);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
     if (cart)
-        e = stage2 ? launch(stage_kernel<true, true>, g, b, c->stream, c->P, c->E, tau, F,
-                            (const double *)c->q, out, c->ctr)
-                   : launch(stage_kernel<true, false>, g, b, c->stream, c->P, c->E, tau, F,
-                            (const double *)nullptr, out, c->ctr);
+        e = stage2 ? launch(stage_kernel<true, true>, g, b, c->stream, c->P, c->E, c->G, tau, F,
+                            (const double *)c->q, out)
+                   : launch(stage_kernel<true, false>, g, b, c->stream, c->P, c->E, c->G, tau, F,
+                            (const double *)nullptr, out);
     else
-        e = stage2 ? launch(stage_kernel<false, true>, g, b, c->stream, c->P, c->E, tau, F,
-                            (const double *)c->q, out, c->ctr)
-                   : launch(stage_kernel<false, false>, g, b, c->stream, c->P, c->E, tau, F,
-                            (const double *)nullptr, out, c->ctr);
+        e = stage2 ? launch(stage_kernel<false, true>, g, b, c->stream, c->P, c->E, c->G, tau, F,
+                            (const double *)c->q, out)
+                   : launch(stage_kernel<false, false>, g, b, c->stream, c->P, c->E, c->G, tau, F,
+                            (const double *)nullptr, out);
     if (e == hipSuccess) e = prof_mark(c, 0, false);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "stage kernel: %s", hipGetErrorString(e));
     return KT_OK;
@@ -707,30 +947,40 @@ kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0
     for (int b = 0; b < 3; ++b) c->u[b] = (double *)(base + L.u) + (size_t)4 * S * b;
     c->ucur = 0; c->uprev = 1; c->ustar = 2;
     c->e = (double *)(base + L.e);
+    c->p = (double *)(base + L.p);
     c->tab = (double *)(base + L.tab);
+    c->slots = (unsigned long long *)(base + L.slots);
     c->ctr = (unsigned long long *)(base + L.ctr);
+    c->nwaves = L.nwaves;
+    c->vf = (double *)(base + L.vf);
+    c->G = L.G;
     c->partial = (double *)(base + L.partial);
     c->obs = (double *)(base + L.obs);
     c->tau = p->tau0;
     c->step = 0;
 
-    // EOS table: per node p/e, T/e^{1/4}, c_s^2 (node e_i = exp(ln_e0 + i dln_e))
+    // EOS table: per node p/e, T/e^{1/4}, c_s^2, 1/e_i (node e_i = exp(ln_e0 + i dln_e))
     c->E.conformal = eos->conformal != 0;
     c->E.inv_a = eos->conformal ? 1.0 / eos->a_sb : 0.0;
     c->E.n = eos->conformal ? 0 : eos->n;
     c->E.ln_e0 = eos->ln_e0;
     c->E.inv_dln = eos->conformal ? 0.0 : 1.0 / eos->dln_e;
     c->E.tab = c->tab;
+    c->P.p_floor = p->e_floor / 3.0;
     if (!eos->conformal) {
-        double *h = (double *)malloc(sizeof(double) * 3 * eos->n);
+        double *h = (double *)malloc(sizeof(double) * EOS_W * eos->n);
         if (!h) { delete c; return fail(nullptr, KT_E_ALLOC, "host allocation failed"); }
         for (int i = 0; i < eos->n; ++i) {
             const double ei = exp(eos->ln_e0 + eos->dln_e * (double)i);
-            h[3 * i] = eos->p[i] / ei;
-            h[3 * i + 1] = eos->T[i] / sqrt(sqrt(ei));
-            h[3 * i + 2] = eos->cs2[i];
+            h[EOS_W * i] = eos->p[i] / ei;
+            h[EOS_W * i + 1] = eos->T[i] / sqrt(sqrt(ei));
+            h[EOS_W * i + 2] = eos->cs2[i];
+            h[EOS_W * i + 3] = 1.0 / ei;
         }
-        hipError_t e1 = hipMemcpyAsync(c->tab, h, sizeof(double) * 3 * eos->n, hipMemcpyHostToDevice, stream);
+        Eos hE = c->E;   // same interpolation on the host for p(e_floor)
+        hE.tab = h;
+        c->P.p_floor = eos_p(hE, p->e_floor);
+        hipError_t e1 = hipMemcpyAsync(c->tab, h, sizeof(double) * EOS_W * eos->n, hipMemcpyHostToDevice, stream);
         hipError_t e2 = hipStreamSynchronize(stream);
         free(h);
         if (e1 != hipSuccess || e2 != hipSuccess) {
@@ -739,7 +989,7 @@ kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0
             return st;
         }
     }
-    hipError_t he = hipMemsetAsync(c->ctr, 0, 256, stream);
+    hipError_t he = hipMemsetAsync(c->slots, 0, (size_t)L.nwaves * C_COUNT * sizeof(unsigned long long), stream);
     if (he != hipSuccess) { delete c; return fail(nullptr, KT_E_HIP, "memset: %s", hipGetErrorString(he)); }
 
     // q^0
@@ -759,7 +1009,8 @@ kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0
     }
     if (he != hipSuccess) { delete c; return fail(nullptr, KT_E_HIP, "initial state: %s", hipGetErrorString(he)); }
     // (e^0, u^0) and u^{-1}
-    kt_status st = run_recover(c, c->tau, c->q, c->u[c->ucur], 0);
+    kt_status st = run_recover(c, c->tau, c->q, c->u[c->ucur], 0, 0);
+    if (st == KT_OK) st = run_faces(c, c->tau, c->q);
     if (st != KT_OK) { kt_status r = fail(nullptr, st, "%s", c->err); delete c; return r; }
     for (int m = 0; m < 4 && he == hipSuccess; ++m)
         he = hipMemcpyAsync(c->u[c->uprev] + m * S, have_up ? s0->u_prev[m] : c->u[c->ucur] + m * S,
@@ -777,17 +1028,20 @@ kt_status kt_step(kt_ctx *c, int32_t n_steps)
     const long long S = c->P.stride;
     for (int s = 0; s < n_steps; ++s) {
         const double tau0 = c->tau, tau1 = c->tau + c->prm.dtau;
-        Fields F1 = {c->q, c->e, c->u[c->ucur], c->u[c->uprev]};
+        // face speeds of q^n are current (computed after the previous recovery)
+        Fields F1 = {c->q, c->e, c->p, c->u[c->ucur], c->u[c->uprev], c->vf};
         kt_status st = run_stage(c, false, tau0, F1, c->qs);
         if (st != KT_OK) return st;
-        st = run_recover(c, tau1, c->qs, c->u[c->ustar], 1);
+        st = run_recover(c, tau1, c->qs, c->u[c->ustar], 1, 1);
+        if (st == KT_OK) st = run_faces(c, tau1, c->qs);
         if (st != KT_OK) return st;
-        Fields F2 = {c->qs, c->e, c->u[c->ustar], c->u[c->ucur]};
+        Fields F2 = {c->qs, c->e, c->p, c->u[c->ustar], c->u[c->ucur], c->vf};
         st = run_stage(c, true, tau1, F2, c->q);
         if (st != KT_OK) return st;
         // u^{n-1} <- u^n; (e, u)^{n+1} into the freed buffer
         const int freed = c->uprev;
-        st = run_recover(c, tau1, c->q, c->u[freed], 1);
+        st = run_recover(c, tau1, c->q, c->u[freed], 1, 1);
+        if (st == KT_OK) st = run_faces(c, tau1, c->q);
         if (st != KT_OK) return st;
         c->uprev = c->ucur;
         c->ucur = freed;
@@ -851,6 +1105,9 @@ kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out)
                           (const double *)c->q, (const double *)c->e, (const double *)c->u[c->ucur], c->partial);
         if (e == hipSuccess)
             e = launch(obs_final_kernel, dim3(1), dim3(64), c->stream, (const double *)c->partial, OBS_BLOCKS, c->obs);
+        if (e == hipSuccess)
+            e = launch(slots_reduce_kernel, dim3(1), dim3(64, C_COUNT), c->stream,
+                       (const unsigned long long *)c->slots, c->nwaves, c->ctr);
         if (e == hipSuccess) e = hipMemcpyAsync(res, c->obs, sizeof(res), hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(ctr, c->ctr, sizeof(ctr), hipMemcpyDeviceToHost, c->stream);
     }

@@ -278,7 +278,8 @@ class Solver:
         p = KtProfile()
         _check(lib().kt_profile_read(self.ctx, C.byref(p)), self.ctx)
         return dict(stage_ms=p.ms[0], stage_launches=p.launches[0],
-                    recover_ms=p.ms[1], recover_launches=p.launches[1])
+                    recover_ms=p.ms[1], recover_launches=p.launches[1],
+                    faces_ms=p.ms[2], faces_launches=p.launches[2])
 
     def close(self):
         if getattr(self, "ctx", None):
