@@ -28,6 +28,17 @@ METRIC = "cell-updates/s per Heun step (128^3 viscous), % HBM peak; learned vs N
 #   one Heun step moves 103 values when recovery is fused with the stages
 STAGE_VALUES = (39, 54)
 STEP_VALUES = 103
+# algorithmic values per cell and launch of each kernel class, averaged over the two stages:
+#   flux     reads q (15) and the stage accumulator (15), writes it (15)           = 45
+#   sources  reads q (15), u (4), u_prev (4), e, p and, in stage 2, q^n (15);
+#            writes 15                                                             = 40 / 55
+#   recover  reads q (15), e; writes e, p, u (4) and the 10 regulated pi           = 32
+#   faces    reads 9 components of q and e; writes v^-, v^+ of 3 faces (6)         = 16
+KERNEL_VALUES = {"flux": 45.0, "sources": 47.5, "recover": 32.0, "faces": 16.0}
+KERNEL_NAMES = {"flux": "flux_kernel (KT flux divergence + stage update)",
+                "sources": "sources_kernel (App. B sources + stage update)",
+                "recover": "recover_kernel (Newton inversion + regulator)",
+                "faces": "face_speeds_kernel (inversion of reconstructed face states)"}
 
 
 def parse():
@@ -103,17 +114,21 @@ def main():
     ms = start.elapsed_time(stop) / args.steps
     prof = solver.profile_read()
     obs = solver.observables()
-    print("bench: timed %d steps, %.3f ms/step, stage %.3f ms/launch, recover %.3f ms/launch"
-          % (args.steps, ms, prof["stage_ms"] / max(1, prof["stage_launches"]),
-             prof["recover_ms"] / max(1, prof["recover_launches"])), file=sys.stderr, flush=True)
+    per = {k: prof[k + "_ms"] / max(1, prof[k + "_launches"]) for k in kt.PROFILE_CLASSES}
+    print("bench: timed %d steps, %.3f ms/step; per launch: %s" % (
+        args.steps, ms, ", ".join("%s %.3f ms" % kv for kv in per.items())),
+        file=sys.stderr, flush=True)
     value = ncell / (ms * 1e-3)
-    stage_avg_s = prof["stage_ms"] / prof["stage_launches"] * 1e-3
-    stage_bytes = 8.0 * ncell * sum(STAGE_VALUES) / len(STAGE_VALUES)
-    achieved = stage_bytes / stage_avg_s / 1e9
+    # dominant kernel by total time in the timed region
+    dom = max(kt.PROFILE_CLASSES, key=lambda k: prof[k + "_ms"])
+    dom_avg_s = per[dom] * 1e-3
+    dom_bytes = 8.0 * ncell * KERNEL_VALUES[dom]
+    achieved = dom_bytes / dom_avg_s / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "stage_kernel (KT flux + sources + Euler/Heun update)",
-            "bytes_per_launch": stage_bytes, "mean_launch_ms": stage_avg_s * 1e3}
+            "kernel": KERNEL_NAMES[dom], "bytes_per_launch": dom_bytes,
+            "mean_launch_ms": per[dom],
+            "per_launch_ms": per}
     rec = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -125,7 +140,8 @@ def main():
                    "zeta_over_s": "0.1 (1/3 - c_s^2)", "eos": "tabulated, 4096 nodes",
                    "precision": "fp64", "inversion_start": "conformal closed form",
                    "step_hbm_frac": STEP_VALUES * 8.0 * value / (HBM_PEAK_GBS * 1e9),
-                   "paper_context_ms_per_step": {"gtx980ti_fp32_128cube": 244.45}},
+                   "paper_context_ms_per_step": {"gtx980ti_fp32_128cube_table": 244.45,
+                                                 "gtx980ti_program_summary": 38400.0}},
         "roofline": roof,
         "diagnostics": {k: obs[k] for k in ("tau", "n_nan", "n_floor", "n_clamp", "n_fallback",
                                             "e_max", "cfl")},

@@ -178,9 +178,9 @@ kt_status kt_recover(kt_ctx *c, int64_t n, double tau, const double *const in[9]
 kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
- * every launch of kt_step.  Kernel classes: 0 = KT stage (flux + sources +
- * update), 1 = cell recovery and regulator, 2 = inversion of the
- * reconstructed states at every face.  kt_profile_enable(c, 1) starts
+ * every launch of kt_step.  Kernel classes: 0 = KT flux divergence and
+ * stage update, 1 = cell recovery and regulator, 2 = inversion of the
+ * reconstructed states at every face, 3 = source terms J of a stage.  kt_profile_enable(c, 1) starts
  * recording (events are pooled, created on first use); kt_profile_read
  * synchronises the stream, returns the totals since the last read and
  * resets them. */

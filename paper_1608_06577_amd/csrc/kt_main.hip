@@ -33,10 +33,7 @@ using namespace ktd;
 
 namespace {
 
-constexpr int BX = 64;     // one wavefront along x; 63 cells are output per wave
-constexpr int XOUT = BX - 1;
-constexpr int BY = 4;      // rows of y per block (one wavefront each)
-constexpr int KC = 4;      // consecutive eta planes per thread (eta faces carried)
+constexpr int KC = 4;      // consecutive eta planes per thread in flux_kernel (eta faces carried)
 
 // ------------------------------------------------------------------ grid --
 
@@ -91,9 +88,6 @@ __device__ __forceinline__ int wrap(int v, int n, int periodic)
     if (v >= n) return periodic ? v % n : n - 1;
     return v;
 }
-
-// compiler-level fence between phases of a kernel
-__device__ __forceinline__ void phase_fence() { __builtin_amdgcn_sched_barrier(0); }
 
 // counters: lane 0 of each wave adds the wave's totals to its own slot row
 __device__ __forceinline__ void slot_add(unsigned long long *slots, long long wave, int which,
@@ -284,115 +278,139 @@ __device__ __forceinline__ void cell_sources(const Phys &P, const Eos &E, double
     }
 }
 
-// One Euler stage for a 63 x BY x KC block of cells (Sec. 3.1, Eq.
-// semiDiscreteKT): C[q] = -sum_d (H_{+1/2} - H_{-1/2})/d_d + J, then
-//   stage 1: out = q + dtau C[q];  stage 2: out = (qn + q + dtau C[q]) / 2.
-// Face speeds come from face_speeds_kernel.  x faces: lane l computes the
-// face on the left of its cell and takes the right one from lane l+1; eta
-// faces: the top face of plane k is the bottom face of plane k+1 (kept in
-// LDS per thread); y faces: two per cell.
+// Sources part of one Euler stage (Sec. 3.1, Eq. semiDiscreteKT, and
+// App. B), one thread per cell:
+//   stage 1: out = q + dtau J;   stage 2: out = qn + q + dtau J.
+// flux_kernel then adds the flux divergence and completes the stage.
 template <bool CART, bool STAGE2>
-__global__ __launch_bounds__(BX *BY) void stage_kernel(Phys P, Eos E, FaceGeo G, double tau,
-                                                         Fields F, const double *qn, double *out)
+__global__ __launch_bounds__(256) void sources_kernel(Phys P, Eos E, double tau, Fields F,
+                                                      const double *qn, double *out)
 {
-    __shared__ double Hb[NQ][BX * BY];   // eta face below the current plane
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int j = blockIdx.y * 4 + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= P.nx || j >= P.ny) return;
+    const idx_t SS = (idx_t)P.stride;
+    const idx_t plane = (idx_t)P.nx * P.ny;
+    const idx_t kp = (idx_t)k * plane;
+    const idx_t rowc = kp + (idx_t)j * P.nx;
+    const idx_t s = rowc + i;
+    const idx_t col = (idx_t)j * P.nx + i;
+    double J[NQ];
+    cell_sources<CART>(P, E, tau, F, SS, s, rowc + wrap(i - 1, P.nx, P.periodic[0]),
+                       rowc + wrap(i + 1, P.nx, P.periodic[0]),
+                       kp + (idx_t)wrap(j - 1, P.ny, P.periodic[1]) * P.nx + i,
+                       kp + (idx_t)wrap(j + 1, P.ny, P.periodic[1]) * P.nx + i,
+                       col + (idx_t)wrap(k - 1, P.neta, P.periodic[2]) * plane,
+                       col + (idx_t)wrap(k + 1, P.neta, P.periodic[2]) * plane, J);
+    if (!P.shear)
+        for (int c = PTT; c <= PEE; ++c) J[c] = 0.0;
+    if (!P.bulk) J[BPI] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) {
+        const idx_t o = (idx_t)c * SS + s;
+        const double t = ld(F.q, o) + P.dtau * J[c];
+        st(out, o, STAGE2 ? ld(qn, o) + t : t);
+    }
+}
+
+// Flux part of one Euler stage: for a 64 x 4 x KC block of cells, the KT
+// flux divergence D = -sum_d (H_{+1/2} - H_{-1/2}) / d_d of every
+// component (Sec. 3.1), then
+//   stage 1: out = out + dtau D;   stage 2: out = (out + dtau D) / 2,
+// which with sources_kernel gives q + dtau C[q] and (qn + q + dtau C[q]) / 2.
+// Face speeds come from face_speeds_kernel.  x faces: lane l computes the
+// face on the left of its cell and takes the right one from lane l+1 (lane
+// 63 computes its right face itself); eta faces: the top face of plane k is
+// the bottom face of plane k+1 (kept in LDS per thread); y faces: two per
+// cell.  Components are processed one at a time.
+template <bool STAGE2>
+__global__ __launch_bounds__(256) void flux_kernel(Phys P, FaceGeo G, const double *q,
+                                                   const double *vf, double *out)
+{
+    __shared__ double Hb[NQ][256];   // eta face below the current plane
     const int lane = threadIdx.x;
-    const int tid = threadIdx.y * BX + lane;
-    const int i = blockIdx.x * XOUT + lane;   // this lane's cell (x)
-    const int j = blockIdx.y * BY + threadIdx.y;
+    const int tid = threadIdx.y * 64 + lane;
+    const int i = blockIdx.x * 64 + lane;
+    const int j = blockIdx.y * 4 + threadIdx.y;
     const int k0 = blockIdx.z * KC;
     const idx_t plane = (idx_t)P.nx * P.ny;
     // lanes outside the grid compute on clamped cells; their results are not stored
     const int ic = i < P.nx ? i : P.nx - 1;
     const int jc = j < P.ny ? j : P.ny - 1;
     const int ifc = i <= P.nx ? i : P.nx;     // x face index of this lane
-    const bool out_ok = lane < XOUT && i < P.nx && j < P.ny;
+    const bool out_ok = i < P.nx && j < P.ny;
+    const bool right = lane == 63 && out_ok;  // this lane also computes its right x face
     const int xm2 = wrap(i - 2, P.nx, P.periodic[0]), xm1 = wrap(i - 1, P.nx, P.periodic[0]);
     const int x0 = wrap(i, P.nx, P.periodic[0]), xp1 = wrap(i + 1, P.nx, P.periodic[0]);
-    const int xcm = wrap(ic - 1, P.nx, P.periodic[0]), xcp = wrap(ic + 1, P.nx, P.periodic[0]);
+    const int xp2 = wrap(i + 2, P.nx, P.periodic[0]);
     const int ym2 = wrap(jc - 2, P.ny, P.periodic[1]), ym1 = wrap(jc - 1, P.ny, P.periodic[1]);
     const int yp1 = wrap(jc + 1, P.ny, P.periodic[1]), yp2 = wrap(jc + 2, P.ny, P.periodic[1]);
-    const double *vfx = F.vf + G.ox, *vfy = F.vf + G.oy, *vfe = F.vf + G.oe;
+    const double *vfx = vf + G.ox, *vfy = vf + G.oy, *vfe = vf + G.oe;
+    const double f = P.dtau;
+    int c_end = NQ;
+    if (!P.bulk) c_end = BPI;
+    if (!P.shear && !P.bulk) c_end = PTT;
 #pragma unroll 1
     for (int kk = 0; kk < KC; ++kk) {
         const int k = k0 + kk;
         if (k >= P.neta) break;    // uniform over the block
-        // component stride, opaque per iteration: keeps the compiler from hoisting
-        // the 60+ per-component stencil offsets out of the loop into registers
-        idx_t SS = (idx_t)P.stride;
-        asm volatile("" : "+s"(SS));
         const idx_t kp = (idx_t)k * plane;
         const idx_t rowc = kp + (idx_t)jc * P.nx;
         const idx_t s = rowc + ic;
-        const int zm1 = wrap(k - 1, P.neta, P.periodic[2]), zp1 = wrap(k + 1, P.neta, P.periodic[2]);
         const idx_t col = (idx_t)jc * P.nx + ic;
-        double acc[NQ];
-        cell_sources<CART>(P, E, tau, F, SS, s, rowc + xcm, rowc + xcp, kp + (idx_t)ym1 * P.nx + ic,
-                           kp + (idx_t)yp1 * P.nx + ic, col + (idx_t)zm1 * plane,
-                           col + (idx_t)zp1 * plane, acc);
-        phase_fence();
-        // x: face between x-1 and x (this lane); the right face comes from lane+1
-        {
-            const idx_t f = fidx_x(P.nx, P.ny, ifc, jc, k);
-            const double vm = ld(vfx, f), vp = ld(vfx + G.nfx, f);
-            const double a = fmax(fabs(vm), fabs(vp));
-#pragma unroll
-            for (int c = 0; c < NQ; ++c) {
-                const double H = face_H(F.q, (idx_t)c * SS, P.theta, rowc + xm2, rowc + xm1, rowc + x0,
-                                        rowc + xp1, vm, vp, a);
-                acc[c] += (H - __shfl_down(H, 1)) * P.inv_dx;
-            }
+        const int zm2 = wrap(k - 2, P.neta, P.periodic[2]), zm1 = wrap(k - 1, P.neta, P.periodic[2]);
+        const int zp1 = wrap(k + 1, P.neta, P.periodic[2]), zp2 = wrap(k + 2, P.neta, P.periodic[2]);
+        // face speeds: x (left face, and the right one for lane 63), y (both), eta (top)
+        const idx_t fx = fidx_x(P.nx, P.ny, ifc, jc, k);
+        const double vmx = ld(vfx, fx), vpx = ld(vfx + G.nfx, fx);
+        const double ax = fmax(fabs(vmx), fabs(vpx));
+        double vmr = 0.0, vpr = 0.0;
+        if (right) {
+            vmr = ld(vfx, fx + 1);
+            vpr = ld(vfx + G.nfx, fx + 1);
         }
-        phase_fence();
-        // y: both faces of the cell
-        {
-            const idx_t base = kp + ic;
-            const idx_t r0 = base + (idx_t)ym2 * P.nx, r1 = base + (idx_t)ym1 * P.nx;
-            const idx_t r2 = base + (idx_t)jc * P.nx, r3 = base + (idx_t)yp1 * P.nx;
-            const idx_t r4 = base + (idx_t)yp2 * P.nx;
-            const idx_t f0 = fidx_y(P.nx, P.ny, ic, jc, k), f1 = fidx_y(P.nx, P.ny, ic, jc + 1, k);
-            const double vm0 = ld(vfy, f0), vp0 = ld(vfy + G.nfy, f0);
-            const double vm1 = ld(vfy, f1), vp1 = ld(vfy + G.nfy, f1);
-            const double a0 = fmax(fabs(vm0), fabs(vp0)), a1 = fmax(fabs(vm1), fabs(vp1));
-#pragma unroll
-            for (int c = 0; c < NQ; ++c)
-                acc[c] += (face_H(F.q, (idx_t)c * SS, P.theta, r0, r1, r2, r3, vm0, vp0, a0)
-                         - face_H(F.q, (idx_t)c * SS, P.theta, r1, r2, r3, r4, vm1, vp1, a1)) * P.inv_dy;
+        const double axr = fmax(fabs(vmr), fabs(vpr));
+        const idx_t fy0 = fidx_y(P.nx, P.ny, ic, jc, k), fy1 = fidx_y(P.nx, P.ny, ic, jc + 1, k);
+        const double vmy0 = ld(vfy, fy0), vpy0 = ld(vfy + G.nfy, fy0);
+        const double vmy1 = ld(vfy, fy1), vpy1 = ld(vfy + G.nfy, fy1);
+        const double ay0 = fmax(fabs(vmy0), fabs(vpy0)), ay1 = fmax(fabs(vmy1), fabs(vpy1));
+        const idx_t fe1 = fidx_e(P.nx, P.ny, ic, jc, k + 1);
+        const double vme = ld(vfe, fe1), vpe = ld(vfe + G.nfe, fe1);
+        const double ae = fmax(fabs(vme), fabs(vpe));
+        double vmb = 0.0, vpb = 0.0;
+        if (kk == 0) {
+            const idx_t fe0 = fidx_e(P.nx, P.ny, ic, jc, k);
+            vmb = ld(vfe, fe0);
+            vpb = ld(vfe + G.nfe, fe0);
         }
-        phase_fence();
-        // eta: bottom face (computed at the first plane, carried afterwards) and top face
-        {
-            const int zp2 = wrap(k + 2, P.neta, P.periodic[2]);
-            if (kk == 0) {
-                const int zm2 = wrap(k - 2, P.neta, P.periodic[2]);
-                const idx_t f = fidx_e(P.nx, P.ny, ic, jc, k);
-                const double vm = ld(vfe, f), vp = ld(vfe + G.nfe, f);
-                const double a = fmax(fabs(vm), fabs(vp));
-#pragma unroll
-                for (int c = 0; c < NQ; ++c)
-                    Hb[c][tid] = face_H(F.q, (idx_t)c * SS, P.theta, col + (idx_t)zm2 * plane,
-                                        col + (idx_t)zm1 * plane, col + kp, col + (idx_t)zp1 * plane,
-                                        vm, vp, a);
-            }
-            const idx_t f = fidx_e(P.nx, P.ny, ic, jc, k + 1);
-            const double vm = ld(vfe, f), vp = ld(vfe + G.nfe, f);
-            const double a = fmax(fabs(vm), fabs(vp));
-#pragma unroll
-            for (int c = 0; c < NQ; ++c) {
-                const double H = face_H(F.q, (idx_t)c * SS, P.theta, col + (idx_t)zm1 * plane, col + kp,
-                                        col + (idx_t)zp1 * plane, col + (idx_t)zp2 * plane, vm, vp, a);
-                acc[c] += (Hb[c][tid] - H) * P.inv_deta;
-                Hb[c][tid] = H;
-            }
-        }
-        if (!P.shear)
-            for (int c = PTT; c <= PEE; ++c) acc[c] = 0.0;
-        if (!P.bulk) acc[BPI] = 0.0;
-        if (out_ok) {
-#pragma unroll
-            for (int c = 0; c < NQ; ++c) {
-                const double qs = ld(F.q, (idx_t)(c) * SS + s) + P.dtau * acc[c];
-                st(out, (idx_t)(c) * SS + s, STAGE2 ? 0.5 * (ld(qn, (idx_t)(c) * SS + s) + qs) : qs);
+        const double ab = fmax(fabs(vmb), fabs(vpb));
+        const idx_t rx = kp + (idx_t)jc * P.nx;
+        const idx_t by = kp + ic;
+        const idx_t r0 = by + (idx_t)ym2 * P.nx, r1 = by + (idx_t)ym1 * P.nx;
+        const idx_t r3 = by + (idx_t)yp1 * P.nx, r4 = by + (idx_t)yp2 * P.nx;
+        const idx_t e0 = col + (idx_t)zm2 * plane, e1 = col + (idx_t)zm1 * plane;
+        const idx_t e3 = col + (idx_t)zp1 * plane, e4 = col + (idx_t)zp2 * plane;
+#pragma unroll 1
+        for (int c = 0; c < c_end; ++c) {
+            if (!P.shear && c == PTT) c = BPI;   // only T^{tau mu} and Pi evolve
+            const idx_t co = (idx_t)c * P.stride;
+            // x
+            const double Hx = face_H(q, co, P.theta, rx + xm2, rx + xm1, rx + x0, rx + xp1, vmx, vpx, ax);
+            double Hr = __shfl_down(Hx, 1);
+            if (right) Hr = face_H(q, co, P.theta, rx + xm1, rx + x0, rx + xp1, rx + xp2, vmr, vpr, axr);
+            double D = (Hx - Hr) * P.inv_dx;
+            // y
+            D += (face_H(q, co, P.theta, r0, r1, s, r3, vmy0, vpy0, ay0)
+                - face_H(q, co, P.theta, r1, s, r3, r4, vmy1, vpy1, ay1)) * P.inv_dy;
+            // eta
+            const double Hb0 = kk == 0 ? face_H(q, co, P.theta, e0, e1, s, e3, vmb, vpb, ab) : Hb[c][tid];
+            const double Ht = face_H(q, co, P.theta, e1, s, e3, e4, vme, vpe, ae);
+            Hb[c][tid] = Ht;
+            D += (Hb0 - Ht) * P.inv_deta;
+            if (out_ok) {
+                const double t = ld(out, co + s) + f * D;
+                st(out, co + s, STAGE2 ? 0.5 * t : t);
             }
         }
     }
@@ -737,7 +755,7 @@ static long long face_waves(const kt_params *p)
 
 static long long stage_waves(const kt_params *p)
 {
-    return (long long)((p->nx + XOUT - 1) / XOUT) * ((p->ny + BY - 1) / BY) * ((p->neta + KC - 1) / KC) * BY;
+    return (long long)((p->nx + 63) / 64) * ((p->ny + 3) / 4) * p->neta * 4;
 }
 
 static long long recover_waves(const kt_params *p)
@@ -824,11 +842,6 @@ static hipError_t launch(K kernel, dim3 g, dim3 b, hipStream_t st, A... args)
     return hipGetLastError();
 }
 
-static dim3 cells_grid(const Phys &P)
-{
-    return dim3((P.nx + XOUT - 1) / XOUT, (P.ny + BY - 1) / BY, (P.neta + KC - 1) / KC);
-}
-
 static dim3 linear_grid(long long n) { return dim3((unsigned)((n + 255) / 256)); }
 
 static kt_status run_recover(kt_ctx *c, double tau, double *q, double *u_out, int regulate,
@@ -864,21 +877,27 @@ static kt_status run_faces(kt_ctx *c, double tau, const double *q)
 static kt_status run_stage(kt_ctx *c, bool stage2, double tau, const Fields &F, double *out)
 {
     const bool cart = c->prm.coords == KT_CARTESIAN;
-    const dim3 g = cells_grid(c->P), b(BX, BY);
-    hipError_t e = prof_mark(c, 0, true);
+    const Phys &P = c->P;
+    const dim3 b(64, 4);
+    const dim3 gs((P.nx + 63) / 64, (P.ny + 3) / 4, P.neta);
+    const double *qn = stage2 ? (const double *)c->q : nullptr;
+    hipError_t e = prof_mark(c, 3, true);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
     if (cart)
-        e = stage2 ? launch(stage_kernel<true, true>, g, b, c->stream, c->P, c->E, c->G, tau, F,
-                            (const double *)c->q, out)
-                   : launch(stage_kernel<true, false>, g, b, c->stream, c->P, c->E, c->G, tau, F,
-                            (const double *)nullptr, out);
+        e = stage2 ? launch(sources_kernel<true, true>, gs, b, c->stream, P, c->E, tau, F, qn, out)
+                   : launch(sources_kernel<true, false>, gs, b, c->stream, P, c->E, tau, F, qn, out);
     else
-        e = stage2 ? launch(stage_kernel<false, true>, g, b, c->stream, c->P, c->E, c->G, tau, F,
-                            (const double *)c->q, out)
-                   : launch(stage_kernel<false, false>, g, b, c->stream, c->P, c->E, c->G, tau, F,
-                            (const double *)nullptr, out);
+        e = stage2 ? launch(sources_kernel<false, true>, gs, b, c->stream, P, c->E, tau, F, qn, out)
+                   : launch(sources_kernel<false, false>, gs, b, c->stream, P, c->E, tau, F, qn, out);
+    if (e == hipSuccess) e = prof_mark(c, 3, false);
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "sources kernel: %s", hipGetErrorString(e));
+    const dim3 gf((P.nx + 63) / 64, (P.ny + 3) / 4, (P.neta + KC - 1) / KC);
+    e = prof_mark(c, 0, true);
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
+    e = stage2 ? launch(flux_kernel<true>, gf, b, c->stream, P, c->G, F.q, F.vf, out)
+               : launch(flux_kernel<false>, gf, b, c->stream, P, c->G, F.q, F.vf, out);
     if (e == hipSuccess) e = prof_mark(c, 0, false);
-    if (e != hipSuccess) return fail(c, KT_E_HIP, "stage kernel: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "flux kernel: %s", hipGetErrorString(e));
     return KT_OK;
 }
 

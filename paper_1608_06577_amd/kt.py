@@ -86,6 +86,10 @@ EXPORTS = ("kt_workspace_bytes", "kt_init", "kt_step", "kt_recover", "kt_observa
            "kt_status_string")
 
 
+# kernel classes of kt_profile (include/kt.h)
+PROFILE_CLASSES = ("flux", "recover", "faces", "sources")
+
+
 def lib():
     """Load libkt.so; raises if the library has not been built."""
     global _lib
@@ -277,9 +281,11 @@ class Solver:
         """Summed kernel times (ms) and launch counts per class since the last read."""
         p = KtProfile()
         _check(lib().kt_profile_read(self.ctx, C.byref(p)), self.ctx)
-        return dict(stage_ms=p.ms[0], stage_launches=p.launches[0],
-                    recover_ms=p.ms[1], recover_launches=p.launches[1],
-                    faces_ms=p.ms[2], faces_launches=p.launches[2])
+        out = {}
+        for k, name in enumerate(PROFILE_CLASSES):
+            out[name + "_ms"] = p.ms[k]
+            out[name + "_launches"] = p.launches[k]
+        return out
 
     def close(self):
         if getattr(self, "ctx", None):
