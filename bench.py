@@ -143,8 +143,10 @@ def main():
                    "paper_context_ms_per_step": {"gtx980ti_fp32_128cube_table": 244.45,
                                                  "gtx980ti_program_summary": 38400.0}},
         "roofline": roof,
-        "diagnostics": {k: obs[k] for k in ("tau", "n_nan", "n_floor", "n_clamp", "n_fallback",
-                                            "e_max", "cfl")},
+        "diagnostics": dict({k: obs[k] for k in ("tau", "n_nan", "n_floor", "n_clamp", "n_fallback",
+                                                 "n_fallback_faces", "e_max", "cfl")},
+                            newton_iters_per_cell=obs["newton_iters_cells"] / max(1, obs["n_recover_cells"]),
+                            newton_iters_per_face_state=obs["newton_iters_faces"] / max(1, obs["n_recover_faces"])),
     }
     solver.close()
     if not args.no_cpu:

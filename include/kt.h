@@ -140,7 +140,8 @@ typedef struct {
     /* recovery counters accumulated since kt_init */
     int64_t newton_iters_cells, n_recover_cells;
     int64_t newton_iters_faces, n_recover_faces;
-    int64_t n_floor, n_clamp, n_fallback;
+    int64_t n_floor, n_clamp, n_fallback;   /* cells */
+    int64_t n_fallback_faces;               /* face states solved by bisection */
 } kt_obs;
 
 /* Device workspace needed for p and eos (bytes, multiple of 256), 0 if the

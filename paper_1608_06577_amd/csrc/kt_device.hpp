@@ -27,7 +27,7 @@ enum : int { F_FLOOR = 1, F_CLAMP = 2, F_FALLBACK = 4 };
 // counters, one slot row per wavefront
 enum : int {
     C_ITERS_CELLS = 0, C_REC_CELLS, C_ITERS_FACES, C_REC_FACES, C_FLOOR, C_CLAMP, C_FALLBACK,
-    C_COUNT
+    C_FALLBACK_FACES, C_COUNT
 };
 
 // EOS node layout: p/e, T/e^{1/4}, c_s^2, 1/e_i
@@ -197,12 +197,14 @@ __device__ __forceinline__ int recover(const Phys &P, const Eos &E, double tau, 
         int n = 0;
         double cs2;
         while (n < P.newton_max) {
+            // f = x - E + M^2/A and f' = 1 - M^2 c_s^2 / A^2 with A = E + p(x) + Pi > 0,
+            // scaled by A and A^2 so that the step f/f' takes one division
             eos_pc(E, x, p, cs2);
             const double A = EE + p + Pi;
-            const double f = x - EE + M2 / A;
-            const double df = 1.0 - M2 * cs2 / (A * A);
-            const bool conv = fabs(f) <= P.newton_tol * EE;
-            x = fmin(fmax(x - f / df, ef), EE);
+            const double fA = fma(x - EE, A, M2);
+            const double dfA2 = fma(-M2, cs2, A * A);
+            const bool conv = fabs(fA) <= P.newton_tol * EE * A;
+            x = fmin(fmax(x - fA * A / dfA2, ef), EE);
             ++n;
             if (conv) {
                 done = true;
@@ -304,12 +306,14 @@ __device__ __forceinline__ double slope(double qm, double q0, double qp, double 
 // with I_pi = I1 + (4/3) I2 - I3 + (tau_pipi/tau_pi) I4 - (6/5) Pi sigma,
 //      I_Pi = (2/3) Pi theta - (8/5)(1/3 - c_s^2) pi:sigma  (Sec. 2.2, 2.4),
 // G^{mu nu} = u^a Gamma^mu_{ab} pi^{b nu} + (mu <-> nu).
-// C[a][m] = partial_a u^m on entry (a: tau, x, y, eta); q holds pi and Pi.
-template <bool CART>
-__device__ __forceinline__ void relaxation_sources(const Phys &P, double tau, const double q[NQ],
-                                                   double e, double p0, double cs2, double T,
-                                                   const double u[4], double C[4][4],
-                                                   double divv, double J[NQ])
+// C[a][m] = partial_a u^m on entry (a: tau, x, y, eta); pv holds the ten pi
+// components in the order of q (pi^{tau tau} first).  Each result is handed
+// to emit(c, q_c, J_c) as soon as it is known (c: index in q).
+template <bool CART, typename Emit>
+__device__ __forceinline__ void relaxation_sources(const Phys &P, double tau, const double pv[10],
+                                                   double Pi, double e, double p0, double cs2,
+                                                   double T, const double u[4], double C[4][4],
+                                                   double divv, Emit &&emit)
 {
     const double g33 = CART ? 1.0 : tau * tau;
     const double inv_tau = 1.0 / tau;
@@ -358,8 +362,7 @@ __device__ __forceinline__ void relaxation_sources(const Phys &P, double tau, co
         const int k = a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
         return m < n ? om[k] : -om[k];
     };
-    auto PI = [&](int m, int n) -> double { return q[pi_index(m, n)]; };
-    const double Pi = P.bulk ? q[BPI] : 0.0;
+    auto PI = [&](int m, int n) -> double { return pv[pi_index(m, n) - PTT]; };
     double pis = 0.0;   // pi^{mu nu} sigma_{mu nu}
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -402,7 +405,7 @@ __device__ __forceinline__ void relaxation_sources(const Phys &P, double tau, co
                     G = hm + hn;
                 }
                 const double rhs = 2.0 * eta_tpi * s - pmn * inv_tpi - Ipi - G;
-                J[pi_index(m, n)] = rhs * inv_ut + pmn * divv;
+                emit(pi_index(m, n), pmn, rhs * inv_ut + pmn * divv);
             }
     }
     if (P.bulk) {
@@ -410,7 +413,7 @@ __device__ __forceinline__ void relaxation_sources(const Phys &P, double tau, co
         const double inv_tPi = 15.0 * d * T / P.zeta_coef;
         const double zeta_tPi = 15.0 * d * d * (e + p0);
         const double IPi = (2.0 / 3.0) * Pi * th - 1.6 * d * pis;
-        J[BPI] = (-zeta_tPi * th - Pi * inv_tPi - IPi) * inv_ut + Pi * divv;
+        emit(BPI, Pi, (-zeta_tPi * th - Pi * inv_tPi - IPi) * inv_ut + Pi * divv);
     }
 }
 

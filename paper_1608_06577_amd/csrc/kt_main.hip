@@ -113,86 +113,96 @@ __device__ __forceinline__ double face_H(const double *q, idx_t co, double theta
     return 0.5 * (vp * qp + vm * qm) - 0.5 * a * (qp - qm);
 }
 
-// inversion of the two reconstructed states of one face; returns v^-, v^+ along d
+// Face speeds (Sec. 3.1, last paragraph): every face of the grid has two
+// reconstructed states, q^- = q_L + slope_L/2 from the cell on its left and
+// q^+ = q_R - slope_R/2 from the cell on its right; each is inverted like a
+// cell (warm start: the e of the cell it was extrapolated from) and the
+// velocity component normal to the face is stored.
+// One thread per face and side.  The launch is cut into six segments of
+// whole blocks, (x, y, eta) x (minus, plus); a thread's index within its
+// segment is the face index of fidx_x / fidx_y / fidx_e.
+struct FaceLaunch {
+    unsigned first_block[7];   // first block of each segment; [6] = total
+};
+
 template <bool CART>
-__device__ __forceinline__ void face_invert(const Phys &P, const Eos &E, double tau,
-                                            const double *__restrict__ q, const double *__restrict__ e,
-                                            idx_t s0, idx_t s1, idx_t s2, idx_t s3,
-                                            int d, double &vm, double &vp, int &iters)
+__global__ __launch_bounds__(256) void face_speeds_kernel(Phys P, Eos E, FaceGeo G, FaceLaunch L,
+                                                          double tau, const double *q,
+                                                          const double *e, double *vf,
+                                                          unsigned long long *slots)
 {
-    const idx_t SS = (idx_t)P.stride;
-    double m[9], p[9];
+    const unsigned b = blockIdx.x;
+    int seg = 0;
 #pragma unroll
-    for (int n = 0; n < 9; ++n) {
-        const int c = n < 8 ? n : BPI;
-        const idx_t co = (idx_t)c * SS;
-        const double a0 = ld(q, co + s0), a1 = ld(q, co + s1), a2 = ld(q, co + s2), a3 = ld(q, co + s3);
-        m[n] = a1 + 0.5 * slope(a0, a1, a2, P.theta);
-        p[n] = a2 - 0.5 * slope(a1, a2, a3, P.theta);
+    for (int t = 1; t < 6; ++t) seg += b >= L.first_block[t] ? 1 : 0;
+    const int d = seg >> 1, side = seg & 1;     // side 0: q^-, side 1: q^+
+    const long long wave = (long long)b * 4 + (threadIdx.x >> 6);
+    const idx_t t = (idx_t)(b - L.first_block[seg]) * 256 + threadIdx.x;
+    const long long nf = d == 0 ? G.nfx : (d == 1 ? G.nfy : G.nfe);
+    int it = 0, fl = 0;
+    const bool valid = (long long)t < nf;
+    if (valid) {
+        // (i, j, k) of the face, the line of cells through it along d
+        idx_t base, step;
+        int pos, n, per;
+        if (d == 0) {
+            const idx_t n1 = (idx_t)P.nx + 1, r = t / n1;
+            pos = (int)(t - r * n1);
+            base = r * (idx_t)P.nx;                    // row (j, k)
+            step = 1;
+            n = P.nx;
+            per = P.periodic[0];
+        } else if (d == 1) {
+            const idx_t r = t / (idx_t)P.nx, k = r / (idx_t)(P.ny + 1);
+            pos = (int)(r - k * (idx_t)(P.ny + 1));
+            base = k * (idx_t)P.nx * P.ny + (t - r * (idx_t)P.nx);
+            step = (idx_t)P.nx;
+            n = P.ny;
+            per = P.periodic[1];
+        } else {
+            const idx_t plane = (idx_t)P.nx * P.ny, k = t / plane;
+            pos = (int)k;
+            base = t - k * plane;
+            step = plane;
+            n = P.neta;
+            per = P.periodic[2];
+        }
+        // face pos lies between cells pos-1 and pos; the state comes from cell c
+        const int c = pos - 1 + side;
+        const idx_t sm = base + (idx_t)wrap(c - 1, n, per) * step;
+        const idx_t s0 = base + (idx_t)wrap(c, n, per) * step;
+        const idx_t sp = base + (idx_t)wrap(c + 1, n, per) * step;
+        const double h = side ? -0.5 : 0.5;
+        const idx_t SS = (idx_t)P.stride;
+        double m[9];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            const idx_t co = (idx_t)(r < 8 ? r : BPI) * SS;
+            const double a0 = ld(q, co + sm), a1 = ld(q, co + s0), a2 = ld(q, co + sp);
+            m[r] = a1 + h * slope(a0, a1, a2, P.theta);
+        }
+        double ee, pe, u[4];
+        fl = recover<CART>(P, E, tau, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7],
+                           P.bulk ? m[8] : 0.0, ld(e, s0), ee, pe, u, it);
+        const long long off = (d == 0 ? G.ox : (d == 1 ? G.oy : G.oe)) + (side ? nf : 0);
+        st(vf + off, t, u[d + 1] / u[0]);
     }
-    double ee, pe, u[4];
-    int it;
-    recover<CART>(P, E, tau, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], P.bulk ? m[8] : 0.0,
-                  ld(e, s1), ee, pe, u, it);
-    vm = u[d + 1] / u[0];
-    iters += it;
-    recover<CART>(P, E, tau, p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7], P.bulk ? p[8] : 0.0,
-                  ld(e, s2), ee, pe, u, it);
-    vp = u[d + 1] / u[0];
-    iters += it;
+    slot_add(slots, wave, C_ITERS_FACES, it);
+    slot_add(slots, wave, C_REC_FACES, valid ? 1 : 0);
+    slot_add(slots, wave, C_FALLBACK_FACES, (fl & F_FALLBACK) ? 1 : 0);
 }
 
-// face speeds of every face of the grid at tau (thread per (i,j,k) in
-// [0,nx] x [0,ny] x [0,neta]: the x face at i, the y face at j, the eta face at k)
-template <bool CART>
-__global__ __launch_bounds__(256) void face_speeds_kernel(Phys P, Eos E, FaceGeo G, double tau,
-                                                          const double *q, const double *e,
-                                                          double *vf, unsigned long long *slots)
+static FaceLaunch face_launch(const FaceGeo &G)
 {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y * 4 + threadIdx.y;
-    const int k = blockIdx.z;
-    const long long wave = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x * 4
-                         + (long long)blockIdx.x * 4 + threadIdx.y;
-    const idx_t plane = (idx_t)P.nx * P.ny;
-    int iters = 0, nf = 0;
-    if (i <= P.nx && j < P.ny && k < P.neta) {   // x face i (between cells i-1 and i) of row (j, k)
-        const idx_t r = (idx_t)k * plane + (idx_t)j * P.nx;
-        double vm, vp;
-        face_invert<CART>(P, E, tau, q, e, r + wrap(i - 2, P.nx, P.periodic[0]),
-                          r + wrap(i - 1, P.nx, P.periodic[0]), r + wrap(i, P.nx, P.periodic[0]),
-                          r + wrap(i + 1, P.nx, P.periodic[0]), 0, vm, vp, iters);
-        const idx_t f = fidx_x(P.nx, P.ny, i, j, k);
-        st(vf + G.ox, f, vm);
-        st(vf + G.ox + G.nfx, f, vp);
-        nf += 2;
+    FaceLaunch L;
+    const long long nf[3] = {G.nfx, G.nfy, G.nfe};
+    unsigned acc = 0;
+    for (int s = 0; s < 6; ++s) {
+        L.first_block[s] = acc;
+        acc += (unsigned)((nf[s >> 1] + 255) / 256);
     }
-    if (i < P.nx && j <= P.ny && k < P.neta) {
-        const idx_t b = (idx_t)k * plane + i;
-        double vm, vp;
-        face_invert<CART>(P, E, tau, q, e, b + (idx_t)wrap(j - 2, P.ny, P.periodic[1]) * P.nx,
-                          b + (idx_t)wrap(j - 1, P.ny, P.periodic[1]) * P.nx,
-                          b + (idx_t)wrap(j, P.ny, P.periodic[1]) * P.nx,
-                          b + (idx_t)wrap(j + 1, P.ny, P.periodic[1]) * P.nx, 1, vm, vp, iters);
-        const idx_t f = fidx_y(P.nx, P.ny, i, j, k);
-        st(vf + G.oy, f, vm);
-        st(vf + G.oy + G.nfy, f, vp);
-        nf += 2;
-    }
-    if (i < P.nx && j < P.ny && k <= P.neta) {
-        const idx_t b = (idx_t)j * P.nx + i;
-        double vm, vp;
-        face_invert<CART>(P, E, tau, q, e, b + (idx_t)wrap(k - 2, P.neta, P.periodic[2]) * plane,
-                          b + (idx_t)wrap(k - 1, P.neta, P.periodic[2]) * plane,
-                          b + (idx_t)wrap(k, P.neta, P.periodic[2]) * plane,
-                          b + (idx_t)wrap(k + 1, P.neta, P.periodic[2]) * plane, 2, vm, vp, iters);
-        const idx_t f = fidx_e(P.nx, P.ny, i, j, k);
-        st(vf + G.oe, f, vm);
-        st(vf + G.oe + G.nfe, f, vp);
-        nf += 2;
-    }
-    slot_add(slots, wave, C_ITERS_FACES, iters);
-    slot_add(slots, wave, C_REC_FACES, nf);
+    L.first_block[6] = acc;
+    return L;
 }
 
 // A^{i nu} = T^{i nu} - v^i T^{tau nu} of one cell for axis i = d+1 (Eqs. Ttt-Tij):
@@ -217,71 +227,12 @@ __device__ __forceinline__ void nonadvective_row(const Phys &P, double tau, cons
     }
 }
 
-// sources J of one cell (App. B): S_c + G_c for T^{tau nu}, relaxation terms for pi and Pi
-template <bool CART>
-__device__ __forceinline__ void cell_sources(const Phys &P, const Eos &E, double tau, const Fields &F,
-                                             idx_t SS, idx_t s, idx_t sxm, idx_t sxp, idx_t sym,
-                                             idx_t syp, idx_t szm, idx_t szp, double J[NQ])
-{
-    double q[NQ];
-#pragma unroll
-    for (int c = 0; c < NQ; ++c) q[c] = ld(F.q, (idx_t)(c) * SS + s);
-    if (!P.shear)
-        for (int c = PTT; c <= PEE; ++c) q[c] = 0.0;
-    const double invh[3] = {P.inv_dx, P.inv_dy, P.inv_deta};
-    double u[4], C[4][4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        u[m] = ld(F.u, (idx_t)(m) * SS + s);
-        C[0][m] = (u[m] - ld(F.up, (idx_t)(m) * SS + s)) * P.inv_dtau;
-    }
-    // central differences (Sec. 3.1): d_i u^m, d_i v^i, S_c = -d_i A^{i nu}
-    double divv = 0.0, Sc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const idx_t sp = d == 0 ? sxp : (d == 1 ? syp : szp);
-        const idx_t sm = d == 0 ? sxm : (d == 1 ? sym : szm);
-        const double hh = 0.5 * invh[d];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) C[d + 1][m] = (ld(F.u, (idx_t)(m) * SS + sp) - ld(F.u, (idx_t)(m) * SS + sm)) * hh;
-        divv += (ld(F.u, (idx_t)((d + 1)) * SS + sp) / ld(F.u, sp) - ld(F.u, (idx_t)((d + 1)) * SS + sm) / ld(F.u, sm)) * hh;
-        double Ap[4], Am[4];
-        nonadvective_row<CART>(P, tau, F, SS, sp, d, Ap);
-        nonadvective_row<CART>(P, tau, F, SS, sm, d, Am);
-#pragma unroll
-        for (int n = 0; n < 4; ++n) Sc[n] -= (Ap[n] - Am[n]) * hh;
-    }
-    const double e = ld(F.e, s);
-    const double p0 = ld(F.p, s);
-    const double Pc = p0 + (P.bulk ? q[BPI] : 0.0);
-    // geometric source of the conservation law (App. B): G^tau = -(T^tt + tau^2 T^ee)/tau,
-    // G^x = -T^tx/tau, G^y = -T^ty/tau, G^eta = -3 T^te/tau, with
-    // tau^2 T^ee = tau^2 v^eta (T^te - pi^te) + P + tau^2 pi^ee.
-    if (!CART) {
-        const double inv_tau = 1.0 / tau, t2 = tau * tau;
-        const double ve = u[3] / u[0];
-        const double t2Tee = t2 * (ve * (q[TE] - q[PTE]) + q[PEE]) + Pc;
-        J[TT] = Sc[0] - (q[TT] + t2Tee) * inv_tau;
-        J[TX] = Sc[1] - q[TX] * inv_tau;
-        J[TY] = Sc[2] - q[TY] * inv_tau;
-        J[TE] = Sc[3] - 3.0 * q[TE] * inv_tau;
-    } else {
-#pragma unroll
-        for (int n = 0; n < 4; ++n) J[n] = Sc[n];
-    }
-#pragma unroll
-    for (int c = PTT; c < NQ; ++c) J[c] = 0.0;
-    if (P.shear || P.bulk) {
-        double pe, cs2, T;
-        eos_full(E, e, pe, cs2, T);
-        relaxation_sources<CART>(P, tau, q, e, p0, cs2, T, u, C, divv, J);
-    }
-}
-
 // Sources part of one Euler stage (Sec. 3.1, Eq. semiDiscreteKT, and
 // App. B), one thread per cell:
-//   stage 1: out = q + dtau J;   stage 2: out = qn + q + dtau J.
-// flux_kernel then adds the flux divergence and completes the stage.
+//   stage 1: out = q + dtau J;   stage 2: out = qn + q + dtau J,
+// J = S_c + G_c for T^{tau nu} and the relaxation terms for pi and Pi.
+// flux_kernel then adds the flux divergence and completes the stage.  Each
+// component is written as soon as its J is known.
 template <bool CART, bool STAGE2>
 __global__ __launch_bounds__(256) void sources_kernel(Phys P, Eos E, double tau, Fields F,
                                                       const double *qn, double *out)
@@ -296,21 +247,79 @@ __global__ __launch_bounds__(256) void sources_kernel(Phys P, Eos E, double tau,
     const idx_t rowc = kp + (idx_t)j * P.nx;
     const idx_t s = rowc + i;
     const idx_t col = (idx_t)j * P.nx + i;
-    double J[NQ];
-    cell_sources<CART>(P, E, tau, F, SS, s, rowc + wrap(i - 1, P.nx, P.periodic[0]),
-                       rowc + wrap(i + 1, P.nx, P.periodic[0]),
-                       kp + (idx_t)wrap(j - 1, P.ny, P.periodic[1]) * P.nx + i,
-                       kp + (idx_t)wrap(j + 1, P.ny, P.periodic[1]) * P.nx + i,
-                       col + (idx_t)wrap(k - 1, P.neta, P.periodic[2]) * plane,
-                       col + (idx_t)wrap(k + 1, P.neta, P.periodic[2]) * plane, J);
-    if (!P.shear)
-        for (int c = PTT; c <= PEE; ++c) J[c] = 0.0;
-    if (!P.bulk) J[BPI] = 0.0;
-#pragma unroll
-    for (int c = 0; c < NQ; ++c) {
+    const idx_t nb[3][2] = {
+        {rowc + wrap(i - 1, P.nx, P.periodic[0]), rowc + wrap(i + 1, P.nx, P.periodic[0])},
+        {kp + (idx_t)wrap(j - 1, P.ny, P.periodic[1]) * P.nx + i,
+         kp + (idx_t)wrap(j + 1, P.ny, P.periodic[1]) * P.nx + i},
+        {col + (idx_t)wrap(k - 1, P.neta, P.periodic[2]) * plane,
+         col + (idx_t)wrap(k + 1, P.neta, P.periodic[2]) * plane}};
+    const double dt = P.dtau;
+    auto emit = [&](int c, double qc, double Jc) {
         const idx_t o = (idx_t)c * SS + s;
-        const double t = ld(F.q, o) + P.dtau * J[c];
+        const double t = qc + dt * Jc;
         st(out, o, STAGE2 ? ld(qn, o) + t : t);
+    };
+    const double invh[3] = {P.inv_dx, P.inv_dy, P.inv_deta};
+    double u[4], C[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        u[m] = ld(F.u, (idx_t)m * SS + s);
+        C[0][m] = (u[m] - ld(F.up, (idx_t)m * SS + s)) * P.inv_dtau;
+    }
+    // central differences (Sec. 3.1): d_i u^m, d_i v^i, S_c = -d_i A^{i nu}
+    double divv = 0.0, Sc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const idx_t sm = nb[d][0], sp = nb[d][1];
+        const double hh = 0.5 * invh[d];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            C[d + 1][m] = (ld(F.u, (idx_t)m * SS + sp) - ld(F.u, (idx_t)m * SS + sm)) * hh;
+        divv += (ld(F.u, (idx_t)(d + 1) * SS + sp) / ld(F.u, sp)
+               - ld(F.u, (idx_t)(d + 1) * SS + sm) / ld(F.u, sm)) * hh;
+        double Ap[4], Am[4];
+        nonadvective_row<CART>(P, tau, F, SS, sp, d, Ap);
+        nonadvective_row<CART>(P, tau, F, SS, sm, d, Am);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) Sc[n] -= (Ap[n] - Am[n]) * hh;
+    }
+    const double e = ld(F.e, s);
+    const double p0 = ld(F.p, s);
+    const double Pim = ld(F.q, (idx_t)BPI * SS + s);
+    const double Pi = P.bulk ? Pim : 0.0;
+    const double Pc = p0 + Pi;
+    double pv[10];
+#pragma unroll
+    for (int c = 0; c < 10; ++c) pv[c] = ld(F.q, (idx_t)(PTT + c) * SS + s);
+    // conservation law: geometric source (App. B) G^tau = -(T^tt + tau^2 T^ee)/tau,
+    // G^x = -T^tx/tau, G^y = -T^ty/tau, G^eta = -3 T^te/tau, with
+    // tau^2 T^ee = tau^2 v^eta (T^te - pi^te) + P + tau^2 pi^ee.
+    {
+        double qt[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) qt[n] = ld(F.q, (idx_t)n * SS + s);
+        if (!CART) {
+            const double inv_tau = 1.0 / tau, t2 = tau * tau;
+            const double ve = u[3] / u[0];
+            const double pte = P.shear ? pv[PTE - PTT] : 0.0, pee = P.shear ? pv[PEE - PTT] : 0.0;
+            const double t2Tee = t2 * (ve * (qt[TE] - pte) + pee) + Pc;
+            emit(TT, qt[TT], Sc[0] - (qt[TT] + t2Tee) * inv_tau);
+            emit(TX, qt[TX], Sc[1] - qt[TX] * inv_tau);
+            emit(TY, qt[TY], Sc[2] - qt[TY] * inv_tau);
+            emit(TE, qt[TE], Sc[3] - 3.0 * qt[TE] * inv_tau);
+        } else {
+#pragma unroll
+            for (int n = 0; n < 4; ++n) emit(n, qt[n], Sc[n]);
+        }
+    }
+    // relaxation equations; components that do not evolve keep their value
+    if (!P.shear)
+        for (int c = 0; c < 10; ++c) emit(PTT + c, pv[c], 0.0);
+    if (!P.bulk) emit(BPI, Pim, 0.0);
+    if (P.shear || P.bulk) {
+        double pe, cs2, T;
+        eos_full(E, e, pe, cs2, T);
+        relaxation_sources<CART>(P, tau, pv, Pi, e, p0, cs2, T, u, C, divv, emit);
     }
 }
 
@@ -750,7 +759,7 @@ static FaceGeo face_geo(const kt_params *p)
 
 static long long face_waves(const kt_params *p)
 {
-    return (long long)((p->nx + 1 + 63) / 64) * ((p->ny + 1 + 3) / 4) * (p->neta + 1) * 4;
+    return (long long)face_launch(face_geo(p)).first_block[6] * 4;
 }
 
 static long long stage_waves(const kt_params *p)
@@ -864,10 +873,11 @@ static kt_status run_faces(kt_ctx *c, double tau, const double *q)
     const bool cart = c->prm.coords == KT_CARTESIAN;
     hipError_t e = prof_mark(c, 2, true);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
-    const dim3 g((c->P.nx + 1 + 63) / 64, (c->P.ny + 1 + 3) / 4, c->P.neta + 1), b(64, 4);
-    e = cart ? launch(face_speeds_kernel<true>, g, b, c->stream, c->P, c->E, c->G, tau, q,
+    const FaceLaunch L = face_launch(c->G);
+    const dim3 g(L.first_block[6]), b(256);
+    e = cart ? launch(face_speeds_kernel<true>, g, b, c->stream, c->P, c->E, c->G, L, tau, q,
                       (const double *)c->e, c->vf, c->slots)
-             : launch(face_speeds_kernel<false>, g, b, c->stream, c->P, c->E, c->G, tau, q,
+             : launch(face_speeds_kernel<false>, g, b, c->stream, c->P, c->E, c->G, L, tau, q,
                       (const double *)c->e, c->vf, c->slots);
     if (e == hipSuccess) e = prof_mark(c, 2, false);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "face kernel: %s", hipGetErrorString(e));
@@ -1156,6 +1166,7 @@ kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out)
         host_out->n_floor = (int64_t)ctr[C_FLOOR];
         host_out->n_clamp = (int64_t)ctr[C_CLAMP];
         host_out->n_fallback = (int64_t)ctr[C_FALLBACK];
+        host_out->n_fallback_faces = (int64_t)ctr[C_FALLBACK_FACES];
     }
     return KT_OK;
 }

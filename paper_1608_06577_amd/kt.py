@@ -58,7 +58,8 @@ class KtObs(C.Structure):
                 ("pi_transverse", C.c_double), ("pi_trace", C.c_double), ("n_nan", C.c_int64),
                 ("newton_iters_cells", C.c_int64), ("n_recover_cells", C.c_int64),
                 ("newton_iters_faces", C.c_int64), ("n_recover_faces", C.c_int64),
-                ("n_floor", C.c_int64), ("n_clamp", C.c_int64), ("n_fallback", C.c_int64)]
+                ("n_floor", C.c_int64), ("n_clamp", C.c_int64), ("n_fallback", C.c_int64),
+                ("n_fallback_faces", C.c_int64)]
 
     def as_dict(self):
         d = {}
