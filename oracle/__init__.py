@@ -69,7 +69,7 @@ def lib():
         ip = C.POINTER(C.c_int32)
         P, E = C.POINTER(_Params), C.POINTER(_EOS)
         L.ora_tmunu.argtypes = [P, E, C.c_double, C.c_int64, dp, dp, dp, dp, dp]
-        L.ora_recover.argtypes = [P, E, C.c_double, C.c_int64, dp, dp, dp, ip, ip]
+        L.ora_recover.argtypes = [P, E, C.c_double, C.c_int64, dp, C.c_void_p, dp, dp, ip, ip]
         L.ora_regulate.argtypes = [P, E, C.c_double, C.c_int64, dp, dp, dp, dp]
         L.ora_eos_eval.argtypes = [E, C.c_int64, dp, dp, dp, dp]
         L.ora_init.argtypes = [P, E, C.c_double, dp, dp, dp, dp]
@@ -184,7 +184,9 @@ def tmunu(phys: Physics, eos, tau, e, u, pi, Pi):
     return q
 
 
-def recover(phys: Physics, eos, tau, q):
+def recover(phys: Physics, eos, tau, q, e_start=None):
+    """Cell inversion of q (n, 15) at tau; e_start (n,) optional Newton start
+    (values <= 0: the conformal closed form, the default)."""
     ref = EOSRef(eos)
     q = np.ascontiguousarray(q, dtype=np.float64)
     n = q.shape[0]
@@ -193,7 +195,13 @@ def recover(phys: Physics, eos, tau, q):
     it = np.empty(n, np.int32)
     fl = np.empty(n, np.int32)
     P = phys.c()
-    lib().ora_recover(C.byref(P), C.byref(ref.c), tau, n, _dp(q), _dp(e), _dp(u), _ip(it), _ip(fl))
+    es = None
+    if e_start is not None:
+        es = np.ascontiguousarray(e_start, dtype=np.float64)
+        assert es.shape == (n,)
+    lib().ora_recover(C.byref(P), C.byref(ref.c), tau, n, _dp(q),
+                      None if es is None else es.ctypes.data_as(C.c_void_p),
+                      _dp(e), _dp(u), _ip(it), _ip(fl))
     return e, u, it, fl
 
 

@@ -201,8 +201,8 @@ static void tmunu_from_primitives(const ora_params *P, const ora_eos *eos, doubl
  *    iterates clamped to [e_floor, E], started from the conformal closed form;
  *    once |f| <= tol E, one more iteration is taken and the loop stops.
  *  - No convergence within newton_max iterations: bisection on [e_floor, E]. */
-static int recover(const ora_params *P, const ora_eos *eos, double tau, const double q[NQ],
-                   double *e_out, double u_out[4], int *iters)
+static int recover_from(const ora_params *P, const ora_eos *eos, double tau, const double q[NQ],
+                        double e_start, double *e_out, double u_out[4], int *iters)
 {
     double glo[4], ghi[4];
     metric(tau, P->cartesian, glo, ghi);
@@ -234,7 +234,7 @@ static int recover(const ora_params *P, const ora_eos *eos, double tau, const do
     if (eos->conformal && !bulk) {
         e = fmax(econf, ef);
     } else {
-        e = fmin(fmax(econf, ef), E);
+        e = fmin(fmax(e_start > 0.0 ? e_start : econf, ef), E);
         int done = 0, n = 0;
         while (n < P->newton_max) {
             double p, cs2, T;
@@ -266,6 +266,13 @@ static int recover(const ora_params *P, const ora_eos *eos, double tau, const do
     for (int i = 1; i < 4; ++i) u_out[i] = M[i] / ((e + Pcal) * ut);
     *e_out = e;
     return flags;
+}
+
+/* the same, started from the conformal closed form */
+static int recover(const ora_params *P, const ora_eos *eos, double tau, const double q[NQ],
+                   double *e_out, double u_out[4], int *iters)
+{
+    return recover_from(P, eos, tau, q, -1.0, e_out, u_out, iters);
 }
 
 /* ------------------------------------------------------------------ */
@@ -662,14 +669,15 @@ void ora_tmunu(const ora_params *P, const ora_eos *eos, double tau, int64_t n, c
         tmunu_from_primitives(P, eos, tau, e[c], u + 4 * c, pi + 10 * c, Pi[c], q + NQ * c);
 }
 
-/* standalone recovery of n cells; iters/flags nullable */
+/* standalone recovery of n cells; iters/flags nullable; e_start (nullable):
+ * per-cell Newton start, values <= 0 meaning the conformal closed form */
 void ora_recover(const ora_params *P, const ora_eos *eos, double tau, int64_t n, const double *q,
-                 double *e, double *u, int32_t *iters, int32_t *flags)
+                 const double *e_start, double *e, double *u, int32_t *iters, int32_t *flags)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < n; ++c) {
         int it;
-        int f = recover(P, eos, tau, q + NQ * c, e + c, u + 4 * c, &it);
+        int f = recover_from(P, eos, tau, q + NQ * c, e_start ? e_start[c] : -1.0, e + c, u + 4 * c, &it);
         if (iters) iters[c] = it;
         if (flags) flags[c] = f;
     }

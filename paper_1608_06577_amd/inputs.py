@@ -523,3 +523,26 @@ def workload_hotspot(nx: int = 128, ny: int = 128, neta: int = 128, dx: float = 
     prims = hotspot_event(grid, tau0=0.5, n_hot=n_hot, seed=seed)
     return Workload("hotspot_viscous_%dx%dx%d" % (nx, ny, neta), grid, 0.5, n_steps, cfg,
                     eos if eos is not None else eos_c1_table(), prims)
+
+
+# --------------------------------------------------------------------------
+# Learned inversion start: seeded initial parameters of the 11-64-64-4 network
+# --------------------------------------------------------------------------
+
+MLP_LAYERS = ((64, 11), (64, 64), (4, 64))   # (fan_out, fan_in) of W1, W2, W3
+MLP_N_PARAMS = sum(o * i + o for o, i in MLP_LAYERS)   # 5188
+
+
+def mlp_init_params(seed: int = 0, y0_bias: float = 0.8) -> np.ndarray:
+    """Flat float32 vector W1, b1, W2, b2, W3, b3 (row-major weights): weights
+    normal with variance 1/fan_in, biases zero except the first output
+    (e/E starts near y0_bias)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for k, (fo, fi) in enumerate(MLP_LAYERS):
+        parts.append(rng.standard_normal((fo, fi)) / math.sqrt(fi))
+        b = np.zeros(fo)
+        if k == len(MLP_LAYERS) - 1:
+            b[0] = y0_bias
+        parts.append(b)
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
