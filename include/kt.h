@@ -169,10 +169,77 @@ kt_status kt_step(kt_ctx *c, int32_t n_steps);
  * pi^{tau tau}, pi^{tau x}, pi^{tau y}, pi^{tau eta}, Pi (Pi may be null = 0).
  * Outputs e_out[n], u_out[4][n]; iters_out and flags_out (bit 1 floor,
  * 2 clamp, 4 bisection fallback) may be null.  Uses the context's EOS and
- * guards; Newton starts from the conformal closed form.  Asynchronous. */
+ * guards; Newton starts from the conformal closed form, or from the network
+ * when the context's start is KT_START_LEARNED.  Asynchronous. */
 kt_status kt_recover(kt_ctx *c, int64_t n, double tau, const double *const in[9],
                      double *e_out, double *const u_out[4], int32_t *iters_out,
                      int32_t *flags_out);
+
+/* ---------------------------------------------------------------------
+ * Learned start of the cell inversion.  Newton's method (Sec. 3.2) needs a
+ * starting e; the paper leaves it open.  A network 11 -> 64 -> 64 -> 4 with
+ * GELU(a) = a Phi(a) maps features of one state to (e/e_c, v^x, v^y,
+ * sqrt(g33) v^eta), where e_c = sqrt(4E^2 - 3M^2) - E (at least e_floor) is
+ * the root for the conformal EOS without bulk, E = T^{tau tau} -
+ * pi^{tau tau}, M^i = T^{tau i} - pi^{tau i}, M^2 = M_x^2 + M_y^2 +
+ * g33 M_eta^2.  The start is y_0 e_c; Newton then converges to the same
+ * tolerance as from any other start, with bisection as the fallback.
+ * Features of a state with T0 = T^{tau tau}: T^{tau x}/T0, T^{tau y}/T0,
+ * sqrt(g33) T^{tau eta}/T0, pi^{tau tau}/T0, pi^{tau x}/T0, pi^{tau y}/T0,
+ * sqrt(g33) pi^{tau eta}/T0, Pi/T0, 0.1 ln T0, c_s^2(T0), p(T0)/T0
+ * (g33 = tau^2 in Milne coordinates, 1 in Cartesian ones).
+ *
+ * Parameters: KT_MLP_NPARAMS floats W1 (64x11), b1 (64), W2 (64x64), b2,
+ * W3 (4x64), b3 (4), weights row major (a = W h + b), held in the
+ * context's workspace together with Adam's moments.  Batched device arrays
+ * are FP32 and feature-major: x[f*n + i] (11 rows), y, targets and dy
+ * [o*n + i] (4 rows), act[k*n + i] (128 rows: the pre-activations of the
+ * two hidden layers).  All calls are asynchronous on the context's stream.
+ * --------------------------------------------------------------------- */
+enum { KT_START_WARM = 0, KT_START_CONFORMAL = 1, KT_START_LEARNED = 2 };
+#define KT_MLP_NPARAMS 5188
+
+/* Newton start of the cell recoveries in kt_step: KT_START_WARM (the cell's
+ * e before the stage; the default), KT_START_CONFORMAL (closed form of the
+ * conformal EOS) or KT_START_LEARNED (needs kt_mlp_set first: KT_E_STATE
+ * otherwise).  kt_recover uses the network for KT_START_LEARNED and the
+ * conformal closed form otherwise.  Face states always start from the e
+ * of the cell they were extrapolated from. */
+kt_status kt_set_inv_start(kt_ctx *c, int32_t start);
+
+/* Copy KT_MLP_NPARAMS parameters from d_params (device) into the context
+ * and zero the Adam moments; kt_mlp_get copies them out. */
+kt_status kt_mlp_set(kt_ctx *c, const float *d_params, int32_t n_params);
+kt_status kt_mlp_get(kt_ctx *c, float *d_params, int32_t n_params);
+
+/* Features x (11 x n) of n states given like kt_recover's in[9] at tau; if
+ * y is non-null, also the targets (e/e_c, v^x, v^y, sqrt(g33) v^eta) from
+ * the recovered e_in[n] and u_in[4][n] (then both are required). */
+kt_status kt_mlp_features(kt_ctx *c, int64_t n, double tau, const double *const in[9],
+                          const double *e_in, const double *const u_in[4], float *x, float *y);
+
+/* Forward pass of n samples: y (4 x n); act (128 x n, nullable) keeps the
+ * pre-activations for kt_mlp_bwd. */
+kt_status kt_mlp_fwd(kt_ctx *c, int64_t n, const float *x, float *y, float *act);
+
+/* Weighted mean squared error over the 4 x n outputs,
+ * L = sum_{o,i} w_o (y - t)^2 / (4 n) with w (host array of 4, nullable =
+ * all 1, each >= 0): dy = 2 w_o (y - t) / (4 n) (nullable) and L into *loss
+ * (device double, nullable). */
+kt_status kt_mlp_loss(kt_ctx *c, int64_t n, const float *y, const float *t, const float *w,
+                      float *dy, double *loss);
+
+/* Gradient of sum_i <dy_i, y_i> with respect to the parameters into
+ * grad[KT_MLP_NPARAMS] (overwritten).  The sum over samples is taken per
+ * block and then over blocks in a fixed order, so the result does not
+ * depend on scheduling. */
+kt_status kt_mlp_bwd(kt_ctx *c, int64_t n, const float *x, const float *act, const float *dy,
+                     float *grad);
+
+/* One Adam step (Kingma & Ba, arXiv:1412.6980) of the context's parameters
+ * with step number t >= 1. */
+kt_status kt_mlp_adam(kt_ctx *c, const float *grad, float lr, float b1, float b2, float eps,
+                      int32_t t);
 
 /* Diagnostics into *host_out (nullable) and, if dev_out is non-null, copies
  * of the current fields into the given device arrays.  Synchronises. */

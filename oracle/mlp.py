@@ -14,16 +14,20 @@ starting value.  Here a small network proposes it:
       ln(T^{tau tau})/10, c_s^2(T^{tau tau}), p(T^{tau tau})/T^{tau tau}
       (g33 = tau^2 in Milne coordinates, 1 in Cartesian ones; c_s^2 and p of
       the equation of state evaluated at e = T^{tau tau});
-  targets y (4): e/E with E = T^{tau tau} - pi^{tau tau}, and the velocity
-      v^x = u^x/u^tau, v^y = u^y/u^tau, sqrt(g33) u^eta/u^tau;
+  targets y (4): e/e_c and the velocity v^x = u^x/u^tau, v^y = u^y/u^tau,
+      sqrt(g33) u^eta/u^tau, where e_c = sqrt(4E^2 - 3M^2) - E is the root for
+      the conformal EOS without bulk (E = T^{tau tau} - pi^{tau tau}, M^2 =
+      (T^{tau x} - pi^{tau x})^2 + (T^{tau y} - pi^{tau y})^2
+      + g33 (T^{tau eta} - pi^{tau eta})^2), floored at e_floor;
   network: 11 -> 64 -> 64 -> 4, GELU(a) = a Phi(a) = a (1 + erf(a/sqrt 2))/2
       after the two hidden layers, linear output;
-  start: e_0 = y_0 E, then the usual Newton polish.
+  start: e_0 = y_0 e_c, then the usual Newton polish.
 
 Parameters are one flat vector of 5188 numbers: W1 (64 x 11, row major), b1
 (64), W2 (64 x 64), b2 (64), W3 (4 x 64), b3 (4); a layer computes
-a = W h + b.  The loss is the mean over samples and outputs of (y - t)^2;
-training uses Adam (Kingma & Ba, arXiv:1412.6980, Algorithm 1).
+a = W h + b.  The loss is the mean over samples and outputs of
+w_o (y_o - t_o)^2 with per-output weights w (default 1); training uses Adam
+(Kingma & Ba, arXiv:1412.6980, Algorithm 1).
 """
 from __future__ import annotations
 
@@ -95,11 +99,13 @@ def backward(theta, x, act, dy):
     return np.concatenate([g[name].ravel() for name, _ in SHAPES])
 
 
-def loss_and_grad(y, t):
-    """Mean over samples and outputs of (y - t)^2 and its gradient in y."""
+def loss_and_grad(y, t, w=None):
+    """Mean over samples and outputs of w_o (y_o - t_o)^2, y and t (n, 4), and
+    its gradient in y."""
     d = np.asarray(y, dtype=np.float64) - np.asarray(t, dtype=np.float64)
+    wt = np.ones(N_OUT) if w is None else np.asarray(w, dtype=np.float64)
     n = d.size
-    return float(np.sum(d * d) / n), 2.0 * d / n
+    return float(np.sum(wt * d * d) / n), 2.0 * wt * d / n
 
 
 def adam(theta, m, v, g, lr, b1, b2, eps, t):
@@ -134,11 +140,20 @@ def features(tau, cartesian, q9, eos):
     return x
 
 
-def targets(tau, cartesian, q9, e, u):
+def conformal_root(tau, cartesian, q9, e_floor):
+    """e_c = sqrt(4E^2 - 3M^2) - E, floored at e_floor (M^2 above 4E^2/3 gives e_floor)."""
+    q9 = np.asarray(q9, dtype=np.float64)
+    g33 = 1.0 if cartesian else float(tau) ** 2
+    E = q9[:, 0] - q9[:, 4]
+    M2 = (q9[:, 1] - q9[:, 5]) ** 2 + (q9[:, 2] - q9[:, 6]) ** 2 + g33 * (q9[:, 3] - q9[:, 7]) ** 2
+    return np.maximum(np.sqrt(np.maximum(4.0 * E * E - 3.0 * M2, 0.0)) - E, e_floor)
+
+
+def targets(tau, cartesian, q9, e, u, e_floor):
     """Training targets from the recovered (e, u): (n, 4)."""
     q9 = np.asarray(q9, dtype=np.float64)
     sg = 1.0 if cartesian else float(tau)
-    E = q9[:, 0] - q9[:, 4]
     u = np.asarray(u, dtype=np.float64)
-    return np.stack([np.asarray(e) / E, u[:, 1] / u[:, 0], u[:, 2] / u[:, 0],
+    ec = conformal_root(tau, cartesian, q9, e_floor)
+    return np.stack([np.asarray(e) / ec, u[:, 1] / u[:, 0], u[:, 2] / u[:, 0],
                      sg * u[:, 3] / u[:, 0]], axis=1)

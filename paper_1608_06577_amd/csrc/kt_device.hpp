@@ -153,14 +153,15 @@ __host__ __device__ __forceinline__ double eos_p(const Eos &E, double e)
 // (1 - m2_delta) W min(E - e_floor, W); conformal EOS without bulk uses the
 // closed form sqrt(4E^2 - 3M^2) - E; otherwise Newton from e_start (<= 0:
 // the conformal value), iterates clamped to [e_floor, E], one extra step
-// after |f| <= tol E, bisection if not converged.  Returns the flags;
-// p_out is p(e) of the equilibrium EOS at the result.
+// after |f| <= tol E, bisection if not converged.
+// invert_core returns the flags and gives e, p(e) of the equilibrium EOS,
+// E = T^{tau tau} - pi^{tau tau} and the (possibly rescaled) M^i.
 template <bool CART>
-__device__ __forceinline__ int recover(const Phys &P, const Eos &E, double tau, double Ttt,
-                                       double Ttx, double Tty, double Tte, double ptt,
-                                       double ptx, double pty, double pte, double Pi,
-                                       double e_start, double &e, double &p_out, double u[4],
-                                       int &iters)
+__device__ __forceinline__ int invert_core(const Phys &P, const Eos &E, double tau, double Ttt,
+                                           double Ttx, double Tty, double Tte, double ptt,
+                                           double ptx, double pty, double pte, double Pi,
+                                           double e_start, double &e, double &p_out, double &EE_out,
+                                           double M[3], int &iters)
 {
     const double ef = P.e_floor;
     const double g33 = CART ? 1.0 : tau * tau;
@@ -169,11 +170,11 @@ __device__ __forceinline__ int recover(const Phys &P, const Eos &E, double tau, 
     double M2 = Mx * Mx + My * My + g33 * (Me * Me);
     const double W = EE + P.p_floor + Pi;
     iters = 0;
+    EE_out = EE;
     if (!(EE > ef) || !(W > 0.0) || !(M2 == M2) || !(M2 < INFINITY)) {
         e = ef;
         p_out = P.p_floor;
-        u[0] = 1.0;
-        u[1] = u[2] = u[3] = 0.0;
+        M[0] = M[1] = M[2] = 0.0;
         return F_FLOOR;
     }
     int flags = 0;
@@ -225,15 +226,37 @@ __device__ __forceinline__ int recover(const Phys &P, const Eos &E, double tau, 
         }
         p = eos_p(E, x);
     }
-    const double Pc = p + Pi;
-    const double ut = sqrt((EE + Pc) / (x + Pc));
-    const double inv = 1.0 / ((x + Pc) * ut);
-    u[0] = ut;
-    u[1] = Mx * inv;
-    u[2] = My * inv;
-    u[3] = Me * inv;
     e = x;
     p_out = p;
+    M[0] = Mx;
+    M[1] = My;
+    M[2] = Me;
+    return flags;
+}
+
+// full recovery: u^tau = sqrt((E + P)/(e + P)), u^i = M^i / ((e + P) u^tau), P = p + Pi
+template <bool CART>
+__device__ __forceinline__ int recover(const Phys &P, const Eos &E, double tau, double Ttt,
+                                       double Ttx, double Tty, double Tte, double ptt,
+                                       double ptx, double pty, double pte, double Pi,
+                                       double e_start, double &e, double &p_out, double u[4],
+                                       int &iters)
+{
+    double EE, M[3];
+    const int flags = invert_core<CART>(P, E, tau, Ttt, Ttx, Tty, Tte, ptt, ptx, pty, pte, Pi,
+                                        e_start, e, p_out, EE, M, iters);
+    if (flags & F_FLOOR) {
+        u[0] = 1.0;
+        u[1] = u[2] = u[3] = 0.0;
+        return flags;
+    }
+    const double Pc = p_out + Pi;
+    const double ut = sqrt((EE + Pc) / (e + Pc));
+    const double inv = 1.0 / ((e + Pc) * ut);
+    u[0] = ut;
+    u[1] = M[0] * inv;
+    u[2] = M[1] * inv;
+    u[3] = M[2] * inv;
     return flags;
 }
 

@@ -28,6 +28,7 @@
 
 #include "kt.h"
 #include "kt_device.hpp"
+#include "kt_mlp.hpp"
 
 using namespace ktd;
 
@@ -89,6 +90,38 @@ __device__ __forceinline__ int wrap(int v, int n, int periodic)
     return v;
 }
 
+// Blocks are dispatched to the chip's 8 XCDs round robin (block b to XCD
+// b % 8), each XCD with its own L2.  This renumbering gives every XCD one
+// contiguous range of logical blocks, so neighbouring tiles, which read each
+// other's halo cells, share an L2.  It is a bijection on [0, nb) for any nb.
+constexpr unsigned NXCD = 8;
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
+{
+    const unsigned q = nb / NXCD, r = nb % NXCD;
+    const unsigned x = b % NXCD, i = b / NXCD;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// logical (x, y, z) block of a 3D grid after the XCD renumbering
+__device__ __forceinline__ void xcd_block3(unsigned &bx, unsigned &by, unsigned &bz)
+{
+    const unsigned gx = gridDim.x, gy = gridDim.y;
+    const unsigned L = xcd_block(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+    bx = L % gx;
+    by = (L / gx) % gy;
+    bz = L / (gx * gy);
+}
+
+// floor(t / d) for t < 2^32, d >= 1, through a double product and one correction
+__device__ __forceinline__ idx_t udiv(idx_t t, idx_t d, double inv_d)
+{
+    idx_t q = (idx_t)((double)t * inv_d);
+    const long long r = (long long)t - (long long)q * d;
+    if (r < 0) q -= 1;
+    else if (r >= (long long)d) q += 1;
+    return q;
+}
+
 // counters: lane 0 of each wave adds the wave's totals to its own slot row
 __device__ __forceinline__ void slot_add(unsigned long long *slots, long long wave, int which,
                                          long long v)
@@ -123,6 +156,7 @@ __device__ __forceinline__ double face_H(const double *q, idx_t co, double theta
 // segment is the face index of fidx_x / fidx_y / fidx_e.
 struct FaceLaunch {
     unsigned first_block[7];   // first block of each segment; [6] = total
+    double inv_nx1, inv_nx, inv_ny1, inv_plane;   // 1/(nx+1), 1/nx, 1/(ny+1), 1/(nx ny)
 };
 
 template <bool CART>
@@ -131,12 +165,12 @@ __global__ __launch_bounds__(256) void face_speeds_kernel(Phys P, Eos E, FaceGeo
                                                           const double *e, double *vf,
                                                           unsigned long long *slots)
 {
-    const unsigned b = blockIdx.x;
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
     int seg = 0;
 #pragma unroll
     for (int t = 1; t < 6; ++t) seg += b >= L.first_block[t] ? 1 : 0;
     const int d = seg >> 1, side = seg & 1;     // side 0: q^-, side 1: q^+
-    const long long wave = (long long)b * 4 + (threadIdx.x >> 6);
+    const long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
     const idx_t t = (idx_t)(b - L.first_block[seg]) * 256 + threadIdx.x;
     const long long nf = d == 0 ? G.nfx : (d == 1 ? G.nfy : G.nfe);
     int it = 0, fl = 0;
@@ -146,21 +180,21 @@ __global__ __launch_bounds__(256) void face_speeds_kernel(Phys P, Eos E, FaceGeo
         idx_t base, step;
         int pos, n, per;
         if (d == 0) {
-            const idx_t n1 = (idx_t)P.nx + 1, r = t / n1;
+            const idx_t n1 = (idx_t)P.nx + 1, r = udiv(t, n1, L.inv_nx1);
             pos = (int)(t - r * n1);
             base = r * (idx_t)P.nx;                    // row (j, k)
             step = 1;
             n = P.nx;
             per = P.periodic[0];
         } else if (d == 1) {
-            const idx_t r = t / (idx_t)P.nx, k = r / (idx_t)(P.ny + 1);
+            const idx_t r = udiv(t, (idx_t)P.nx, L.inv_nx), k = udiv(r, (idx_t)(P.ny + 1), L.inv_ny1);
             pos = (int)(r - k * (idx_t)(P.ny + 1));
             base = k * (idx_t)P.nx * P.ny + (t - r * (idx_t)P.nx);
             step = (idx_t)P.nx;
             n = P.ny;
             per = P.periodic[1];
         } else {
-            const idx_t plane = (idx_t)P.nx * P.ny, k = t / plane;
+            const idx_t plane = (idx_t)P.nx * P.ny, k = udiv(t, plane, L.inv_plane);
             pos = (int)k;
             base = t - k * plane;
             step = plane;
@@ -181,20 +215,27 @@ __global__ __launch_bounds__(256) void face_speeds_kernel(Phys P, Eos E, FaceGeo
             const double a0 = ld(q, co + sm), a1 = ld(q, co + s0), a2 = ld(q, co + sp);
             m[r] = a1 + h * slope(a0, a1, a2, P.theta);
         }
-        double ee, pe, u[4];
-        fl = recover<CART>(P, E, tau, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7],
-                           P.bulk ? m[8] : 0.0, ld(e, s0), ee, pe, u, it);
+        // v^d = u^d / u^tau = M^d / (E + P) (Sec. 2.4), 0 on the floor
+        double ee, pe, EE, M[3];
+        const double Pi = P.bulk ? m[8] : 0.0;
+        fl = invert_core<CART>(P, E, tau, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], Pi,
+                               ld(e, s0), ee, pe, EE, M, it);
+        const double v = (fl & F_FLOOR) ? 0.0 : M[d] / (EE + pe + Pi);
         const long long off = (d == 0 ? G.ox : (d == 1 ? G.oy : G.oe)) + (side ? nf : 0);
-        st(vf + off, t, u[d + 1] / u[0]);
+        st(vf + off, t, v);
     }
     slot_add(slots, wave, C_ITERS_FACES, it);
     slot_add(slots, wave, C_REC_FACES, valid ? 1 : 0);
     slot_add(slots, wave, C_FALLBACK_FACES, (fl & F_FALLBACK) ? 1 : 0);
 }
 
-static FaceLaunch face_launch(const FaceGeo &G)
+static FaceLaunch face_launch(const FaceGeo &G, int nx, int ny)
 {
     FaceLaunch L;
+    L.inv_nx1 = 1.0 / (nx + 1.0);
+    L.inv_nx = 1.0 / nx;
+    L.inv_ny1 = 1.0 / (ny + 1.0);
+    L.inv_plane = 1.0 / ((double)nx * ny);
     const long long nf[3] = {G.nfx, G.nfy, G.nfe};
     unsigned acc = 0;
     for (int s = 0; s < 6; ++s) {
@@ -237,9 +278,11 @@ template <bool CART, bool STAGE2>
 __global__ __launch_bounds__(256) void sources_kernel(Phys P, Eos E, double tau, Fields F,
                                                       const double *qn, double *out)
 {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int j = blockIdx.y * 4 + threadIdx.y;
-    const int k = blockIdx.z;
+    unsigned bx, by, bz;
+    xcd_block3(bx, by, bz);
+    const int i = bx * 64 + threadIdx.x;
+    const int j = by * 4 + threadIdx.y;
+    const int k = bz;
     if (i >= P.nx || j >= P.ny) return;
     const idx_t SS = (idx_t)P.stride;
     const idx_t plane = (idx_t)P.nx * P.ny;
@@ -338,11 +381,13 @@ __global__ __launch_bounds__(256) void flux_kernel(Phys P, FaceGeo G, const doub
                                                    const double *vf, double *out)
 {
     __shared__ double Hb[NQ][256];   // eta face below the current plane
+    unsigned bx, by, bz;
+    xcd_block3(bx, by, bz);
     const int lane = threadIdx.x;
     const int tid = threadIdx.y * 64 + lane;
-    const int i = blockIdx.x * 64 + lane;
-    const int j = blockIdx.y * 4 + threadIdx.y;
-    const int k0 = blockIdx.z * KC;
+    const int i = bx * 64 + lane;
+    const int j = by * 4 + threadIdx.y;
+    const int k0 = bz * KC;
     const idx_t plane = (idx_t)P.nx * P.ny;
     // lanes outside the grid compute on clamped cells; their results are not stored
     const int ic = i < P.nx ? i : P.nx - 1;
@@ -425,12 +470,14 @@ __global__ __launch_bounds__(256) void flux_kernel(Phys P, FaceGeo G, const doub
     }
 }
 
-// recovery of every cell at tau (warm start: the cell's previous e), then
-// the regulator and the floor reset; writes e, p(e) and u
-template <bool CART>
+// recovery of every cell at tau, then the regulator and the floor reset;
+// writes e, p(e) and u.  Newton start: the cell's previous e (warm), the
+// conformal closed form, or (LEARNED) y_0 E from the network of kt_mlp.hpp.
+template <bool CART, bool LEARNED>
 __global__ __launch_bounds__(256) void recover_kernel(Phys P, Eos E, double tau, double *q,
                                                       double *e_io, double *p_out, double *u_out,
                                                       int do_regulate, int warm,
+                                                      const float *__restrict__ mlpw,
                                                       unsigned long long *slots)
 {
     const idx_t s = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -439,13 +486,27 @@ __global__ __launch_bounds__(256) void recover_kernel(Phys P, Eos E, double tau,
     int it = 0, fl = 0;
     const bool valid = (long long)s < P.ncell;
     if (valid) {
+        double es = warm ? ld(e_io, s) : -1.0;
+        if (LEARNED) {   // before the cell's state is held in registers
+            const double Ttt = ld(q, s), ptt = ld(q, (idx_t)PTT * SS + s);
+            if (Ttt > 0.0 && Ttt - ptt > 0.0) {
+                const double Ttx = ld(q, SS + s), Tty = ld(q, 2 * SS + s), Tte = ld(q, 3 * SS + s);
+                const double ptx = ld(q, (idx_t)PTX * SS + s), pty = ld(q, (idx_t)PTY * SS + s);
+                const double pte = ld(q, (idx_t)PTE * SS + s);
+                float x[ktm::NI];
+                ktm::features<CART>(E, tau, Ttt, Ttx, Tty, Tte, ptt, ptx, pty, pte,
+                                    P.bulk ? ld(q, (idx_t)BPI * SS + s) : 0.0, x);
+                es = (double)ktm::forward_y0(mlpw, x)
+                   * ktm::conformal_root<CART>(P.e_floor, tau, Ttt, Ttx, Tty, Tte, ptt, ptx, pty, pte);
+            }
+        }
         double qc[NQ];
 #pragma unroll
         for (int c = 0; c < NQ; ++c) qc[c] = ld(q, (idx_t)(c) * SS + s);
         const double Pi = P.bulk ? qc[BPI] : 0.0;
         double e, p0, u[4];
         fl = recover<CART>(P, E, tau, qc[TT], qc[TX], qc[TY], qc[TE], qc[PTT], qc[PTX], qc[PTY],
-                           qc[PTE], Pi, warm ? ld(e_io, s) : -1.0, e, p0, u, it);
+                           qc[PTE], Pi, es, e, p0, u, it);
         st(e_io, s, e);
         st(p_out, s, p0);
 #pragma unroll
@@ -500,18 +561,30 @@ struct RecIn {
     int *flags;
 };
 
-template <bool CART>
+template <bool CART, bool LEARNED>
 __global__ __launch_bounds__(256) void recover_standalone_kernel(Phys P, Eos E, double tau,
-                                                                 long long n, RecIn R)
+                                                                 long long n, RecIn R,
+                                                                 const float *__restrict__ mlpw)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const double Pi = (P.bulk && R.in[8]) ? R.in[8][s] : 0.0;
+    const double Ttt = R.in[0][s], ptt = R.in[4][s];
+    double es = -1.0;
+    if (LEARNED) {
+        if (Ttt > 0.0 && Ttt - ptt > 0.0) {
+            float x[ktm::NI];
+            ktm::features<CART>(E, tau, Ttt, R.in[1][s], R.in[2][s], R.in[3][s], ptt, R.in[5][s],
+                                R.in[6][s], R.in[7][s], Pi, x);
+            es = (double)ktm::forward_y0(mlpw, x)
+               * ktm::conformal_root<CART>(P.e_floor, tau, Ttt, R.in[1][s], R.in[2][s], R.in[3][s], ptt,
+                                           R.in[5][s], R.in[6][s], R.in[7][s]);
+        }
+    }
     double e, p, u[4];
     int it;
-    const int fl = recover<CART>(P, E, tau, R.in[0][s], R.in[1][s], R.in[2][s], R.in[3][s],
-                                 R.in[4][s], R.in[5][s], R.in[6][s], R.in[7][s], Pi, -1.0, e, p,
-                                 u, it);
+    const int fl = recover<CART>(P, E, tau, Ttt, R.in[1][s], R.in[2][s], R.in[3][s], ptt,
+                                 R.in[5][s], R.in[6][s], R.in[7][s], Pi, es, e, p, u, it);
     R.e[s] = e;
 #pragma unroll
     for (int m = 0; m < 4; ++m) R.u[m][s] = u[m];
@@ -682,6 +755,10 @@ struct kt_ctx {
     double *vf;
     FaceGeo G;
     double *partial, *obs;
+    float *mlp_w, *mlp_m, *mlp_v, *mlp_part;   // network parameters, Adam moments, gradient partials
+    double *loss_part;
+    bool mlp_ready;
+    int inv_start;
     double tau;
     long long step;
     char err[512];
@@ -740,7 +817,7 @@ static long long cell_stride(const kt_params *p)
 }
 
 struct Layout {
-    size_t q, qs, u, e, p, vf, tab, slots, ctr, partial, obs, total;
+    size_t q, qs, u, e, p, vf, tab, slots, ctr, partial, obs, mlp, mlp_part, loss_part, total;
     long long nwaves;
     FaceGeo G;
 };
@@ -759,7 +836,7 @@ static FaceGeo face_geo(const kt_params *p)
 
 static long long face_waves(const kt_params *p)
 {
-    return (long long)face_launch(face_geo(p)).first_block[6] * 4;
+    return (long long)face_launch(face_geo(p), p->nx, p->ny).first_block[6] * 4;
 }
 
 static long long stage_waves(const kt_params *p)
@@ -793,6 +870,9 @@ static Layout layout(const kt_params *p, const kt_eos *eos)
     L.ctr = off; off += 256;
     L.partial = off; off += round_up((size_t)OBS_BLOCKS * O_COUNT * sizeof(double), 256);
     L.obs = off; off += 256;
+    L.mlp = off; off += round_up((size_t)3 * ktm::NP * sizeof(float), 256);
+    L.mlp_part = off; off += round_up((size_t)ktm::BWD_BLOCKS * ktm::NP * sizeof(float), 256);
+    L.loss_part = off; off += round_up((size_t)(ktm::LOSS_BLOCKS + 1) * sizeof(double), 256);
     L.total = off;
     return L;
 }
@@ -853,16 +933,29 @@ static hipError_t launch(K kernel, dim3 g, dim3 b, hipStream_t st, A... args)
 
 static dim3 linear_grid(long long n) { return dim3((unsigned)((n + 255) / 256)); }
 
+// warm != 0: a step's recovery, whose start follows the context's choice
+// (previous e, conformal closed form, or the network); warm == 0: conformal
 static kt_status run_recover(kt_ctx *c, double tau, double *q, double *u_out, int regulate,
                              int warm)
 {
     const bool cart = c->prm.coords == KT_CARTESIAN;
+    const bool learned = warm && c->inv_start == KT_START_LEARNED;
+    if (warm && c->inv_start == KT_START_CONFORMAL) warm = 0;
+    if (learned) warm = 0;
     hipError_t e = prof_mark(c, 1, true);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
-    e = cart ? launch(recover_kernel<true>, linear_grid(c->P.ncell), dim3(256), c->stream,
-                      c->P, c->E, tau, q, c->e, c->p, u_out, regulate, warm, c->slots)
-             : launch(recover_kernel<false>, linear_grid(c->P.ncell), dim3(256), c->stream,
-                      c->P, c->E, tau, q, c->e, c->p, u_out, regulate, warm, c->slots);
+    const dim3 g = linear_grid(c->P.ncell), b(256);
+    const float *w = c->mlp_w;
+    if (cart)
+        e = learned ? launch(recover_kernel<true, true>, g, b, c->stream, c->P, c->E, tau, q, c->e, c->p,
+                             u_out, regulate, warm, w, c->slots)
+                    : launch(recover_kernel<true, false>, g, b, c->stream, c->P, c->E, tau, q, c->e, c->p,
+                             u_out, regulate, warm, w, c->slots);
+    else
+        e = learned ? launch(recover_kernel<false, true>, g, b, c->stream, c->P, c->E, tau, q, c->e, c->p,
+                             u_out, regulate, warm, w, c->slots)
+                    : launch(recover_kernel<false, false>, g, b, c->stream, c->P, c->E, tau, q, c->e, c->p,
+                             u_out, regulate, warm, w, c->slots);
     if (e == hipSuccess) e = prof_mark(c, 1, false);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "recover kernel: %s", hipGetErrorString(e));
     return KT_OK;
@@ -873,7 +966,7 @@ static kt_status run_faces(kt_ctx *c, double tau, const double *q)
     const bool cart = c->prm.coords == KT_CARTESIAN;
     hipError_t e = prof_mark(c, 2, true);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
-    const FaceLaunch L = face_launch(c->G);
+    const FaceLaunch L = face_launch(c->G, c->P.nx, c->P.ny);
     const dim3 g(L.first_block[6]), b(256);
     e = cart ? launch(face_speeds_kernel<true>, g, b, c->stream, c->P, c->E, c->G, L, tau, q,
                       (const double *)c->e, c->vf, c->slots)
@@ -985,6 +1078,13 @@ kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0
     c->G = L.G;
     c->partial = (double *)(base + L.partial);
     c->obs = (double *)(base + L.obs);
+    c->mlp_w = (float *)(base + L.mlp);
+    c->mlp_m = c->mlp_w + ktm::NP;
+    c->mlp_v = c->mlp_m + ktm::NP;
+    c->mlp_part = (float *)(base + L.mlp_part);
+    c->loss_part = (double *)(base + L.loss_part);
+    c->mlp_ready = false;
+    c->inv_start = KT_START_WARM;
     c->tau = p->tau0;
     c->step = 0;
 
@@ -1099,9 +1199,15 @@ kt_status kt_recover(kt_ctx *c, int64_t n, double tau, const double *const in[9]
     for (int m = 0; m < 4; ++m) R.u[m] = u_out[m];
     R.iters = iters_out;
     R.flags = flags_out;
-    hipError_t e = c->prm.coords == KT_CARTESIAN
-        ? launch(recover_standalone_kernel<true>, linear_grid(n), dim3(256), c->stream, c->P, c->E, tau, (long long)n, R)
-        : launch(recover_standalone_kernel<false>, linear_grid(n), dim3(256), c->stream, c->P, c->E, tau, (long long)n, R);
+    const bool learned = c->inv_start == KT_START_LEARNED;
+    const float *w = c->mlp_w;
+    hipError_t e;
+    if (c->prm.coords == KT_CARTESIAN)
+        e = learned ? launch(recover_standalone_kernel<true, true>, linear_grid(n), dim3(256), c->stream, c->P, c->E, tau, (long long)n, R, w)
+                    : launch(recover_standalone_kernel<true, false>, linear_grid(n), dim3(256), c->stream, c->P, c->E, tau, (long long)n, R, w);
+    else
+        e = learned ? launch(recover_standalone_kernel<false, true>, linear_grid(n), dim3(256), c->stream, c->P, c->E, tau, (long long)n, R, w)
+                    : launch(recover_standalone_kernel<false, false>, linear_grid(n), dim3(256), c->stream, c->P, c->E, tau, (long long)n, R, w);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "recover kernel: %s", hipGetErrorString(e));
     return KT_OK;
 }
@@ -1168,6 +1274,130 @@ kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out)
         host_out->n_fallback = (int64_t)ctr[C_FALLBACK];
         host_out->n_fallback_faces = (int64_t)ctr[C_FALLBACK_FACES];
     }
+    return KT_OK;
+}
+
+kt_status kt_set_inv_start(kt_ctx *c, int32_t start)
+{
+    if (!c) return fail(nullptr, KT_E_ARG, "null context");
+    if (start != KT_START_WARM && start != KT_START_CONFORMAL && start != KT_START_LEARNED)
+        return fail(c, KT_E_ARG, "unknown start %d", start);
+    if (start == KT_START_LEARNED && !c->mlp_ready)
+        return fail(c, KT_E_STATE, "the learned start needs parameters (kt_mlp_set)");
+    c->inv_start = start;
+    return KT_OK;
+}
+
+kt_status kt_mlp_set(kt_ctx *c, const float *d_params, int32_t n_params)
+{
+    if (!c) return fail(nullptr, KT_E_ARG, "null context");
+    if (!d_params) return fail(c, KT_E_ARG, "null parameters");
+    if (n_params != KT_MLP_NPARAMS) return fail(c, KT_E_ARG, "n_params must be %d", KT_MLP_NPARAMS);
+    const size_t b = sizeof(float) * ktm::NP;
+    hipError_t e = hipMemcpyAsync(c->mlp_w, d_params, b, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->mlp_m, 0, 2 * b, c->stream);
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "kt_mlp_set: %s", hipGetErrorString(e));
+    c->mlp_ready = true;
+    return KT_OK;
+}
+
+kt_status kt_mlp_get(kt_ctx *c, float *d_params, int32_t n_params)
+{
+    if (!c) return fail(nullptr, KT_E_ARG, "null context");
+    if (!d_params || n_params != KT_MLP_NPARAMS) return fail(c, KT_E_ARG, "need %d parameters", KT_MLP_NPARAMS);
+    if (!c->mlp_ready) return fail(c, KT_E_STATE, "no parameters set");
+    hipError_t e = hipMemcpyAsync(d_params, c->mlp_w, sizeof(float) * ktm::NP, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "kt_mlp_get: %s", hipGetErrorString(e));
+    return KT_OK;
+}
+
+kt_status kt_mlp_features(kt_ctx *c, int64_t n, double tau, const double *const in[9],
+                          const double *e_in, const double *const u_in[4], float *x, float *y)
+{
+    if (!c) return fail(nullptr, KT_E_ARG, "null context");
+    if (n < 0) return fail(c, KT_E_ARG, "n must be >= 0");
+    if (n == 0) return KT_OK;
+    if (!in || !x) return fail(c, KT_E_ARG, "null input or output");
+    for (int k = 0; k < 8; ++k)
+        if (!in[k]) return fail(c, KT_E_ARG, "input %d is null", k);
+    if (y && (!e_in || !u_in || !u_in[0] || !u_in[1] || !u_in[2] || !u_in[3]))
+        return fail(c, KT_E_ARG, "targets need e and u");
+    if (c->prm.coords == KT_MILNE && !(tau > 0)) return fail(c, KT_E_ARG, "tau must be > 0");
+    ktm::StateIn S;
+    for (int k = 0; k < 9; ++k) S.in[k] = in[k];
+    S.e = e_in;
+    for (int m = 0; m < 4; ++m) S.u[m] = u_in ? u_in[m] : nullptr;
+    hipError_t e = c->prm.coords == KT_CARTESIAN
+        ? launch(ktm::features_kernel<true>, linear_grid(n), dim3(256), c->stream, c->P, c->E, tau, (long long)n, S, x, y)
+        : launch(ktm::features_kernel<false>, linear_grid(n), dim3(256), c->stream, c->P, c->E, tau, (long long)n, S, x, y);
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "features kernel: %s", hipGetErrorString(e));
+    return KT_OK;
+}
+
+kt_status kt_mlp_fwd(kt_ctx *c, int64_t n, const float *x, float *y, float *act)
+{
+    if (!c) return fail(nullptr, KT_E_ARG, "null context");
+    if (n < 0) return fail(c, KT_E_ARG, "n must be >= 0");
+    if (!c->mlp_ready) return fail(c, KT_E_STATE, "no parameters set");
+    if (n == 0) return KT_OK;
+    if (!x || !y) return fail(c, KT_E_ARG, "null input or output");
+    hipError_t e = launch(ktm::forward_kernel, linear_grid(n), dim3(256), c->stream, (long long)n,
+                          (const float *)c->mlp_w, x, y, act);
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "forward kernel: %s", hipGetErrorString(e));
+    return KT_OK;
+}
+
+kt_status kt_mlp_loss(kt_ctx *c, int64_t n, const float *y, const float *t, const float *w,
+                      float *dy, double *loss)
+{
+    if (!c) return fail(nullptr, KT_E_ARG, "null context");
+    if (n < 1) return fail(c, KT_E_ARG, "n must be >= 1");
+    if (!y || !t) return fail(c, KT_E_ARG, "null outputs or targets");
+    ktm::LossW W;
+    for (int o = 0; o < ktm::NO; ++o) {
+        W.w[o] = w ? (double)w[o] : 1.0;
+        if (!(W.w[o] >= 0.0)) return fail(c, KT_E_ARG, "loss weights must be >= 0");
+    }
+    long long nb = (4 * n + 255) / 256;
+    nb = nb < ktm::LOSS_BLOCKS ? nb : ktm::LOSS_BLOCKS;
+    hipError_t e = launch(ktm::loss_kernel, dim3((unsigned)nb), dim3(256), c->stream, (long long)n, y, t,
+                          W, dy, c->loss_part);
+    if (e == hipSuccess && loss)
+        e = launch(ktm::loss_final_kernel, dim3(1), dim3(64), c->stream, (const double *)c->loss_part,
+                   (int)nb, (long long)n, loss);
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "loss kernel: %s", hipGetErrorString(e));
+    return KT_OK;
+}
+
+kt_status kt_mlp_bwd(kt_ctx *c, int64_t n, const float *x, const float *act, const float *dy,
+                     float *grad)
+{
+    if (!c) return fail(nullptr, KT_E_ARG, "null context");
+    if (n < 1) return fail(c, KT_E_ARG, "n must be >= 1");
+    if (!c->mlp_ready) return fail(c, KT_E_STATE, "no parameters set");
+    if (!x || !act || !dy || !grad) return fail(c, KT_E_ARG, "null argument");
+    long long nb = (n + ktm::BCH - 1) / ktm::BCH;
+    nb = nb < ktm::BWD_BLOCKS ? nb : ktm::BWD_BLOCKS;
+    hipError_t e = launch(ktm::backward_kernel, dim3((unsigned)nb), dim3(256), c->stream, (long long)n,
+                          (const float *)c->mlp_w, x, act, dy, c->mlp_part);
+    if (e == hipSuccess)
+        e = launch(ktm::grad_reduce_kernel, dim3((ktm::NP + 255) / 256), dim3(256), c->stream,
+                   (const float *)c->mlp_part, (int)nb, grad);
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "backward kernel: %s", hipGetErrorString(e));
+    return KT_OK;
+}
+
+kt_status kt_mlp_adam(kt_ctx *c, const float *grad, float lr, float b1, float b2, float eps, int32_t t)
+{
+    if (!c) return fail(nullptr, KT_E_ARG, "null context");
+    if (!c->mlp_ready) return fail(c, KT_E_STATE, "no parameters set");
+    if (!grad || t < 1 || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
+        return fail(c, KT_E_ARG, "invalid Adam arguments");
+    const float c1 = (float)(1.0 - pow((double)b1, (double)t));
+    const float c2 = (float)(1.0 - pow((double)b2, (double)t));
+    hipError_t e = launch(ktm::adam_kernel, dim3((ktm::NP + 255) / 256), dim3(256), c->stream, c->mlp_w,
+                          c->mlp_m, c->mlp_v, grad, lr, b1, b2, eps, c1, c2);
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "adam kernel: %s", hipGetErrorString(e));
     return KT_OK;
 }
 

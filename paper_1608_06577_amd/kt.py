@@ -84,7 +84,11 @@ _lib = None
 #: every function the C ABI exports (the names declared in include/kt.h)
 EXPORTS = ("kt_workspace_bytes", "kt_init", "kt_step", "kt_recover", "kt_observables",
            "kt_profile_enable", "kt_profile_read", "kt_destroy", "kt_last_error",
-           "kt_status_string")
+           "kt_status_string", "kt_set_inv_start", "kt_mlp_set", "kt_mlp_get", "kt_mlp_features",
+           "kt_mlp_fwd", "kt_mlp_loss", "kt_mlp_bwd", "kt_mlp_adam")
+
+KT_START_WARM, KT_START_CONFORMAL, KT_START_LEARNED = 0, 1, 2
+KT_MLP_NPARAMS = 5188
 
 
 # kernel classes of kt_profile (include/kt.h)
@@ -114,8 +118,18 @@ def lib():
         L.kt_status_string.restype = C.c_char_p
         L.kt_profile_enable.argtypes = [C.c_void_p, C.c_int32]
         L.kt_profile_read.argtypes = [C.c_void_p, C.POINTER(KtProfile)]
+        vp = C.c_void_p
+        L.kt_set_inv_start.argtypes = [vp, C.c_int32]
+        L.kt_mlp_set.argtypes = [vp, vp, C.c_int32]
+        L.kt_mlp_get.argtypes = [vp, vp, C.c_int32]
+        L.kt_mlp_features.argtypes = [vp, C.c_int64, C.c_double, vp * 9, vp, vp, vp, vp]
+        L.kt_mlp_fwd.argtypes = [vp, C.c_int64, vp, vp, vp]
+        L.kt_mlp_loss.argtypes = [vp, C.c_int64, vp, vp, C.POINTER(C.c_float), vp, vp]
+        L.kt_mlp_bwd.argtypes = [vp, C.c_int64, vp, vp, vp, vp]
+        L.kt_mlp_adam.argtypes = [vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32]
         for f in ("kt_init", "kt_step", "kt_recover", "kt_observables", "kt_profile_enable",
-                  "kt_profile_read"):
+                  "kt_profile_read", "kt_set_inv_start", "kt_mlp_set", "kt_mlp_get",
+                  "kt_mlp_features", "kt_mlp_fwd", "kt_mlp_loss", "kt_mlp_bwd", "kt_mlp_adam"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -274,6 +288,64 @@ class Solver:
         _check(lib().kt_recover(self.ctx, n, float(tau), arr, C.c_void_p(e.data_ptr()), uarr,
                                 _ptr(it), _ptr(fl)), self.ctx)
         return e, u, it, fl
+
+    # ---------------------------------------------- learned inversion start
+    def set_inv_start(self, start: int):
+        _check(lib().kt_set_inv_start(self.ctx, int(start)), self.ctx)
+
+    def mlp_set(self, params):
+        """params: device float32 tensor of KT_MLP_NPARAMS (W1, b1, W2, b2, W3, b3)."""
+        assert params.dtype == self.torch.float32 and params.numel() == KT_MLP_NPARAMS
+        params = params.contiguous()
+        _check(lib().kt_mlp_set(self.ctx, _ptr(params), KT_MLP_NPARAMS), self.ctx)
+        self.torch.cuda.synchronize(self.device)
+
+    def mlp_get(self):
+        out = self.torch.empty(KT_MLP_NPARAMS, dtype=self.torch.float32, device=self.device)
+        _check(lib().kt_mlp_get(self.ctx, _ptr(out), KT_MLP_NPARAMS), self.ctx)
+        return out
+
+    def mlp_features(self, ins, tau: float, e=None, u=None):
+        """ins: 9 device float64 tensors (n,); e (n,), u (4, n) optional -> x (11, n)[, y (4, n)]."""
+        torch = self.torch
+        n = ins[0].numel()
+        arr = (C.c_void_p * 9)(*[t.data_ptr() if t is not None else None for t in ins])
+        x = torch.empty((11, n), dtype=torch.float32, device=self.device)
+        y = torch.empty((4, n), dtype=torch.float32, device=self.device) if e is not None else None
+        uarr = (C.c_void_p * 4)(*[u[m].data_ptr() for m in range(4)]) if u is not None else None
+        _check(lib().kt_mlp_features(self.ctx, n, float(tau), arr, _ptr(e),
+                                     C.cast(uarr, C.c_void_p) if uarr is not None else None,
+                                     _ptr(x), _ptr(y)), self.ctx)
+        return (x, y) if y is not None else x
+
+    def mlp_fwd(self, x, keep_act=False):
+        """x (11, n) float32 -> y (4, n)[, act (128, n)]."""
+        torch = self.torch
+        n = x.shape[1]
+        y = torch.empty((4, n), dtype=torch.float32, device=self.device)
+        act = torch.empty((128, n), dtype=torch.float32, device=self.device) if keep_act else None
+        _check(lib().kt_mlp_fwd(self.ctx, n, _ptr(x.contiguous()), _ptr(y), _ptr(act)), self.ctx)
+        return (y, act) if keep_act else y
+
+    def mlp_loss(self, y, t, w=None):
+        """-> (loss device float64 scalar tensor, dy (4, n)); w: 4 output weights."""
+        torch = self.torch
+        n = y.shape[1]
+        dy = torch.empty_like(y)
+        loss = torch.empty((), dtype=torch.float64, device=self.device)
+        wp = (C.c_float * 4)(*w) if w is not None else None
+        _check(lib().kt_mlp_loss(self.ctx, n, _ptr(y.contiguous()), _ptr(t.contiguous()), wp,
+                                 _ptr(dy), _ptr(loss)), self.ctx)
+        return loss, dy
+
+    def mlp_bwd(self, x, act, dy):
+        grad = self.torch.empty(KT_MLP_NPARAMS, dtype=self.torch.float32, device=self.device)
+        _check(lib().kt_mlp_bwd(self.ctx, x.shape[1], _ptr(x.contiguous()), _ptr(act.contiguous()),
+                                _ptr(dy.contiguous()), _ptr(grad)), self.ctx)
+        return grad
+
+    def mlp_adam(self, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        _check(lib().kt_mlp_adam(self.ctx, _ptr(grad), lr, b1, b2, eps, int(t)), self.ctx)
 
     def profile(self, on: bool):
         _check(lib().kt_profile_enable(self.ctx, int(on)), self.ctx)

@@ -98,3 +98,27 @@ def test_init_rejects_bad_arguments_without_device_work(L):
     assert L.kt_observables(None, None, None) == kt.KT_E_ARG
     L.kt_destroy(None)
     assert L.kt_status_string(kt.KT_E_ALLOC) == b"workspace too small"
+
+
+def test_learned_start_entry_points_reject_null_context(L):
+    """Argument marshalling of every learned-start entry point, nullable
+    arguments given as null: each rejects the null context before any device
+    work."""
+    vp = C.c_void_p
+    arr9 = (vp * 9)()
+    u4 = C.cast((vp * 4)(), vp)
+    w4 = (C.c_float * 4)(1.0, 0.5, 0.5, 0.5)
+    calls = [
+        L.kt_set_inv_start(None, kt.KT_START_LEARNED),
+        L.kt_mlp_set(None, None, kt.KT_MLP_NPARAMS),
+        L.kt_mlp_get(None, None, kt.KT_MLP_NPARAMS),
+        L.kt_mlp_features(None, 4, 1.0, arr9, None, None, None, None),
+        L.kt_mlp_features(None, 4, 1.0, arr9, None, u4, None, None),
+        L.kt_mlp_fwd(None, 4, None, None, None),
+        L.kt_mlp_loss(None, 4, None, None, None, None, None),
+        L.kt_mlp_loss(None, 4, None, None, w4, None, None),
+        L.kt_mlp_bwd(None, 4, None, None, None, None),
+        L.kt_mlp_adam(None, None, 1e-3, 0.9, 0.999, 1e-8, 1),
+    ]
+    assert all(c == kt.KT_E_ARG for c in calls), calls
+    assert b"null context" in L.kt_last_error(None)

@@ -88,17 +88,19 @@ def test_backward_matches_finite_differences():
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])), (k, fd, g[k])
 
 
-def test_loss_gradient():
+@pytest.mark.parametrize("w", [None, (1.0, 0.1, 0.2, 0.05)])
+def test_loss_gradient(w):
     rng = np.random.default_rng(2)
     y, t = rng.standard_normal((5, 4)), rng.standard_normal((5, 4))
-    L, dy = M.loss_and_grad(y, t)
-    assert abs(L - np.mean((y - t) ** 2)) < 1e-15
+    L, dy = M.loss_and_grad(y, t, w)
+    wt = np.ones(4) if w is None else np.array(w)
+    assert abs(L - sum(wt[o] * np.sum((y[:, o] - t[:, o]) ** 2) for o in range(4)) / 20) < 1e-15
     h = 1e-6
     for k in range(20):
         yp, ym = y.copy(), y.copy()
         yp.flat[k] += h
         ym.flat[k] -= h
-        fd = (M.loss_and_grad(yp, t)[0] - M.loss_and_grad(ym, t)[0]) / (2 * h)
+        fd = (M.loss_and_grad(yp, t, w)[0] - M.loss_and_grad(ym, t, w)[0]) / (2 * h)
         assert abs(fd - dy.flat[k]) < 1e-9
 
 
@@ -132,16 +134,22 @@ def test_features_and_targets_of_known_states(oracle_lib):
     assert np.allclose(x[:, 8], np.log(e) / 10, rtol=0, atol=1e-15)
     assert np.array_equal(x[:, 9], cs2) and np.allclose(x[:, 10], p / e, rtol=1e-15)
     u = np.tile([1.0, 0.0, 0.0, 0.0], (4, 1))
-    assert np.allclose(M.targets(tau, False, q9, e, u), np.tile([1.0, 0, 0, 0], (4, 1)), atol=1e-15)
+    assert np.allclose(M.targets(tau, False, q9, e, u, 1e-9), np.tile([1.0, 0, 0, 0], (4, 1)), atol=1e-15)
     # moving viscous states: targets of the recovered state equal those of the primitives
     ev, uv, pi, Pi = random_state(tau, 200, u_scale=1.2)
     q = oracle.tmunu(phys, eos, tau, ev, uv, pack_pi(pi), Pi)
     q9 = q[:, [0, 1, 2, 3, 4, 5, 6, 7, 14]]
     er, ur, _, fl = oracle.recover(phys, eos, tau, q)
     assert np.all(fl == 0)
-    t_rec = M.targets(tau, False, q9, er, ur)
+    t_rec = M.targets(tau, False, q9, er, ur, 1e-9)
+    # conformal root of the same (E, M): for p = e/3, e = E - M^2/(E + e/3) is a
+    # quadratic whose positive root is sqrt(4E^2 - 3M^2) - E
     E = q[:, 0] - q[:, 4]
-    t_true = np.stack([ev / E, uv[:, 1] / uv[:, 0], uv[:, 2] / uv[:, 0], tau * uv[:, 3] / uv[:, 0]], 1)
+    Ml = np.stack([q[:, 1] - q[:, 5], q[:, 2] - q[:, 6], q[:, 3] - q[:, 7]], 1)
+    M2 = Ml[:, 0] ** 2 + Ml[:, 1] ** 2 + tau * tau * Ml[:, 2] ** 2
+    ec = M.conformal_root(tau, False, q9, 1e-9)
+    assert np.max(np.abs(ec - (E - M2 / (E + ec / 3.0))) / ec) < 1e-13
+    t_true = np.stack([ev / ec, uv[:, 1] / uv[:, 0], uv[:, 2] / uv[:, 0], tau * uv[:, 3] / uv[:, 0]], 1)
     assert np.max(np.abs(t_rec - t_true)) < 1e-12
     # x_0 = T^{tau x}/T^{tau tau} with T^{tau mu} = (e + P) u^tau u^mu - P g^{tau mu} + pi^{tau mu}
     x = M.features(tau, False, q9, eos)
