@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (for counter scaling)")
     ap.add_argument("--n", type=int, default=128, help="grid cells per axis")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-events leg")
     return ap.parse_args()
 
 
@@ -149,6 +150,44 @@ def main():
                             newton_iters_per_face_state=obs["newton_iters_faces"] / max(1, obs["n_recover_faces"])),
     }
     solver.close()
+    # the mixed-precision state on the same event and step count (reported beside the FP64 line)
+    cfg_m = dict(w.config)
+    cfg_m["mixed"] = True
+    sm = kt.Solver(w.grid, cfg_m, w.eos, w.prims, device="cuda:0")
+    sm.step(args.warmup)
+    torch.cuda.synchronize()
+    start.record()
+    sm.step(args.steps)
+    stop.record()
+    torch.cuda.synchronize()
+    ms_m = start.elapsed_time(stop) / args.steps
+    rec["variants"] = {"mixed_precision": {
+        "ms_per_step": ms_m, "value": ncell / (ms_m * 1e-3),
+        "state": "T^{tau mu} FP64; pi, Pi, e, p, u, face speeds FP32; inversion FP64"}}
+    sm.close()
+    print("bench: mixed precision %.3f ms/step" % ms_m, file=sys.stderr, flush=True)
+    if not args.no_batch:
+        # 48 hot-spot events on uneven grids, FP32 state, one launch per kernel for all
+        # events, one step replayed as a hipGraph, flux tiling autotuned per grid shape
+        evs = I.workload_batch()
+        ncb = sum(e.grid.ncells for e in evs)
+        batch = kt.Batch([(e.grid, e.config, e.prims) for e in evs], evs[0].eos, device="cuda:0")
+        del evs
+        kc = batch.tune()
+        batch.step(args.warmup)
+        torch.cuda.synchronize()
+        start.record()
+        batch.step(args.steps)
+        stop.record()
+        torch.cuda.synchronize()
+        ms_b = start.elapsed_time(stop) / args.steps
+        rec["variants"]["batch_48_events"] = {
+            "ms_per_step": ms_b, "value": ncb / (ms_b * 1e-3), "cells": ncb,
+            "shapes": [list(s) for s in I.BATCH_SHAPES], "flux_eta_planes": sorted(set(kc)),
+            "state": "mixed precision; all events per launch; step replayed as a hipGraph"}
+        batch.close()
+        print("bench: batch of 48 events %.3f ms/step (%.3g cell-updates/s)" % (ms_b, ncb / (ms_b * 1e-3)),
+              file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("bench: CPU oracle baseline (bounded sample)", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

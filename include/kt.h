@@ -62,7 +62,7 @@ typedef enum {
     KT_E_UNSUPPORTED = 5   /* valid request this build does not implement */
 } kt_status;
 
-enum { KT_FP64 = 0, KT_MIXED = 1 };
+enum { KT_FP64 = 0, KT_MIXED = 1 };           /* kt_params.precision */
 enum { KT_MILNE = 0, KT_CARTESIAN = 1 };       /* Cartesian: metric diag(1,-1,-1,-1), no geometric sources (Sec. 5.1) */
 enum { KT_BC_OUTFLOW = 0, KT_BC_PERIODIC = 1 };
 
@@ -99,7 +99,10 @@ typedef struct {
     int32_t floor_resets_q;        /* a cell put on the floor gets q = (e_floor,0,0,0; 0; 0) */
     double newton_tol;             /* stop when |f(e)| <= newton_tol * E, then one more step */
     int32_t newton_max;            /* Newton iterations before the bisection fallback */
-    int32_t precision;             /* KT_FP64 (KT_MIXED: KT_E_UNSUPPORTED in this build) */
+    int32_t precision;             /* KT_FP64, or KT_MIXED: T^{tau mu} stored and accumulated in
+                                    * FP64; pi, Pi, e, p, u and face speeds stored in FP32, flux
+                                    * and source arithmetic in FP32, inversion and regulator in
+                                    * FP64 */
 } kt_params;
 
 /* Initial data on the device.  Either q[0..14] (conserved form; all 15
@@ -154,7 +157,7 @@ size_t kt_workspace_bytes(const kt_params *p, const kt_eos *eos);
  * kt_workspace_bytes(p, eos), 256-byte aligned.  Synchronises stream.
  * Errors: KT_E_ARG (sizes, spacings, theta outside [1,2], tau0 <= 0 in
  * Milne, dtau <= 0, e_floor <= 0, table with n < 2, null pointers),
- * KT_E_ALLOC (workspace too small), KT_E_UNSUPPORTED (precision), KT_E_HIP. */
+ * KT_E_ALLOC (workspace too small), KT_E_HIP. */
 kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0,
                   void *d_ws, size_t ws_bytes, hipStream_t stream, kt_ctx **out);
 
@@ -259,6 +262,37 @@ typedef struct {
 
 kt_status kt_profile_enable(kt_ctx *c, int32_t on);
 kt_status kt_profile_read(kt_ctx *c, kt_profile *out);
+
+/* ---------------------------------------------------------------------
+ * Batches of events.  n_events events (each its own grid and initial state;
+ * the same coordinates, precision, tau0 and dtau) are advanced together:
+ * every kernel of a Heun step is one launch over the tiles of all events,
+ * and one step is captured once as a hipGraph and replayed.  Results equal
+ * those of separate contexts bit for bit.  Newton starts from the warm
+ * start (the cell's e before the stage).
+ *
+ * Workspace: kt_batch_workspace_bytes(p, n, eos) bytes (256-byte aligned,
+ * caller-owned, must outlive the batch), holding every event's workspace,
+ * the batch time and the per-event launch tables.  p and s0 are arrays of
+ * n_events entries; kt_batch_init synchronises the stream.
+ * kt_batch_step enqueues n_steps steps (asynchronous; the graph runs on a
+ * stream of the batch ordered after and before the caller's stream).
+ * kt_batch_tune times the flux kernel of every distinct grid shape with 1,
+ * 2, 4 and 8 eta planes per block on the live state (which it does not
+ * change), keeps the fastest (kc_out[n_events], nullable) and synchronises.
+ * kt_batch_observables is kt_observables of one event.
+ * --------------------------------------------------------------------- */
+typedef struct kt_batch kt_batch;
+
+size_t kt_batch_workspace_bytes(const kt_params *p, int32_t n_events, const kt_eos *eos);
+kt_status kt_batch_init(const kt_params *p, int32_t n_events, const kt_eos *eos,
+                        const kt_init_state *s0, void *d_ws, size_t ws_bytes, hipStream_t stream,
+                        kt_batch **out);
+kt_status kt_batch_step(kt_batch *b, int32_t n_steps);
+kt_status kt_batch_tune(kt_batch *b, int32_t *kc_out);
+kt_status kt_batch_observables(kt_batch *b, int32_t event, kt_obs *host_out, const kt_fields *dev_out);
+void kt_batch_destroy(kt_batch *b);
+const char *kt_batch_last_error(const kt_batch *b);
 
 /* Release the context (not the workspace).  Null is allowed. */
 void kt_destroy(kt_ctx *c);

@@ -312,14 +312,17 @@ __device__ __forceinline__ double regulate(const Phys &P, double tau, double q[N
 
 // ---------------------------------------------------------------- minmod --
 // generalized minmod of Sec. 3.1 on undivided differences; sgn(0) = 0.
-__device__ __forceinline__ double mm2(double x, double y)
+// R is the arithmetic type (double, or float for the mixed-precision state).
+template <typename R>
+__device__ __forceinline__ R mm2(R x, R y)
 {
-    return (copysign(0.5, x) + copysign(0.5, y)) * fmin(fabs(x), fabs(y));
+    return (copysign(R(0.5), x) + copysign(R(0.5), y)) * fmin(fabs(x), fabs(y));
 }
 
-__device__ __forceinline__ double slope(double qm, double q0, double qp, double theta)
+template <typename R>
+__device__ __forceinline__ R slope(R qm, R q0, R qp, R theta)
 {
-    return mm2(theta * (q0 - qm), mm2(0.5 * (qp - qm), theta * (qp - q0)));
+    return mm2(theta * (q0 - qm), mm2(R(0.5) * (qp - qm), theta * (qp - q0)));
 }
 
 // ------------------------------------------------- relaxation sources ----
@@ -331,40 +334,41 @@ __device__ __forceinline__ double slope(double qm, double q0, double qp, double 
 // G^{mu nu} = u^a Gamma^mu_{ab} pi^{b nu} + (mu <-> nu).
 // C[a][m] = partial_a u^m on entry (a: tau, x, y, eta); pv holds the ten pi
 // components in the order of q (pi^{tau tau} first).  Each result is handed
-// to emit(c, q_c, J_c) as soon as it is known (c: index in q).
-template <bool CART, typename Emit>
-__device__ __forceinline__ void relaxation_sources(const Phys &P, double tau, const double pv[10],
-                                                   double Pi, double e, double p0, double cs2,
-                                                   double T, const double u[4], double C[4][4],
-                                                   double divv, Emit &&emit)
+// to emit(c, q_c, J_c) as soon as it is known (c: index in q).  Arithmetic
+// in R.
+template <bool CART, typename R, typename Emit>
+__device__ __forceinline__ void relaxation_sources(const Phys &P, double tau_d, const R pv[10],
+                                                   R Pi, R e, R p0, R cs2, R T, const R u[4],
+                                                   R C[4][4], R divv, Emit &&emit)
 {
-    const double g33 = CART ? 1.0 : tau * tau;
-    const double inv_tau = 1.0 / tau;
-    const double glo[4] = {1.0, -1.0, -1.0, -g33};
-    const double ghi[4] = {1.0, -1.0, -1.0, -1.0 / g33};
+    const R tau = R(tau_d);
+    const R g33 = CART ? R(1) : tau * tau;
+    const R inv_tau = R(1) / tau;
+    const R glo[4] = {R(1), R(-1), R(-1), -g33};
+    const R ghi[4] = {R(1), R(-1), R(-1), R(-1) / g33};
     // covariant derivative C[a][m] = u^m_{;a}
     if (!CART) {
         C[3][0] += tau * u[3];          // Gamma^tau_{eta eta} u^eta
         C[0][3] += u[3] * inv_tau;      // Gamma^eta_{tau eta} u^eta
         C[3][3] += u[0] * inv_tau;      // Gamma^eta_{eta tau} u^tau
     }
-    const double th = C[0][0] + C[1][1] + C[2][2] + C[3][3];
-    double Du[4], Dl[4];
+    const R th = C[0][0] + C[1][1] + C[2][2] + C[3][3];
+    R Du[4], Dl[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         Du[m] = u[0] * C[0][m] + u[1] * C[1][m] + u[2] * C[2][m] + u[3] * C[3][m];
         Dl[m] = glo[m] * Du[m];
     }
     // sigma (10) and omega (6) from nabla^m u^n = g^{mm} C[m][n] - u^m D u^n
-    double sg[10], om[6];
+    R sg[10], om[6];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int n = m; n < 4; ++n) {
-            const double a = ghi[m] * C[m][n] - u[m] * Du[n];
-            const double b = ghi[n] * C[n][m] - u[n] * Du[m];
-            const double Dmn = (m == n ? ghi[m] : 0.0) - u[m] * u[n];
-            sg[pi_index(m, n) - PTT] = 0.5 * (a + b) - th * (1.0 / 3.0) * Dmn;
+            const R a = ghi[m] * C[m][n] - u[m] * Du[n];
+            const R b = ghi[n] * C[n][m] - u[n] * Du[m];
+            const R Dmn = (m == n ? ghi[m] : R(0)) - u[m] * u[n];
+            sg[pi_index(m, n) - PTT] = R(0.5) * (a + b) - th * R(1.0 / 3.0) * Dmn;
         }
     // antisymmetric part, stored for m < n in the order (01, 02, 03, 12, 13, 23)
     {
@@ -373,69 +377,70 @@ __device__ __forceinline__ void relaxation_sources(const Phys &P, double tau, co
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int n = m + 1; n < 4; ++n) {
-                const double a = ghi[m] * C[m][n] - u[m] * Du[n];
-                const double b = ghi[n] * C[n][m] - u[n] * Du[m];
-                om[k++] = 0.5 * (a - b);
+                const R a = ghi[m] * C[m][n] - u[m] * Du[n];
+                const R b = ghi[n] * C[n][m] - u[n] * Du[m];
+                om[k++] = R(0.5) * (a - b);
             }
     }
-    auto SG = [&](int m, int n) -> double { return sg[pi_index(m, n) - PTT]; };
-    auto OM = [&](int m, int n) -> double {
-        if (m == n) return 0.0;
+    auto SG = [&](int m, int n) -> R { return sg[pi_index(m, n) - PTT]; };
+    auto OM = [&](int m, int n) -> R {
+        if (m == n) return R(0);
         const int a = m < n ? m : n, b = m < n ? n : m;
         const int k = a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
         return m < n ? om[k] : -om[k];
     };
-    auto PI = [&](int m, int n) -> double { return pv[pi_index(m, n) - PTT]; };
-    double pis = 0.0;   // pi^{mu nu} sigma_{mu nu}
+    auto PI = [&](int m, int n) -> R { return pv[pi_index(m, n) - PTT]; };
+    R pis = R(0);   // pi^{mu nu} sigma_{mu nu}
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int n = m; n < 4; ++n)
-            pis += (m == n ? 1.0 : 2.0) * glo[m] * glo[n] * PI(m, n) * SG(m, n);
-    const double inv_ut = 1.0 / u[0];
+            pis += (m == n ? R(1) : R(2)) * glo[m] * glo[n] * PI(m, n) * SG(m, n);
+    const R inv_ut = R(1) / u[0];
 
     if (P.shear) {
-        double av[4];   // a^m = pi^{m l} D u_l
+        R av[4];   // a^m = pi^{m l} D u_l
 #pragma unroll
         for (int m = 0; m < 4; ++m)
             av[m] = PI(m, 0) * Dl[0] + PI(m, 1) * Dl[1] + PI(m, 2) * Dl[2] + PI(m, 3) * Dl[3];
-        const double inv_tpi = T / (5.0 * P.eta_s);
-        const double eta_tpi = (e + p0) * 0.2;
-        const double h03 = CART ? 0.0 : tau * u[3];     // u^a Gamma^tau_{a eta}
-        const double h30 = CART ? 0.0 : u[3] * inv_tau; // u^a Gamma^eta_{a tau}
-        const double h33 = CART ? 0.0 : u[0] * inv_tau; // u^a Gamma^eta_{a eta}
+        const R inv_tpi = T / (R(5) * R(P.eta_s));
+        const R eta_tpi = (e + p0) * R(0.2);
+        const R h03 = CART ? R(0) : tau * u[3];     // u^a Gamma^tau_{a eta}
+        const R h30 = CART ? R(0) : u[3] * inv_tau; // u^a Gamma^eta_{a tau}
+        const R h33 = CART ? R(0) : u[0] * inv_tau; // u^a Gamma^eta_{a eta}
+        const R taupipi = R(P.taupipi);
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int n = m; n < 4; ++n) {
-                double I3 = 0.0, c4 = 0.0;
+                R I3 = R(0), c4 = R(0);
 #pragma unroll
                 for (int l = 0; l < 4; ++l) {
                     // pi^{m l} g_ll omega^{n l} + (m <-> n);  pi^{m l} g_ll sigma^{n l} + (m <-> n)
                     I3 += glo[l] * (PI(m, l) * OM(n, l) + PI(n, l) * OM(m, l));
                     c4 += glo[l] * (PI(m, l) * SG(n, l) + PI(n, l) * SG(m, l));
                 }
-                const double I1 = u[n] * av[m] + u[m] * av[n];
-                const double I4 = 0.5 * c4 - ((m == n ? ghi[m] : 0.0) - u[m] * u[n]) * pis * (1.0 / 3.0);
-                const double s = SG(m, n), pmn = PI(m, n);
-                const double Ipi = I1 + (4.0 / 3.0) * th * pmn - I3 + P.taupipi * I4 - 1.2 * Pi * s;
-                double G = 0.0;
+                const R I1 = u[n] * av[m] + u[m] * av[n];
+                const R I4 = R(0.5) * c4 - ((m == n ? ghi[m] : R(0)) - u[m] * u[n]) * pis * R(1.0 / 3.0);
+                const R s = SG(m, n), pmn = PI(m, n);
+                const R Ipi = I1 + R(4.0 / 3.0) * th * pmn - I3 + taupipi * I4 - R(1.2) * Pi * s;
+                R G = R(0);
                 if (!CART) {
-                    const double hm = (m == 0 ? h03 * PI(3, n) : 0.0)
-                                    + (m == 3 ? h30 * PI(0, n) + h33 * PI(3, n) : 0.0);
-                    const double hn = (n == 0 ? h03 * PI(3, m) : 0.0)
-                                    + (n == 3 ? h30 * PI(0, m) + h33 * PI(3, m) : 0.0);
+                    const R hm = (m == 0 ? h03 * PI(3, n) : R(0))
+                               + (m == 3 ? h30 * PI(0, n) + h33 * PI(3, n) : R(0));
+                    const R hn = (n == 0 ? h03 * PI(3, m) : R(0))
+                               + (n == 3 ? h30 * PI(0, m) + h33 * PI(3, m) : R(0));
                     G = hm + hn;
                 }
-                const double rhs = 2.0 * eta_tpi * s - pmn * inv_tpi - Ipi - G;
+                const R rhs = R(2) * eta_tpi * s - pmn * inv_tpi - Ipi - G;
                 emit(pi_index(m, n), pmn, rhs * inv_ut + pmn * divv);
             }
     }
     if (P.bulk) {
-        const double d = 1.0 / 3.0 - cs2;
-        const double inv_tPi = 15.0 * d * T / P.zeta_coef;
-        const double zeta_tPi = 15.0 * d * d * (e + p0);
-        const double IPi = (2.0 / 3.0) * Pi * th - 1.6 * d * pis;
+        const R d = R(1.0 / 3.0) - cs2;
+        const R inv_tPi = R(15) * d * T / R(P.zeta_coef);
+        const R zeta_tPi = R(15) * d * d * (e + p0);
+        const R IPi = R(2.0 / 3.0) * Pi * th - R(1.6) * d * pis;
         emit(BPI, Pi, (-zeta_tPi * th - Pi * inv_tPi - IPi) * inv_ut + Pi * divv);
     }
 }

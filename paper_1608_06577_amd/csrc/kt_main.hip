@@ -38,36 +38,54 @@ constexpr int KC = 4;      // consecutive eta planes per thread in flux_kernel (
 
 // ------------------------------------------------------------------ grid --
 
-struct Fields {       // base pointers; component c of an array is base + c * stride
-    const double *q;
-    const double *e;
-    const double *p;
+// Field pointers of one stage.  T^{tau mu} and u^mu are always FP64; the
+// other components (pi, Pi), e, p and the face speeds have the storage type S
+// (double, or float for the mixed-precision state).  u stays FP64 because
+// the sources take differences of it (the backward difference in tau and
+// central differences in space) that cancel several digits.  Component c of
+// an array is at base + c * stride; qP holds q's components 4..14.
+template <typename S>
+struct Fields {
+    const double *qT;
+    const S *qP;
+    const S *e;
+    const S *p;
     const double *u;
     const double *up;
-    const double *vf;     // face speeds: v^-, v^+ per face, x, y and eta face arrays (see FaceGeo)
+    const S *vf;     // face speeds: v^-, v^+ per face, x, y and eta face arrays (see FaceGeo)
 };
 
 // Face arrays: the x faces of row (j,k) are i = 0..nx (face i lies between
 // cells i-1 and i), likewise for y and eta; each face holds v^- and v^+ of
-// its axis.  Offsets into Fields::vf, in doubles.
+// its axis.  Offsets into Fields::vf, in elements.
 struct FaceGeo {
     long long nfx, nfy, nfe;          // faces per axis
     long long ox, oy, oe;             // offsets of the three arrays (v^- block then v^+ block)
 };
 
-// Cell and face indices are 32-bit; a load adds the byte offset idx*8 to a
-// per-component base pointer that is uniform across the wavefront (kept in
-// scalar registers), so no 64-bit address is formed per lane.
+// Cell and face indices are 32-bit; a load adds the byte offset
+// idx*sizeof(T) to a per-component base pointer that is uniform across the
+// wavefront (kept in scalar registers), so no 64-bit address is formed per
+// lane.
 typedef uint32_t idx_t;
 
-__device__ __forceinline__ double ld(const double *base, idx_t i)
+template <typename T>
+__device__ __forceinline__ T ld(const T *base, idx_t i)
 {
-    return *(const double *)((const char *)base + (size_t)(i << 3));
+    return *(const T *)((const char *)base + (size_t)(i * (idx_t)sizeof(T)));
 }
 
-__device__ __forceinline__ void st(double *base, idx_t i, double v)
+template <typename T>
+__device__ __forceinline__ void st(T *base, idx_t i, T v)
 {
-    *(double *)((char *)base + (size_t)(i << 3)) = v;
+    *(T *)((char *)base + (size_t)(i * (idx_t)sizeof(T))) = v;
+}
+
+// component c (0..14) of q given as its FP64 part qT (0..3) and qP (4..14)
+template <typename S>
+__device__ __forceinline__ double ldq(const double *qT, const S *qP, int c, idx_t SS, idx_t s)
+{
+    return c < PTT ? ld(qT, (idx_t)c * SS + s) : (double)ld(qP, (idx_t)(c - PTT) * SS + s);
 }
 
 __host__ __device__ __forceinline__ idx_t fidx_x(int nx, int ny, int i, int j, int k)
@@ -122,14 +140,19 @@ __device__ __forceinline__ idx_t udiv(idx_t t, idx_t d, double inv_d)
     return q;
 }
 
-// counters: lane 0 of each wave adds the wave's totals to its own slot row
-__device__ __forceinline__ void slot_add(unsigned long long *slots, long long wave, int which,
-                                         long long v)
+// counters: the wave's total of a small non-negative integer v < 2^nbits,
+// summed bit by bit from ballots (no cross-lane shuffles); lane 0 adds it to
+// the wave's own slot row
+__device__ __forceinline__ void slot_add(unsigned long long *slots, long long wave, int which, int v,
+                                         int nbits = 1)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if ((threadIdx.x & 63) == 0 && v != 0) slots[wave * C_COUNT + which] += (unsigned long long)v;
+    unsigned long long tot = 0;
+    for (int b = 0; b < nbits; ++b) tot += (unsigned long long)__popcll(__ballot((v >> b) & 1)) << b;
+    if ((threadIdx.x & 63) == 0 && tot != 0) slots[wave * C_COUNT + which] += tot;
 }
+
+// bits needed for Newton iteration counts (at most newton_max)
+__device__ __forceinline__ int iter_bits(const Phys &P) { return 32 - __clz(P.newton_max); }
 
 // ------------------------------------------------------------ KT flux ----
 // One face between the cells s1 (left) and s2 (right) with outer neighbours
@@ -137,13 +160,14 @@ __device__ __forceinline__ void slot_add(unsigned long long *slots, long long wa
 // q^- = q_L + slope_L/2 and q^+ = q_R - slope_R/2, the inversion of both
 // (face_speeds_kernel; Sec. 3.1 last paragraph), the local speed
 // a = max(|v^-|, |v^+|) and H = (v^+ q^+ + v^- q^-)/2 - a (q^+ - q^-)/2.
-__device__ __forceinline__ double face_H(const double *q, idx_t co, double theta, idx_t s0, idx_t s1,
-                                         idx_t s2, idx_t s3, double vm, double vp, double a)
+template <typename R, typename T>
+__device__ __forceinline__ R face_H(const T *q, idx_t co, R theta, idx_t s0, idx_t s1, idx_t s2,
+                                    idx_t s3, R vm, R vp, R a)
 {
-    const double a0 = ld(q, co + s0), a1 = ld(q, co + s1), a2 = ld(q, co + s2), a3 = ld(q, co + s3);
-    const double qm = a1 + 0.5 * slope(a0, a1, a2, theta);
-    const double qp = a2 - 0.5 * slope(a1, a2, a3, theta);
-    return 0.5 * (vp * qp + vm * qm) - 0.5 * a * (qp - qm);
+    const R a0 = R(ld(q, co + s0)), a1 = R(ld(q, co + s1)), a2 = R(ld(q, co + s2)), a3 = R(ld(q, co + s3));
+    const R qm = a1 + R(0.5) * slope(a0, a1, a2, theta);
+    const R qp = a2 - R(0.5) * slope(a1, a2, a3, theta);
+    return R(0.5) * (vp * qp + vm * qm) - R(0.5) * a * (qp - qm);
 }
 
 // Face speeds (Sec. 3.1, last paragraph): every face of the grid has two
@@ -159,18 +183,18 @@ struct FaceLaunch {
     double inv_nx1, inv_nx, inv_ny1, inv_plane;   // 1/(nx+1), 1/nx, 1/(ny+1), 1/(nx ny)
 };
 
-template <bool CART>
-__global__ __launch_bounds__(256) void face_speeds_kernel(Phys P, Eos E, FaceGeo G, FaceLaunch L,
-                                                          double tau, const double *q,
-                                                          const double *e, double *vf,
-                                                          unsigned long long *slots)
+// b: the block within this event's launch; wave: its counter slot row
+template <bool CART, typename S>
+__device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, const FaceGeo G,
+                                                 const FaceLaunch L, double tau, const double *qT,
+                                                 const S *qP, const S *e, S *vf,
+                                                 unsigned long long *slots, unsigned b, long long wave)
 {
-    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    typedef S R;   // reconstruction arithmetic; the inversion itself is FP64
     int seg = 0;
 #pragma unroll
     for (int t = 1; t < 6; ++t) seg += b >= L.first_block[t] ? 1 : 0;
     const int d = seg >> 1, side = seg & 1;     // side 0: q^-, side 1: q^+
-    const long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
     const idx_t t = (idx_t)(b - L.first_block[seg]) * 256 + threadIdx.x;
     const long long nf = d == 0 ? G.nfx : (d == 1 ? G.nfy : G.nfe);
     int it = 0, fl = 0;
@@ -206,27 +230,45 @@ __global__ __launch_bounds__(256) void face_speeds_kernel(Phys P, Eos E, FaceGeo
         const idx_t sm = base + (idx_t)wrap(c - 1, n, per) * step;
         const idx_t s0 = base + (idx_t)wrap(c, n, per) * step;
         const idx_t sp = base + (idx_t)wrap(c + 1, n, per) * step;
-        const double h = side ? -0.5 : 0.5;
+        const R h = side ? R(-0.5) : R(0.5);
+        const R theta = R(P.theta);
         const idx_t SS = (idx_t)P.stride;
         double m[9];
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
-            const idx_t co = (idx_t)(r < 8 ? r : BPI) * SS;
-            const double a0 = ld(q, co + sm), a1 = ld(q, co + s0), a2 = ld(q, co + sp);
-            m[r] = a1 + h * slope(a0, a1, a2, P.theta);
+            R a0, a1, a2;
+            if (r < 4) {
+                const idx_t co = (idx_t)r * SS;
+                a0 = R(ld(qT, co + sm)); a1 = R(ld(qT, co + s0)); a2 = R(ld(qT, co + sp));
+            } else {
+                const idx_t co = (idx_t)(r < 8 ? r - PTT : BPI - PTT) * SS;
+                a0 = R(ld(qP, co + sm)); a1 = R(ld(qP, co + s0)); a2 = R(ld(qP, co + sp));
+            }
+            m[r] = (double)(a1 + h * slope(a0, a1, a2, theta));
         }
         // v^d = u^d / u^tau = M^d / (E + P) (Sec. 2.4), 0 on the floor
         double ee, pe, EE, M[3];
         const double Pi = P.bulk ? m[8] : 0.0;
         fl = invert_core<CART>(P, E, tau, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], Pi,
-                               ld(e, s0), ee, pe, EE, M, it);
-        const double v = (fl & F_FLOOR) ? 0.0 : M[d] / (EE + pe + Pi);
+                               (double)ld(e, s0), ee, pe, EE, M, it);
+        const double Md = d == 0 ? M[0] : (d == 1 ? M[1] : M[2]);
+        const double v = (fl & F_FLOOR) ? 0.0 : Md / (EE + pe + Pi);
         const long long off = (d == 0 ? G.ox : (d == 1 ? G.oy : G.oe)) + (side ? nf : 0);
-        st(vf + off, t, v);
+        st(vf + off, t, (S)v);
     }
-    slot_add(slots, wave, C_ITERS_FACES, it);
+    slot_add(slots, wave, C_ITERS_FACES, it, iter_bits(P));
     slot_add(slots, wave, C_REC_FACES, valid ? 1 : 0);
     slot_add(slots, wave, C_FALLBACK_FACES, (fl & F_FALLBACK) ? 1 : 0);
+}
+
+template <bool CART, typename S>
+__global__ __launch_bounds__(256) void face_speeds_kernel(Phys P, Eos E, FaceGeo G, FaceLaunch L,
+                                                          double tau, const double *qT, const S *qP,
+                                                          const S *e, S *vf,
+                                                          unsigned long long *slots)
+{
+    face_speeds_body<CART, S>(P, E, G, L, tau, qT, qP, e, vf, slots, xcd_block(blockIdx.x, gridDim.x),
+                              (long long)blockIdx.x * 4 + (threadIdx.x >> 6));
 }
 
 static FaceLaunch face_launch(const FaceGeo &G, int nx, int ny)
@@ -249,37 +291,39 @@ static FaceLaunch face_launch(const FaceGeo &G, int nx, int ny)
 // A^{i nu} = T^{i nu} - v^i T^{tau nu} of one cell for axis i = d+1 (Eqs. Ttt-Tij):
 //   A^{i tau} = P v^i + pi^{i tau} - v^i pi^{tau tau}
 //   A^{i j}   = -P g^{ij} + pi^{ij} - v^i pi^{tau j}
-template <bool CART>
-__device__ __forceinline__ void nonadvective_row(const Phys &P, double tau, const Fields &F,
+// (FP64: it feeds the conservation law, whose central differences cancel digits)
+template <bool CART, typename S>
+__device__ __forceinline__ void nonadvective_row(const Phys &P, double tau, const Fields<S> &F,
                                                  idx_t SS, idx_t s, int d, double A[4])
 {
-    const double Pc = ld(F.p, s) + (P.bulk ? ld(F.q, (idx_t)(BPI) * SS + s) : 0.0);
-    const double v = ld(F.u, (idx_t)((d + 1)) * SS + s) / ld(F.u, s);
+    const double Pc = (double)ld(F.p, s) + (P.bulk ? (double)ld(F.qP, (idx_t)(BPI - PTT) * SS + s) : 0.0);
+    const double v = ld(F.u, (idx_t)(d + 1) * SS + s) / ld(F.u, s);
     const int ii = d + 1;
     const double gii = ii == 3 ? (CART ? -1.0 : -1.0 / (tau * tau)) : -1.0;
     A[0] = Pc * v;
 #pragma unroll
     for (int n = 1; n < 4; ++n) A[n] = n == ii ? -Pc * gii : 0.0;
     if (P.shear) {
-        A[0] += ld(F.q, (idx_t)pi_index(ii, 0) * SS + s) - v * ld(F.q, (idx_t)(PTT) * SS + s);
+        auto pi = [&](int c) -> double { return (double)ld(F.qP, (idx_t)(c - PTT) * SS + s); };
+        A[0] += pi(pi_index(ii, 0)) - v * pi(PTT);
 #pragma unroll
-        for (int n = 1; n < 4; ++n)
-            A[n] += ld(F.q, (idx_t)pi_index(ii, n) * SS + s) - v * ld(F.q, (idx_t)pi_index(0, n) * SS + s);
+        for (int n = 1; n < 4; ++n) A[n] += pi(pi_index(ii, n)) - v * pi(pi_index(0, n));
     }
 }
 
 // Sources part of one Euler stage (Sec. 3.1, Eq. semiDiscreteKT, and
 // App. B), one thread per cell:
 //   stage 1: out = q + dtau J;   stage 2: out = qn + q + dtau J,
-// J = S_c + G_c for T^{tau nu} and the relaxation terms for pi and Pi.
+// J = S_c + G_c for T^{tau mu} and the relaxation terms for pi and Pi.
 // flux_kernel then adds the flux divergence and completes the stage.  Each
-// component is written as soon as its J is known.
-template <bool CART, bool STAGE2>
-__global__ __launch_bounds__(256) void sources_kernel(Phys P, Eos E, double tau, Fields F,
-                                                      const double *qn, double *out)
+// component is written as soon as its J is known.  J is computed in the
+// storage type S; T^{tau mu} is accumulated in FP64.
+template <bool CART, bool STAGE2, typename S>
+__device__ __forceinline__ void sources_body(const Phys &P, const Eos &E, double tau, const Fields<S> &F,
+                                             const double *qnT, const S *qnP, double *outT, S *outP,
+                                             unsigned bx, unsigned by, unsigned bz)
 {
-    unsigned bx, by, bz;
-    xcd_block3(bx, by, bz);
+    typedef S R;
     const int i = bx * 64 + threadIdx.x;
     const int j = by * 4 + threadIdx.y;
     const int k = bz;
@@ -297,73 +341,90 @@ __global__ __launch_bounds__(256) void sources_kernel(Phys P, Eos E, double tau,
         {col + (idx_t)wrap(k - 1, P.neta, P.periodic[2]) * plane,
          col + (idx_t)wrap(k + 1, P.neta, P.periodic[2]) * plane}};
     const double dt = P.dtau;
-    auto emit = [&](int c, double qc, double Jc) {
+    // T^{tau mu}: FP64 value, source and accumulation
+    auto emitT = [&](int c, double qc, double Jc) {
         const idx_t o = (idx_t)c * SS + s;
         const double t = qc + dt * Jc;
-        st(out, o, STAGE2 ? ld(qn, o) + t : t);
+        st(outT, o, STAGE2 ? ld(qnT, o) + t : t);
     };
-    const double invh[3] = {P.inv_dx, P.inv_dy, P.inv_deta};
-    double u[4], C[4][4];
+    auto emitP = [&](int c, R qc, R Jc) {
+        const idx_t o = (idx_t)(c - PTT) * SS + s;
+        const R t = qc + R(dt) * Jc;
+        st(outP, o, STAGE2 ? R(ld(qnP, o)) + t : t);
+    };
+    const double invhd[3] = {P.inv_dx, P.inv_dy, P.inv_deta};
+    R u[4], C[4][4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        u[m] = ld(F.u, (idx_t)m * SS + s);
-        C[0][m] = (u[m] - ld(F.up, (idx_t)m * SS + s)) * P.inv_dtau;
+        const double um = ld(F.u, (idx_t)m * SS + s);
+        u[m] = R(um);
+        C[0][m] = R((um - ld(F.up, (idx_t)m * SS + s)) * P.inv_dtau);
     }
-    // central differences (Sec. 3.1): d_i u^m, d_i v^i, S_c = -d_i A^{i nu}
-    double divv = 0.0, Sc[4] = {0.0, 0.0, 0.0, 0.0};
+    // central differences (Sec. 3.1): d_i u^m, d_i v^i, S_c = -d_i A^{i nu} (S_c in FP64)
+    R divv = R(0);
+    double Sc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const idx_t sm = nb[d][0], sp = nb[d][1];
-        const double hh = 0.5 * invh[d];
+        const double hh = 0.5 * invhd[d];
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-            C[d + 1][m] = (ld(F.u, (idx_t)m * SS + sp) - ld(F.u, (idx_t)m * SS + sm)) * hh;
-        divv += (ld(F.u, (idx_t)(d + 1) * SS + sp) / ld(F.u, sp)
-               - ld(F.u, (idx_t)(d + 1) * SS + sm) / ld(F.u, sm)) * hh;
+            C[d + 1][m] = R((ld(F.u, (idx_t)m * SS + sp) - ld(F.u, (idx_t)m * SS + sm)) * hh);
+        divv += R((ld(F.u, (idx_t)(d + 1) * SS + sp) / ld(F.u, sp)
+                 - ld(F.u, (idx_t)(d + 1) * SS + sm) / ld(F.u, sm)) * hh);
         double Ap[4], Am[4];
-        nonadvective_row<CART>(P, tau, F, SS, sp, d, Ap);
-        nonadvective_row<CART>(P, tau, F, SS, sm, d, Am);
+        nonadvective_row<CART, S>(P, tau, F, SS, sp, d, Ap);
+        nonadvective_row<CART, S>(P, tau, F, SS, sm, d, Am);
 #pragma unroll
         for (int n = 0; n < 4; ++n) Sc[n] -= (Ap[n] - Am[n]) * hh;
     }
-    const double e = ld(F.e, s);
-    const double p0 = ld(F.p, s);
-    const double Pim = ld(F.q, (idx_t)BPI * SS + s);
-    const double Pi = P.bulk ? Pim : 0.0;
-    const double Pc = p0 + Pi;
-    double pv[10];
+    const R e = R(ld(F.e, s));
+    const R p0 = R(ld(F.p, s));
+    const R Pim = R(ld(F.qP, (idx_t)(BPI - PTT) * SS + s));
+    const R Pi = P.bulk ? Pim : R(0);
+    R pv[10];
 #pragma unroll
-    for (int c = 0; c < 10; ++c) pv[c] = ld(F.q, (idx_t)(PTT + c) * SS + s);
+    for (int c = 0; c < 10; ++c) pv[c] = R(ld(F.qP, (idx_t)c * SS + s));
     // conservation law: geometric source (App. B) G^tau = -(T^tt + tau^2 T^ee)/tau,
     // G^x = -T^tx/tau, G^y = -T^ty/tau, G^eta = -3 T^te/tau, with
     // tau^2 T^ee = tau^2 v^eta (T^te - pi^te) + P + tau^2 pi^ee.
     {
         double qt[4];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) qt[n] = ld(F.q, (idx_t)n * SS + s);
+        for (int n = 0; n < 4; ++n) qt[n] = ld(F.qT, (idx_t)n * SS + s);
         if (!CART) {
             const double inv_tau = 1.0 / tau, t2 = tau * tau;
-            const double ve = u[3] / u[0];
-            const double pte = P.shear ? pv[PTE - PTT] : 0.0, pee = P.shear ? pv[PEE - PTT] : 0.0;
-            const double t2Tee = t2 * (ve * (qt[TE] - pte) + pee) + Pc;
-            emit(TT, qt[TT], Sc[0] - (qt[TT] + t2Tee) * inv_tau);
-            emit(TX, qt[TX], Sc[1] - qt[TX] * inv_tau);
-            emit(TY, qt[TY], Sc[2] - qt[TY] * inv_tau);
-            emit(TE, qt[TE], Sc[3] - 3.0 * qt[TE] * inv_tau);
+            const double ve = ld(F.u, 3 * SS + s) / ld(F.u, s);
+            const double pte = P.shear ? (double)pv[PTE - PTT] : 0.0, pee = P.shear ? (double)pv[PEE - PTT] : 0.0;
+            const double t2Tee = t2 * (ve * (qt[TE] - pte) + pee) + ((double)ld(F.p, s) + (double)Pi);
+            emitT(TT, qt[TT], Sc[0] - (qt[TT] + t2Tee) * inv_tau);
+            emitT(TX, qt[TX], Sc[1] - qt[TX] * inv_tau);
+            emitT(TY, qt[TY], Sc[2] - qt[TY] * inv_tau);
+            emitT(TE, qt[TE], Sc[3] - 3.0 * qt[TE] * inv_tau);
         } else {
 #pragma unroll
-            for (int n = 0; n < 4; ++n) emit(n, qt[n], Sc[n]);
+            for (int n = 0; n < 4; ++n) emitT(n, qt[n], Sc[n]);
         }
     }
     // relaxation equations; components that do not evolve keep their value
     if (!P.shear)
-        for (int c = 0; c < 10; ++c) emit(PTT + c, pv[c], 0.0);
-    if (!P.bulk) emit(BPI, Pim, 0.0);
+        for (int c = 0; c < 10; ++c) emitP(PTT + c, pv[c], R(0));
+    if (!P.bulk) emitP(BPI, Pim, R(0));
     if (P.shear || P.bulk) {
         double pe, cs2, T;
-        eos_full(E, e, pe, cs2, T);
-        relaxation_sources<CART>(P, tau, pv, Pi, e, p0, cs2, T, u, C, divv, emit);
+        eos_full(E, (double)e, pe, cs2, T);
+        relaxation_sources<CART, R>(P, tau, pv, Pi, e, p0, R(cs2), R(T), u, C, divv, emitP);
     }
+}
+
+template <bool CART, bool STAGE2, typename S>
+__global__ __launch_bounds__(256) void sources_kernel(Phys P, Eos E, double tau, Fields<S> F,
+                                                      const double *qnT, const S *qnP,
+                                                      double *outT, S *outP)
+{
+    unsigned bx, by, bz;
+    xcd_block3(bx, by, bz);
+    sources_body<CART, STAGE2, S>(P, E, tau, F, qnT, qnP, outT, outP, bx, by, bz);
 }
 
 // Flux part of one Euler stage: for a 64 x 4 x KC block of cells, the KT
@@ -376,19 +437,20 @@ __global__ __launch_bounds__(256) void sources_kernel(Phys P, Eos E, double tau,
 // 63 computes its right face itself); eta faces: the top face of plane k is
 // the bottom face of plane k+1 (kept in LDS per thread); y faces: two per
 // cell.  Components are processed one at a time.
-template <bool STAGE2>
-__global__ __launch_bounds__(256) void flux_kernel(Phys P, FaceGeo G, const double *q,
-                                                   const double *vf, double *out)
+// Hb: the block's LDS carry of the eta faces; kc: eta planes per block
+template <bool STAGE2, typename S>
+__device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const double *qT, const S *qP,
+                                          const S *vf, double *outT, S *outP, double (*HbT)[256],
+                                          S (*Hb)[256], unsigned bx, unsigned by, unsigned bz, int kc)
 {
-    __shared__ double Hb[NQ][256];   // eta face below the current plane
-    unsigned bx, by, bz;
-    xcd_block3(bx, by, bz);
+    typedef S R;   // flux arithmetic of pi and Pi; T^{tau mu} is done in FP64
     const int lane = threadIdx.x;
     const int tid = threadIdx.y * 64 + lane;
     const int i = bx * 64 + lane;
     const int j = by * 4 + threadIdx.y;
-    const int k0 = bz * KC;
+    const int k0 = bz * kc;
     const idx_t plane = (idx_t)P.nx * P.ny;
+    const idx_t SS = (idx_t)P.stride;
     // lanes outside the grid compute on clamped cells; their results are not stored
     const int ic = i < P.nx ? i : P.nx - 1;
     const int jc = j < P.ny ? j : P.ny - 1;
@@ -400,13 +462,12 @@ __global__ __launch_bounds__(256) void flux_kernel(Phys P, FaceGeo G, const doub
     const int xp2 = wrap(i + 2, P.nx, P.periodic[0]);
     const int ym2 = wrap(jc - 2, P.ny, P.periodic[1]), ym1 = wrap(jc - 1, P.ny, P.periodic[1]);
     const int yp1 = wrap(jc + 1, P.ny, P.periodic[1]), yp2 = wrap(jc + 2, P.ny, P.periodic[1]);
-    const double *vfx = vf + G.ox, *vfy = vf + G.oy, *vfe = vf + G.oe;
+    const S *vfx = vf + G.ox, *vfy = vf + G.oy, *vfe = vf + G.oe;
     const double f = P.dtau;
-    int c_end = NQ;
-    if (!P.bulk) c_end = BPI;
-    if (!P.shear && !P.bulk) c_end = PTT;
+    // evolved dissipative components: pi (if shear) and Pi (if bulk)
+    const int c0 = P.shear ? PTT : BPI, c1 = P.bulk ? NQ : BPI;
 #pragma unroll 1
-    for (int kk = 0; kk < KC; ++kk) {
+    for (int kk = 0; kk < kc; ++kk) {
         const int k = k0 + kk;
         if (k >= P.neta) break;    // uniform over the block
         const idx_t kp = (idx_t)k * plane;
@@ -417,114 +478,287 @@ __global__ __launch_bounds__(256) void flux_kernel(Phys P, FaceGeo G, const doub
         const int zp1 = wrap(k + 1, P.neta, P.periodic[2]), zp2 = wrap(k + 2, P.neta, P.periodic[2]);
         // face speeds: x (left face, and the right one for lane 63), y (both), eta (top)
         const idx_t fx = fidx_x(P.nx, P.ny, ifc, jc, k);
-        const double vmx = ld(vfx, fx), vpx = ld(vfx + G.nfx, fx);
-        const double ax = fmax(fabs(vmx), fabs(vpx));
-        double vmr = 0.0, vpr = 0.0;
+        const R vmx = R(ld(vfx, fx)), vpx = R(ld(vfx + G.nfx, fx));
+        const R ax = fmax(fabs(vmx), fabs(vpx));
+        R vmr = R(0), vpr = R(0);
         if (right) {
-            vmr = ld(vfx, fx + 1);
-            vpr = ld(vfx + G.nfx, fx + 1);
+            vmr = R(ld(vfx, fx + 1));
+            vpr = R(ld(vfx + G.nfx, fx + 1));
         }
-        const double axr = fmax(fabs(vmr), fabs(vpr));
+        const R axr = fmax(fabs(vmr), fabs(vpr));
         const idx_t fy0 = fidx_y(P.nx, P.ny, ic, jc, k), fy1 = fidx_y(P.nx, P.ny, ic, jc + 1, k);
-        const double vmy0 = ld(vfy, fy0), vpy0 = ld(vfy + G.nfy, fy0);
-        const double vmy1 = ld(vfy, fy1), vpy1 = ld(vfy + G.nfy, fy1);
-        const double ay0 = fmax(fabs(vmy0), fabs(vpy0)), ay1 = fmax(fabs(vmy1), fabs(vpy1));
+        const R vmy0 = R(ld(vfy, fy0)), vpy0 = R(ld(vfy + G.nfy, fy0));
+        const R vmy1 = R(ld(vfy, fy1)), vpy1 = R(ld(vfy + G.nfy, fy1));
+        const R ay0 = fmax(fabs(vmy0), fabs(vpy0)), ay1 = fmax(fabs(vmy1), fabs(vpy1));
         const idx_t fe1 = fidx_e(P.nx, P.ny, ic, jc, k + 1);
-        const double vme = ld(vfe, fe1), vpe = ld(vfe + G.nfe, fe1);
-        const double ae = fmax(fabs(vme), fabs(vpe));
-        double vmb = 0.0, vpb = 0.0;
+        const R vme = R(ld(vfe, fe1)), vpe = R(ld(vfe + G.nfe, fe1));
+        const R ae = fmax(fabs(vme), fabs(vpe));
+        R vmb = R(0), vpb = R(0);
         if (kk == 0) {
             const idx_t fe0 = fidx_e(P.nx, P.ny, ic, jc, k);
-            vmb = ld(vfe, fe0);
-            vpb = ld(vfe + G.nfe, fe0);
+            vmb = R(ld(vfe, fe0));
+            vpb = R(ld(vfe + G.nfe, fe0));
         }
-        const double ab = fmax(fabs(vmb), fabs(vpb));
+        const R ab = fmax(fabs(vmb), fabs(vpb));
         const idx_t rx = kp + (idx_t)jc * P.nx;
-        const idx_t by = kp + ic;
-        const idx_t r0 = by + (idx_t)ym2 * P.nx, r1 = by + (idx_t)ym1 * P.nx;
-        const idx_t r3 = by + (idx_t)yp1 * P.nx, r4 = by + (idx_t)yp2 * P.nx;
+        const idx_t bb = kp + ic;
+        const idx_t r0 = bb + (idx_t)ym2 * P.nx, r1 = bb + (idx_t)ym1 * P.nx;
+        const idx_t r3 = bb + (idx_t)yp1 * P.nx, r4 = bb + (idx_t)yp2 * P.nx;
         const idx_t e0 = col + (idx_t)zm2 * plane, e1 = col + (idx_t)zm1 * plane;
         const idx_t e3 = col + (idx_t)zp1 * plane, e4 = col + (idx_t)zp2 * plane;
-#pragma unroll 1
-        for (int c = 0; c < c_end; ++c) {
-            if (!P.shear && c == PTT) c = BPI;   // only T^{tau mu} and Pi evolve
-            const idx_t co = (idx_t)c * P.stride;
+        // divergence D of one component (array q, component offset co) in the
+        // arithmetic type RR, with the eta carry Hc
+        auto divergence = [&](auto rtag, const auto *q, idx_t co, auto *Hc) {
+            typedef decltype(rtag) RR;
+            const RR th = RR(P.theta);
             // x
-            const double Hx = face_H(q, co, P.theta, rx + xm2, rx + xm1, rx + x0, rx + xp1, vmx, vpx, ax);
-            double Hr = __shfl_down(Hx, 1);
-            if (right) Hr = face_H(q, co, P.theta, rx + xm1, rx + x0, rx + xp1, rx + xp2, vmr, vpr, axr);
-            double D = (Hx - Hr) * P.inv_dx;
+            const RR Hx = face_H<RR>(q, co, th, rx + xm2, rx + xm1, rx + x0, rx + xp1, RR(vmx), RR(vpx), RR(ax));
+            RR Hr = __shfl_down(Hx, 1);
+            if (right)
+                Hr = face_H<RR>(q, co, th, rx + xm1, rx + x0, rx + xp1, rx + xp2, RR(vmr), RR(vpr), RR(axr));
+            RR D = (Hx - Hr) * RR(P.inv_dx);
             // y
-            D += (face_H(q, co, P.theta, r0, r1, s, r3, vmy0, vpy0, ay0)
-                - face_H(q, co, P.theta, r1, s, r3, r4, vmy1, vpy1, ay1)) * P.inv_dy;
+            D += (face_H<RR>(q, co, th, r0, r1, s, r3, RR(vmy0), RR(vpy0), RR(ay0))
+                - face_H<RR>(q, co, th, r1, s, r3, r4, RR(vmy1), RR(vpy1), RR(ay1))) * RR(P.inv_dy);
             // eta
-            const double Hb0 = kk == 0 ? face_H(q, co, P.theta, e0, e1, s, e3, vmb, vpb, ab) : Hb[c][tid];
-            const double Ht = face_H(q, co, P.theta, e1, s, e3, e4, vme, vpe, ae);
-            Hb[c][tid] = Ht;
-            D += (Hb0 - Ht) * P.inv_deta;
+            const RR Hb0 = kk == 0 ? face_H<RR>(q, co, th, e0, e1, s, e3, RR(vmb), RR(vpb), RR(ab)) : Hc[tid];
+            const RR Ht = face_H<RR>(q, co, th, e1, s, e3, e4, RR(vme), RR(vpe), RR(ae));
+            Hc[tid] = Ht;
+            D += (Hb0 - Ht) * RR(P.inv_deta);
+            return D;
+        };
+#pragma unroll 1
+        for (int c = 0; c < PTT; ++c) {
+            const idx_t co = (idx_t)c * SS;
+            const double D = divergence(0.0, qT, co, HbT[c]);
             if (out_ok) {
-                const double t = ld(out, co + s) + f * D;
-                st(out, co + s, STAGE2 ? 0.5 * t : t);
+                const double t = ld(outT, co + s) + f * D;
+                st(outT, co + s, STAGE2 ? 0.5 * t : t);
+            }
+        }
+#pragma unroll 1
+        for (int c = c0; c < c1; ++c) {
+            const idx_t co = (idx_t)(c - PTT) * SS;
+            const R D = divergence(R(0), qP, co, Hb[c - PTT]);
+            if (out_ok) {
+                const R t = R(ld(outP, co + s)) + R(f) * D;
+                st(outP, co + s, STAGE2 ? R(0.5) * t : t);
             }
         }
     }
 }
 
+template <bool STAGE2, typename S>
+__global__ __launch_bounds__(256) void flux_kernel(Phys P, FaceGeo G, const double *qT, const S *qP,
+                                                   const S *vf, double *outT, S *outP, int kc)
+{
+    __shared__ double HbT[PTT][256];      // eta face below the current plane: T^{tau mu}
+    __shared__ S Hb[NQ - PTT][256];       // and pi, Pi
+    unsigned bx, by, bz;
+    xcd_block3(bx, by, bz);
+    flux_body<STAGE2, S>(P, G, qT, qP, vf, outT, outP, HbT, Hb, bx, by, bz, kc);
+}
+
 // recovery of every cell at tau, then the regulator and the floor reset;
 // writes e, p(e) and u.  Newton start: the cell's previous e (warm), the
-// conformal closed form, or (LEARNED) y_0 E from the network of kt_mlp.hpp.
-template <bool CART, bool LEARNED>
-__global__ __launch_bounds__(256) void recover_kernel(Phys P, Eos E, double tau, double *q,
-                                                      double *e_io, double *p_out, double *u_out,
-                                                      int do_regulate, int warm,
-                                                      const float *__restrict__ mlpw,
-                                                      unsigned long long *slots)
+// conformal closed form, or (LEARNED) y_0 e_c from the network of kt_mlp.hpp.
+// The inversion and the regulator run in FP64 whatever the storage type S.
+template <bool CART, bool LEARNED, typename S>
+__device__ __forceinline__ void recover_body(const Phys &P, const Eos &E, double tau, double *qT, S *qP,
+                                             S *e_io, S *p_out, double *u_out, int do_regulate, int warm,
+                                             const float *__restrict__ mlpw, unsigned long long *slots,
+                                             idx_t s)
 {
-    const idx_t s = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
     const long long wave = s >> 6;
     const idx_t SS = (idx_t)P.stride;
     int it = 0, fl = 0;
     const bool valid = (long long)s < P.ncell;
     if (valid) {
-        double es = warm ? ld(e_io, s) : -1.0;
+        double es = warm ? (double)ld(e_io, s) : -1.0;
         if (LEARNED) {   // before the cell's state is held in registers
-            const double Ttt = ld(q, s), ptt = ld(q, (idx_t)PTT * SS + s);
+            const double Ttt = ld(qT, s), ptt = ldq(qT, qP, PTT, SS, s);
             if (Ttt > 0.0 && Ttt - ptt > 0.0) {
-                const double Ttx = ld(q, SS + s), Tty = ld(q, 2 * SS + s), Tte = ld(q, 3 * SS + s);
-                const double ptx = ld(q, (idx_t)PTX * SS + s), pty = ld(q, (idx_t)PTY * SS + s);
-                const double pte = ld(q, (idx_t)PTE * SS + s);
+                const double Ttx = ld(qT, SS + s), Tty = ld(qT, 2 * SS + s), Tte = ld(qT, 3 * SS + s);
+                const double ptx = ldq(qT, qP, PTX, SS, s), pty = ldq(qT, qP, PTY, SS, s);
+                const double pte = ldq(qT, qP, PTE, SS, s);
                 float x[ktm::NI];
                 ktm::features<CART>(E, tau, Ttt, Ttx, Tty, Tte, ptt, ptx, pty, pte,
-                                    P.bulk ? ld(q, (idx_t)BPI * SS + s) : 0.0, x);
+                                    P.bulk ? ldq(qT, qP, BPI, SS, s) : 0.0, x);
                 es = (double)ktm::forward_y0(mlpw, x)
                    * ktm::conformal_root<CART>(P.e_floor, tau, Ttt, Ttx, Tty, Tte, ptt, ptx, pty, pte);
             }
         }
         double qc[NQ];
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) qc[c] = ld(q, (idx_t)(c) * SS + s);
+        for (int c = 0; c < NQ; ++c) qc[c] = ldq(qT, qP, c, SS, s);
         const double Pi = P.bulk ? qc[BPI] : 0.0;
         double e, p0, u[4];
         fl = recover<CART>(P, E, tau, qc[TT], qc[TX], qc[TY], qc[TE], qc[PTT], qc[PTX], qc[PTY],
                            qc[PTE], Pi, es, e, p0, u, it);
-        st(e_io, s, e);
-        st(p_out, s, p0);
+        st(e_io, s, (S)e);
+        st(p_out, s, (S)p0);
 #pragma unroll
         for (int m = 0; m < 4; ++m) st(u_out, (idx_t)(m) * SS + s, u[m]);
         if ((fl & F_FLOOR) && P.floor_reset) {
 #pragma unroll
-            for (int c = 0; c < NQ; ++c) st(q, (idx_t)(c) * SS + s, c == TT ? P.e_floor : 0.0);
+            for (int c = 0; c < PTT; ++c) st(qT, (idx_t)c * SS + s, c == TT ? P.e_floor : 0.0);
+#pragma unroll
+            for (int c = PTT; c < NQ; ++c) st(qP, (idx_t)(c - PTT) * SS + s, (S)0);
         } else if (do_regulate && P.regulate && P.shear) {
             regulate<CART>(P, tau, qc, e, p0, u);
 #pragma unroll
-            for (int c = PTT; c < NQ; ++c) st(q, (idx_t)(c) * SS + s, qc[c]);
+            for (int c = PTT; c < NQ; ++c) st(qP, (idx_t)(c - PTT) * SS + s, (S)qc[c]);
         }
     }
-    slot_add(slots, wave, C_ITERS_CELLS, it);
+    slot_add(slots, wave, C_ITERS_CELLS, it, iter_bits(P));
     slot_add(slots, wave, C_REC_CELLS, valid ? 1 : 0);
     slot_add(slots, wave, C_FLOOR, (fl & F_FLOOR) ? 1 : 0);
     slot_add(slots, wave, C_CLAMP, (fl & F_CLAMP) ? 1 : 0);
     slot_add(slots, wave, C_FALLBACK, (fl & F_FALLBACK) ? 1 : 0);
+}
+
+template <bool CART, bool LEARNED, typename S>
+__global__ __launch_bounds__(256) void recover_kernel(Phys P, Eos E, double tau, double *qT, S *qP,
+                                                      S *e_io, S *p_out, double *u_out,
+                                                      int do_regulate, int warm,
+                                                      const float *__restrict__ mlpw,
+                                                      unsigned long long *slots)
+{
+    recover_body<CART, LEARNED, S>(P, E, tau, qT, qP, e_io, p_out, u_out, do_regulate, warm, mlpw, slots,
+                                   (idx_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ------------------------------------------------------------- batches ---
+// One launch advances every event of a batch.  Block g of the launch (after
+// the XCD renumbering) belongs to the event e with first[e] <= g < first[e+1]
+// and is that event's block g - first[e]; the event's arguments sit in a
+// device table read with wave-uniform loads.  Events share tau (kept on the
+// device so that a captured step can be replayed) and the time step.
+__device__ __forceinline__ int batch_event(const unsigned *first, int n, unsigned g)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename S>
+struct BStage {             // one event of a stage (sources + flux launches)
+    Phys P;
+    Eos E;
+    FaceGeo G;
+    Fields<S> F;            // input of the stage
+    const double *qnT;      // q^n (stage 2 only)
+    const S *qnP;
+    double *outT;
+    S *outP;
+    unsigned sgx, sgy;      // sources grid (x, y); z = neta
+    unsigned fgx, fgy;      // flux grid (x, y); z = ceil(neta / kc)
+    int kc;                 // eta planes per flux block
+};
+
+template <typename S>
+struct BRec {               // one event of a recovery launch
+    Phys P;
+    Eos E;
+    double *qT;
+    S *qP, *e, *p;
+    double *u;
+    unsigned long long *slots;
+};
+
+template <typename S>
+struct BFace {              // one event of a face-speed launch
+    Phys P;
+    Eos E;
+    FaceGeo G;
+    FaceLaunch L;
+    const double *qT;
+    const S *qP, *e;
+    S *vf;
+    unsigned long long *slots;
+};
+
+struct BCopy {              // u^{n-1} <- u^n, u^n <- u^{n+1} of one event (4 * stride elements)
+    double *up, *u, *un;
+    long long n;
+};
+
+template <bool CART, bool STAGE2, typename S>
+__global__ __launch_bounds__(256) void sources_batch(const BStage<S> *__restrict__ tab,
+                                                     const unsigned *__restrict__ first, int n,
+                                                     const double *__restrict__ tau_dev)
+{
+    const unsigned g = xcd_block(blockIdx.x, gridDim.x);
+    const int ev = batch_event(first, n, g);
+    const BStage<S> &A = tab[ev];
+    const unsigned lb = g - first[ev];
+    const unsigned bx = lb % A.sgx, by = (lb / A.sgx) % A.sgy, bz = lb / (A.sgx * A.sgy);
+    const double tau = STAGE2 ? tau_dev[0] + A.P.dtau : tau_dev[0];
+    sources_body<CART, STAGE2, S>(A.P, A.E, tau, A.F, A.qnT, A.qnP, A.outT, A.outP, bx, by, bz);
+}
+
+template <bool STAGE2, typename S>
+__global__ __launch_bounds__(256) void flux_batch(const BStage<S> *__restrict__ tab,
+                                                  const unsigned *__restrict__ first, int n)
+{
+    __shared__ double HbT[PTT][256];
+    __shared__ S Hb[NQ - PTT][256];
+    const unsigned g = xcd_block(blockIdx.x, gridDim.x);
+    const int ev = batch_event(first, n, g);
+    const BStage<S> &A = tab[ev];
+    const unsigned lb = g - first[ev];
+    const unsigned bx = lb % A.fgx, by = (lb / A.fgx) % A.fgy, bz = lb / (A.fgx * A.fgy);
+    flux_body<STAGE2, S>(A.P, A.G, A.F.qT, A.F.qP, A.F.vf, A.outT, A.outP, HbT, Hb, bx, by, bz, A.kc);
+}
+
+template <bool CART, typename S>
+__global__ __launch_bounds__(256) void recover_batch(const BRec<S> *__restrict__ tab,
+                                                     const unsigned *__restrict__ first, int n,
+                                                     const double *__restrict__ tau_dev)
+{
+    const unsigned g = blockIdx.x;
+    const int ev = batch_event(first, n, g);
+    const BRec<S> &A = tab[ev];
+    const double tau = tau_dev[0] + A.P.dtau;
+    recover_body<CART, false, S>(A.P, A.E, tau, A.qT, A.qP, A.e, A.p, A.u, 1, 1, nullptr, A.slots,
+                                 (idx_t)(g - first[ev]) * 256 + threadIdx.x);
+}
+
+template <bool CART, typename S>
+__global__ __launch_bounds__(256) void faces_batch(const BFace<S> *__restrict__ tab,
+                                                   const unsigned *__restrict__ first, int n,
+                                                   const double *__restrict__ tau_dev)
+{
+    const unsigned g = xcd_block(blockIdx.x, gridDim.x);
+    const int ev = batch_event(first, n, g);
+    const BFace<S> &A = tab[ev];
+    const unsigned lb = g - first[ev];
+    const double tau = tau_dev[0] + A.P.dtau;
+    face_speeds_body<CART, S>(A.P, A.E, A.G, A.L, tau, A.qT, A.qP, A.e, A.vf, A.slots, lb,
+                              (long long)lb * 4 + (threadIdx.x >> 6));
+}
+
+__global__ __launch_bounds__(256) void rotate_batch(const BCopy *__restrict__ tab,
+                                                    const unsigned *__restrict__ first, int n)
+{
+    const unsigned g = blockIdx.x;
+    const int ev = batch_event(first, n, g);
+    const BCopy &A = tab[ev];
+    const long long i = (long long)(g - first[ev]) * 256 + threadIdx.x;
+    if (i < A.n) {
+        A.up[i] = A.u[i];
+        A.u[i] = A.un[i];
+    }
+}
+
+// tau^{n+1} = tau^n + dtau, one thread (part of the captured step)
+__global__ void tau_advance_kernel(double *tau_dev, double dtau)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) tau_dev[0] = tau_dev[0] + dtau;
 }
 
 // T^{tau mu} from primitives (Sec. 2.4, Eqs. Ttt, Tti): (e+P) u^tau u^mu - P g^{tau mu} + pi^{tau mu}
@@ -535,7 +769,8 @@ struct PrimPtrs {
     const double *Pi;
 };
 
-__global__ __launch_bounds__(256) void tmunu_kernel(Phys P, Eos E, PrimPtrs in, double *q)
+template <typename S>
+__global__ __launch_bounds__(256) void tmunu_kernel(Phys P, Eos E, PrimPtrs in, double *qT, S *qP)
 {
     const idx_t s = (idx_t)blockIdx.x * blockDim.x + threadIdx.x;
     if ((long long)s >= P.ncell) return;
@@ -547,10 +782,25 @@ __global__ __launch_bounds__(256) void tmunu_kernel(Phys P, Eos E, PrimPtrs in, 
     const double w = (e + Pc) * ut;
 #pragma unroll
     for (int m = 0; m < 4; ++m)   // pi^{tau m} are the first four of the ten
-        st(q, (idx_t)(m) * SS + s, w * ld(in.u[m], s) - (m == 0 ? Pc : 0.0) + ld(in.pi[m], s));
+        st(qT, (idx_t)(m) * SS + s, w * ld(in.u[m], s) - (m == 0 ? Pc : 0.0) + ld(in.pi[m], s));
 #pragma unroll
-    for (int c = 0; c < 10; ++c) st(q, (idx_t)((PTT + c)) * SS + s, ld(in.pi[c], s));
-    st(q, (idx_t)(BPI) * SS + s, Pi);
+    for (int c = 0; c < 10; ++c) st(qP, (idx_t)c * SS + s, (S)ld(in.pi[c], s));
+    st(qP, (idx_t)(BPI - PTT) * SS + s, (S)Pi);
+}
+
+// FP64 inputs to the FP32 storage (n elements)
+__global__ __launch_bounds__(256) void from_double_kernel(long long n, const double *in, float *out)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
+// conversion of stored fields to FP64 for export (n elements)
+template <typename S>
+__global__ __launch_bounds__(256) void to_double_kernel(long long n, const S *in, double *out)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (double)in[i];
 }
 
 struct RecIn {
@@ -620,11 +870,10 @@ enum : int {
 };
 constexpr int OBS_THREADS = 256;
 
-template <bool CART>
+template <bool CART, typename ST>
 __global__ __launch_bounds__(OBS_THREADS) void obs_partial_kernel(Phys P, Eos E, double tau,
-                                                                  const double *q,
-                                                                  const double *e,
-                                                                  const double *u,
+                                                                  const double *qT, const ST *qP,
+                                                                  const ST *e, const double *u,
                                                                   double *partial)
 {
     __shared__ double red[OBS_THREADS / 64][O_COUNT];
@@ -641,15 +890,15 @@ __global__ __launch_bounds__(OBS_THREADS) void obs_partial_kernel(Phys P, Eos E,
         bool finite = true;
 #pragma unroll
         for (int c = 0; c < NQ; ++c) {
-            qc[c] = q[c * S + s];
+            qc[c] = c < PTT ? qT[c * S + s] : (double)qP[(c - PTT) * S + s];
             finite = finite && isfinite(qc[c]);
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            uc[m] = u[m * S + s];
+            uc[m] = (double)u[m * S + s];
             finite = finite && isfinite(uc[m]);
         }
-        const double ec = e[s];
+        const double ec = (double)e[s];
         finite = finite && isfinite(ec);
         if (!finite) {
             acc[O_NAN] += 1.0;
@@ -747,12 +996,17 @@ struct kt_ctx {
     Eos E;
     hipStream_t stream;
     double *ws;
-    double *q, *qs, *e, *p, *u[3];   // u[cur], u[prev], u[star] by index below
+    // storage: T^{tau mu} in FP64; pi, Pi, e, p, u and the face speeds in the
+    // storage type (8-byte double, or 4-byte float for KT_MIXED)
+    bool mixed;
+    size_t es;                        // bytes per element of the storage type
+    double *qT[2];                    // T^{tau mu} of q (0) and q* (1)
+    char *qP[2];                      // components 4..14 of q and q*
+    char *e, *p, *u[3], *vf;          // u[cur], u[prev], u[star] by index below
     int ucur, uprev, ustar;
     double *tab;
     unsigned long long *slots, *ctr;
     long long nwaves;
-    double *vf;
     FaceGeo G;
     double *partial, *obs;
     float *mlp_w, *mlp_m, *mlp_v, *mlp_part;   // network parameters, Adam moments, gradient partials
@@ -817,7 +1071,7 @@ static long long cell_stride(const kt_params *p)
 }
 
 struct Layout {
-    size_t q, qs, u, e, p, vf, tab, slots, ctr, partial, obs, mlp, mlp_part, loss_part, total;
+    size_t qT, qP, qsT, qsP, u, e, p, vf, tab, slots, ctr, partial, obs, mlp, mlp_part, loss_part, total;
     long long nwaves;
     FaceGeo G;
 };
@@ -853,15 +1107,18 @@ static long long recover_waves(const kt_params *p)
 static Layout layout(const kt_params *p, const kt_eos *eos)
 {
     Layout L;
-    const size_t S = (size_t)cell_stride(p) * sizeof(double);
-    size_t off = 0;
-    L.q = off;  off += 15 * S;
-    L.qs = off; off += 15 * S;
-    L.u = off;  off += 12 * S;
-    L.e = off;  off += S;
-    L.p = off;  off += S;
+    const size_t es = p->precision == KT_MIXED ? sizeof(float) : sizeof(double);
+    const size_t S8 = (size_t)cell_stride(p) * sizeof(double), SE = (size_t)cell_stride(p) * es;
+    size_t off = 0;   // every array starts on a 256-byte boundary (the stride is a multiple of 64)
+    L.qT = off;  off += 4 * S8;
+    L.qP = off;  off += 11 * SE;
+    L.qsT = off; off += 4 * S8;
+    L.qsP = off; off += 11 * SE;
+    L.u = off;  off += 12 * S8;   // u^mu is FP64 in both precisions
+    L.e = off;  off += SE;
+    L.p = off;  off += SE;
     L.G = face_geo(p);
-    L.vf = off; off += round_up((size_t)(L.G.oe + 2 * L.G.nfe) * sizeof(double), 256);
+    L.vf = off; off += round_up((size_t)(L.G.oe + 2 * L.G.nfe) * es, 256);
     L.tab = off; off += round_up((size_t)(eos->conformal ? 1 : eos->n) * EOS_W * sizeof(double), 256);
     const long long sw = stage_waves(p), rw = recover_waves(p), fw = face_waves(p);
     L.nwaves = sw > rw ? sw : rw;
@@ -896,6 +1153,7 @@ static const char *check_args(const kt_params *p, const kt_eos *eos)
     if (!(p->e_floor > 0)) return "e_floor must be > 0";
     if (!(p->m2_delta > 0 && p->m2_delta < 1)) return "m2_delta must lie in (0, 1)";
     if (!(p->newton_tol > 0) || p->newton_max < 1) return "Newton tolerance and iteration limit must be positive";
+    if (p->precision != KT_FP64 && p->precision != KT_MIXED) return "precision must be KT_FP64 or KT_MIXED";
     if (eos->conformal) {
         if (!(eos->a_sb > 0)) return "conformal EOS needs a_sb > 0";
     } else {
@@ -934,9 +1192,10 @@ static hipError_t launch(K kernel, dim3 g, dim3 b, hipStream_t st, A... args)
 static dim3 linear_grid(long long n) { return dim3((unsigned)((n + 255) / 256)); }
 
 // warm != 0: a step's recovery, whose start follows the context's choice
-// (previous e, conformal closed form, or the network); warm == 0: conformal
-static kt_status run_recover(kt_ctx *c, double tau, double *q, double *u_out, int regulate,
-                             int warm)
+// (previous e, conformal closed form, or the network); warm == 0: conformal.
+// which: 0 = q, 1 = q*; ub: u buffer receiving u.
+template <typename S>
+static kt_status run_recover_t(kt_ctx *c, double tau, int which, int ub, int regulate, int warm)
 {
     const bool cart = c->prm.coords == KT_CARTESIAN;
     const bool learned = warm && c->inv_start == KT_START_LEARNED;
@@ -946,62 +1205,110 @@ static kt_status run_recover(kt_ctx *c, double tau, double *q, double *u_out, in
     if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
     const dim3 g = linear_grid(c->P.ncell), b(256);
     const float *w = c->mlp_w;
+    double *qT = c->qT[which];
+    S *qP = (S *)c->qP[which], *ee = (S *)c->e, *pp = (S *)c->p;
+    double *uu = (double *)c->u[ub];
     if (cart)
-        e = learned ? launch(recover_kernel<true, true>, g, b, c->stream, c->P, c->E, tau, q, c->e, c->p,
-                             u_out, regulate, warm, w, c->slots)
-                    : launch(recover_kernel<true, false>, g, b, c->stream, c->P, c->E, tau, q, c->e, c->p,
-                             u_out, regulate, warm, w, c->slots);
+        e = learned ? launch(recover_kernel<true, true, S>, g, b, c->stream, c->P, c->E, tau, qT, qP, ee, pp,
+                             uu, regulate, warm, w, c->slots)
+                    : launch(recover_kernel<true, false, S>, g, b, c->stream, c->P, c->E, tau, qT, qP, ee, pp,
+                             uu, regulate, warm, w, c->slots);
     else
-        e = learned ? launch(recover_kernel<false, true>, g, b, c->stream, c->P, c->E, tau, q, c->e, c->p,
-                             u_out, regulate, warm, w, c->slots)
-                    : launch(recover_kernel<false, false>, g, b, c->stream, c->P, c->E, tau, q, c->e, c->p,
-                             u_out, regulate, warm, w, c->slots);
+        e = learned ? launch(recover_kernel<false, true, S>, g, b, c->stream, c->P, c->E, tau, qT, qP, ee, pp,
+                             uu, regulate, warm, w, c->slots)
+                    : launch(recover_kernel<false, false, S>, g, b, c->stream, c->P, c->E, tau, qT, qP, ee, pp,
+                             uu, regulate, warm, w, c->slots);
     if (e == hipSuccess) e = prof_mark(c, 1, false);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "recover kernel: %s", hipGetErrorString(e));
     return KT_OK;
 }
 
-static kt_status run_faces(kt_ctx *c, double tau, const double *q)
+static kt_status run_recover(kt_ctx *c, double tau, int which, int ub, int regulate, int warm)
+{
+    return c->mixed ? run_recover_t<float>(c, tau, which, ub, regulate, warm)
+                    : run_recover_t<double>(c, tau, which, ub, regulate, warm);
+}
+
+template <typename S>
+static kt_status run_faces_t(kt_ctx *c, double tau, int which)
 {
     const bool cart = c->prm.coords == KT_CARTESIAN;
     hipError_t e = prof_mark(c, 2, true);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
     const FaceLaunch L = face_launch(c->G, c->P.nx, c->P.ny);
     const dim3 g(L.first_block[6]), b(256);
-    e = cart ? launch(face_speeds_kernel<true>, g, b, c->stream, c->P, c->E, c->G, L, tau, q,
-                      (const double *)c->e, c->vf, c->slots)
-             : launch(face_speeds_kernel<false>, g, b, c->stream, c->P, c->E, c->G, L, tau, q,
-                      (const double *)c->e, c->vf, c->slots);
+    const double *qT = c->qT[which];
+    const S *qP = (const S *)c->qP[which], *ee = (const S *)c->e;
+    e = cart ? launch(face_speeds_kernel<true, S>, g, b, c->stream, c->P, c->E, c->G, L, tau, qT, qP,
+                      ee, (S *)c->vf, c->slots)
+             : launch(face_speeds_kernel<false, S>, g, b, c->stream, c->P, c->E, c->G, L, tau, qT, qP,
+                      ee, (S *)c->vf, c->slots);
     if (e == hipSuccess) e = prof_mark(c, 2, false);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "face kernel: %s", hipGetErrorString(e));
     return KT_OK;
 }
 
-static kt_status run_stage(kt_ctx *c, bool stage2, double tau, const Fields &F, double *out)
+static kt_status run_faces(kt_ctx *c, double tau, int which)
+{
+    return c->mixed ? run_faces_t<float>(c, tau, which) : run_faces_t<double>(c, tau, which);
+}
+
+// one Euler stage on q (stage 1: q^n, src 0, into q*) or q* (stage 2: src 1,
+// into q^{n+1} over q^n), with flow u[ub] and previous flow u[ubp]
+template <typename S>
+static kt_status run_stage_t(kt_ctx *c, bool stage2, double tau, int src, int ub, int ubp)
 {
     const bool cart = c->prm.coords == KT_CARTESIAN;
     const Phys &P = c->P;
     const dim3 b(64, 4);
     const dim3 gs((P.nx + 63) / 64, (P.ny + 3) / 4, P.neta);
-    const double *qn = stage2 ? (const double *)c->q : nullptr;
+    Fields<S> F = {c->qT[src], (const S *)c->qP[src], (const S *)c->e, (const S *)c->p,
+                   (const double *)c->u[ub], (const double *)c->u[ubp], (const S *)c->vf};
+    const int dst = 1 - src;
+    double *outT = c->qT[dst];
+    S *outP = (S *)c->qP[dst];
+    const double *qnT = stage2 ? c->qT[0] : nullptr;
+    const S *qnP = stage2 ? (const S *)c->qP[0] : nullptr;
     hipError_t e = prof_mark(c, 3, true);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
     if (cart)
-        e = stage2 ? launch(sources_kernel<true, true>, gs, b, c->stream, P, c->E, tau, F, qn, out)
-                   : launch(sources_kernel<true, false>, gs, b, c->stream, P, c->E, tau, F, qn, out);
+        e = stage2 ? launch(sources_kernel<true, true, S>, gs, b, c->stream, P, c->E, tau, F, qnT, qnP, outT, outP)
+                   : launch(sources_kernel<true, false, S>, gs, b, c->stream, P, c->E, tau, F, qnT, qnP, outT, outP);
     else
-        e = stage2 ? launch(sources_kernel<false, true>, gs, b, c->stream, P, c->E, tau, F, qn, out)
-                   : launch(sources_kernel<false, false>, gs, b, c->stream, P, c->E, tau, F, qn, out);
+        e = stage2 ? launch(sources_kernel<false, true, S>, gs, b, c->stream, P, c->E, tau, F, qnT, qnP, outT, outP)
+                   : launch(sources_kernel<false, false, S>, gs, b, c->stream, P, c->E, tau, F, qnT, qnP, outT, outP);
     if (e == hipSuccess) e = prof_mark(c, 3, false);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "sources kernel: %s", hipGetErrorString(e));
     const dim3 gf((P.nx + 63) / 64, (P.ny + 3) / 4, (P.neta + KC - 1) / KC);
     e = prof_mark(c, 0, true);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
-    e = stage2 ? launch(flux_kernel<true>, gf, b, c->stream, P, c->G, F.q, F.vf, out)
-               : launch(flux_kernel<false>, gf, b, c->stream, P, c->G, F.q, F.vf, out);
+    e = stage2 ? launch(flux_kernel<true, S>, gf, b, c->stream, P, c->G, F.qT, F.qP, F.vf, outT, outP, KC)
+               : launch(flux_kernel<false, S>, gf, b, c->stream, P, c->G, F.qT, F.qP, F.vf, outT, outP, KC);
     if (e == hipSuccess) e = prof_mark(c, 0, false);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "flux kernel: %s", hipGetErrorString(e));
     return KT_OK;
+}
+
+static kt_status run_stage(kt_ctx *c, bool stage2, double tau, int src, int ub, int ubp)
+{
+    return c->mixed ? run_stage_t<float>(c, stage2, tau, src, ub, ubp)
+                    : run_stage_t<double>(c, stage2, tau, src, ub, ubp);
+}
+
+// FP64 device array -> storage-type array (n elements), or a plain copy
+static hipError_t store_from_double(kt_ctx *c, char *dst, const double *src, long long n)
+{
+    if (!c->mixed)
+        return hipMemcpyAsync(dst, src, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, c->stream);
+    return launch(from_double_kernel, linear_grid(n), dim3(256), c->stream, n, src, (float *)dst);
+}
+
+// storage-type array -> FP64 device array
+static hipError_t store_to_double(kt_ctx *c, double *dst, const char *src, long long n)
+{
+    if (!c->mixed)
+        return hipMemcpyAsync(dst, src, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, c->stream);
+    return launch(to_double_kernel<float>, linear_grid(n), dim3(256), c->stream, n, (const float *)src, dst);
 }
 
 extern "C" {
@@ -1033,8 +1340,7 @@ kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0
     if (!out) return fail(nullptr, KT_E_ARG, "out is null");
     *out = nullptr;
     if (const char *m = check_args(p, eos)) return fail(nullptr, KT_E_ARG, "%s", m);
-    if (p->precision != KT_FP64)
-        return fail(nullptr, KT_E_UNSUPPORTED, "only KT_FP64 is implemented in this build");
+
     if (!s0 || !d_ws) return fail(nullptr, KT_E_ARG, "null initial state or workspace");
     if (((uintptr_t)d_ws) % 256) return fail(nullptr, KT_E_ARG, "workspace must be 256-byte aligned");
     const bool have_q = s0->q[0] != nullptr;
@@ -1063,18 +1369,24 @@ kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0
     c->stream = stream;
     char *base = (char *)d_ws;
     c->ws = (double *)d_ws;
-    c->q = (double *)(base + L.q);
-    c->qs = (double *)(base + L.qs);
+    c->mixed = p->precision == KT_MIXED;
+    c->es = c->mixed ? sizeof(float) : sizeof(double);
     const long long S = c->P.stride;
-    for (int b = 0; b < 3; ++b) c->u[b] = (double *)(base + L.u) + (size_t)4 * S * b;
+    const size_t SE = (size_t)S * c->es;
+    c->qT[0] = (double *)(base + L.qT);
+    c->qP[0] = base + L.qP;
+    c->qT[1] = (double *)(base + L.qsT);
+    c->qP[1] = base + L.qsP;
+    const size_t S8 = (size_t)S * sizeof(double);
+    for (int b = 0; b < 3; ++b) c->u[b] = base + L.u + 4 * S8 * b;
     c->ucur = 0; c->uprev = 1; c->ustar = 2;
-    c->e = (double *)(base + L.e);
-    c->p = (double *)(base + L.p);
+    c->e = base + L.e;
+    c->p = base + L.p;
     c->tab = (double *)(base + L.tab);
     c->slots = (unsigned long long *)(base + L.slots);
     c->ctr = (unsigned long long *)(base + L.ctr);
     c->nwaves = L.nwaves;
-    c->vf = (double *)(base + L.vf);
+    c->vf = base + L.vf;
     c->G = L.G;
     c->partial = (double *)(base + L.partial);
     c->obs = (double *)(base + L.obs);
@@ -1124,25 +1436,27 @@ kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0
     // q^0
     const size_t bytes = sizeof(double) * (size_t)c->P.ncell;
     if (have_q) {
-        for (int k = 0; k < 15; ++k) {
-            he = hipMemcpyAsync(c->q + k * S, s0->q[k], bytes, hipMemcpyDeviceToDevice, stream);
-            if (he != hipSuccess) break;
-        }
+        for (int k = 0; k < 15 && he == hipSuccess; ++k)
+            he = k < PTT ? hipMemcpyAsync(c->qT[0] + k * S, s0->q[k], bytes, hipMemcpyDeviceToDevice, stream)
+                         : store_from_double(c, c->qP[0] + (k - PTT) * SE, s0->q[k], c->P.ncell);
     } else {
         PrimPtrs in;
         in.e = s0->e;
         for (int m = 0; m < 4; ++m) in.u[m] = s0->u[m];
         for (int k = 0; k < 10; ++k) in.pi[k] = s0->pi[k];
         in.Pi = s0->Pi;
-        he = launch(tmunu_kernel, linear_grid(c->P.ncell), dim3(256), stream, c->P, c->E, in, c->q);
+        he = c->mixed ? launch(tmunu_kernel<float>, linear_grid(c->P.ncell), dim3(256), stream, c->P, c->E, in,
+                               c->qT[0], (float *)c->qP[0])
+                      : launch(tmunu_kernel<double>, linear_grid(c->P.ncell), dim3(256), stream, c->P, c->E, in,
+                               c->qT[0], (double *)c->qP[0]);
     }
-    if (he != hipSuccess) { delete c; return fail(nullptr, KT_E_HIP, "initial state: %s", hipGetErrorString(he)); }
+    if (he != hipSuccess) { kt_destroy(c); return fail(nullptr, KT_E_HIP, "initial state: %s", hipGetErrorString(he)); }
     // (e^0, u^0) and u^{-1}
-    kt_status st = run_recover(c, c->tau, c->q, c->u[c->ucur], 0, 0);
-    if (st == KT_OK) st = run_faces(c, c->tau, c->q);
-    if (st != KT_OK) { kt_status r = fail(nullptr, st, "%s", c->err); delete c; return r; }
+    kt_status st = run_recover(c, c->tau, 0, c->ucur, 0, 0);
+    if (st == KT_OK) st = run_faces(c, c->tau, 0);
+    if (st != KT_OK) { kt_status r = fail(nullptr, st, "%s", c->err); kt_destroy(c); return r; }
     for (int m = 0; m < 4 && he == hipSuccess; ++m)
-        he = hipMemcpyAsync(c->u[c->uprev] + m * S, have_up ? s0->u_prev[m] : c->u[c->ucur] + m * S,
+        he = hipMemcpyAsync(c->u[c->uprev] + m * S8, have_up ? (const char *)s0->u_prev[m] : c->u[c->ucur] + m * S8,
                             bytes, hipMemcpyDeviceToDevice, stream);
     if (he == hipSuccess) he = hipStreamSynchronize(stream);
     if (he != hipSuccess) { delete c; return fail(nullptr, KT_E_HIP, "init: %s", hipGetErrorString(he)); }
@@ -1154,30 +1468,26 @@ kt_status kt_step(kt_ctx *c, int32_t n_steps)
 {
     if (!c) return fail(nullptr, KT_E_ARG, "null context");
     if (n_steps < 0) return fail(c, KT_E_ARG, "n_steps must be >= 0");
-    const long long S = c->P.stride;
     for (int s = 0; s < n_steps; ++s) {
         const double tau0 = c->tau, tau1 = c->tau + c->prm.dtau;
         // face speeds of q^n are current (computed after the previous recovery)
-        Fields F1 = {c->q, c->e, c->p, c->u[c->ucur], c->u[c->uprev], c->vf};
-        kt_status st = run_stage(c, false, tau0, F1, c->qs);
+        kt_status st = run_stage(c, false, tau0, 0, c->ucur, c->uprev);
         if (st != KT_OK) return st;
-        st = run_recover(c, tau1, c->qs, c->u[c->ustar], 1, 1);
-        if (st == KT_OK) st = run_faces(c, tau1, c->qs);
+        st = run_recover(c, tau1, 1, c->ustar, 1, 1);
+        if (st == KT_OK) st = run_faces(c, tau1, 1);
         if (st != KT_OK) return st;
-        Fields F2 = {c->qs, c->e, c->p, c->u[c->ustar], c->u[c->ucur], c->vf};
-        st = run_stage(c, true, tau1, F2, c->q);
+        st = run_stage(c, true, tau1, 1, c->ustar, c->ucur);
         if (st != KT_OK) return st;
         // u^{n-1} <- u^n; (e, u)^{n+1} into the freed buffer
         const int freed = c->uprev;
-        st = run_recover(c, tau1, c->q, c->u[freed], 1, 1);
-        if (st == KT_OK) st = run_faces(c, tau1, c->q);
+        st = run_recover(c, tau1, 0, freed, 1, 1);
+        if (st == KT_OK) st = run_faces(c, tau1, 0);
         if (st != KT_OK) return st;
         c->uprev = c->ucur;
         c->ucur = freed;
         c->tau = tau1;
         c->step += 1;
     }
-    (void)S;
     return KT_OK;
 }
 
@@ -1215,29 +1525,42 @@ kt_status kt_recover(kt_ctx *c, int64_t n, double tau, const double *const in[9]
 kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out)
 {
     if (!c) return fail(nullptr, KT_E_ARG, "null context");
-    const long long S = c->P.stride;
-    const size_t bytes = sizeof(double) * (size_t)c->P.ncell;
+    const long long S = c->P.stride, n = c->P.ncell;
+    const size_t SE = (size_t)S * c->es;
+    const size_t bytes = sizeof(double) * (size_t)n;
     hipError_t e = hipSuccess;
     if (dev_out) {
-        if (dev_out->e) e = hipMemcpyAsync(dev_out->e, c->e, bytes, hipMemcpyDeviceToDevice, c->stream);
+        if (dev_out->e) e = store_to_double(c, dev_out->e, c->e, n);
         for (int m = 0; m < 4 && e == hipSuccess; ++m) {
             if (dev_out->u[m])
-                e = hipMemcpyAsync(dev_out->u[m], c->u[c->ucur] + m * S, bytes, hipMemcpyDeviceToDevice, c->stream);
+                e = hipMemcpyAsync(dev_out->u[m], (const double *)c->u[c->ucur] + m * S, bytes, hipMemcpyDeviceToDevice,
+                                   c->stream);
             if (e == hipSuccess && dev_out->u_prev[m])
-                e = hipMemcpyAsync(dev_out->u_prev[m], c->u[c->uprev] + m * S, bytes, hipMemcpyDeviceToDevice, c->stream);
+                e = hipMemcpyAsync(dev_out->u_prev[m], (const double *)c->u[c->uprev] + m * S, bytes,
+                                   hipMemcpyDeviceToDevice, c->stream);
         }
         for (int k = 0; k < 15 && e == hipSuccess; ++k)
-            if (dev_out->q[k]) e = hipMemcpyAsync(dev_out->q[k], c->q + k * S, bytes, hipMemcpyDeviceToDevice, c->stream);
+            if (dev_out->q[k])
+                e = k < PTT ? hipMemcpyAsync(dev_out->q[k], c->qT[0] + k * S, bytes, hipMemcpyDeviceToDevice, c->stream)
+                            : store_to_double(c, dev_out->q[k], c->qP[0] + (k - PTT) * SE, n);
         if (e != hipSuccess) return fail(c, KT_E_HIP, "field export: %s", hipGetErrorString(e));
     }
     double res[O_COUNT];
     unsigned long long ctr[C_COUNT];
     if (host_out) {
         const bool cart = c->prm.coords == KT_CARTESIAN;
-        e = cart ? launch(obs_partial_kernel<true>, dim3(OBS_BLOCKS), dim3(OBS_THREADS), c->stream, c->P, c->E, c->tau,
-                          (const double *)c->q, (const double *)c->e, (const double *)c->u[c->ucur], c->partial)
-                 : launch(obs_partial_kernel<false>, dim3(OBS_BLOCKS), dim3(OBS_THREADS), c->stream, c->P, c->E, c->tau,
-                          (const double *)c->q, (const double *)c->e, (const double *)c->u[c->ucur], c->partial);
+        const dim3 g(OBS_BLOCKS), b(OBS_THREADS);
+        const double *qT = c->qT[0];
+        if (c->mixed)
+            e = cart ? launch(obs_partial_kernel<true, float>, g, b, c->stream, c->P, c->E, c->tau, qT,
+                              (const float *)c->qP[0], (const float *)c->e, (const double *)c->u[c->ucur], c->partial)
+                     : launch(obs_partial_kernel<false, float>, g, b, c->stream, c->P, c->E, c->tau, qT,
+                              (const float *)c->qP[0], (const float *)c->e, (const double *)c->u[c->ucur], c->partial);
+        else
+            e = cart ? launch(obs_partial_kernel<true, double>, g, b, c->stream, c->P, c->E, c->tau, qT,
+                              (const double *)c->qP[0], (const double *)c->e, (const double *)c->u[c->ucur], c->partial)
+                     : launch(obs_partial_kernel<false, double>, g, b, c->stream, c->P, c->E, c->tau, qT,
+                              (const double *)c->qP[0], (const double *)c->e, (const double *)c->u[c->ucur], c->partial);
         if (e == hipSuccess)
             e = launch(obs_final_kernel, dim3(1), dim3(64), c->stream, (const double *)c->partial, OBS_BLOCKS, c->obs);
         if (e == hipSuccess)
@@ -1432,5 +1755,419 @@ void kt_destroy(kt_ctx *c)
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     delete c;
 }
+
+}  // extern "C"
+
+// ======================================================================
+// Batches of events
+// ======================================================================
+
+struct kt_batch {
+    int n;
+    std::vector<kt_ctx *> ev;
+    hipStream_t user;            // the caller's stream
+    hipStream_t cap;             // stream the step graph is captured on and replayed on
+    hipEvent_t fork_ev, join_ev;
+    bool mixed, cart;
+    double dtau;
+    double *tau_dev;
+    char *tab;                   // device tables (see batch_tables)
+    size_t tab_bytes;
+    std::vector<int> kc;         // eta planes per flux block, per event
+    unsigned nb_src, nb_flux, nb_rec, nb_face, nb_rot;
+    size_t o_s1, o_s2, o_r1, o_r2, o_f1, o_f2, o_rot;             // table offsets
+    size_t o_fsrc, o_fflux, o_frec, o_fface, o_frot;              // first-block arrays
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    bool have_graph;
+    double tau;
+    long long step;
+    char err[512];
+};
+
+static kt_status bfail(kt_batch *b, kt_status s, const char *fmt, ...)
+{
+    char *dst = b ? b->err : g_err;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(dst, 512, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+// bytes of the device tables of n events (the larger, FP64 layout)
+static size_t batch_table_bytes(int n)
+{
+    size_t t = 0;
+    t += 2 * round_up(sizeof(BStage<double>) * n, 256);
+    t += 2 * round_up(sizeof(BRec<double>) * n, 256);
+    t += 2 * round_up(sizeof(BFace<double>) * n, 256);
+    t += round_up(sizeof(BCopy) * n, 256);
+    t += 5 * round_up(sizeof(unsigned) * (n + 1), 256);
+    return t;
+}
+
+static size_t event_ws(const kt_params *p, const kt_eos *eos)
+{
+    return round_up(layout(p, eos).total, 256);
+}
+
+// Build the per-event argument tables of one step and upload them (the
+// caller's stream, synchronised).  Buffers of every event: q (index 0) and
+// q* (1); u[0] = u^n, u[1] = u^{n-1}, u[2] = u* and then u^{n+1}, which the
+// rotation copies into u[0] after moving u[0] into u[1].
+template <typename S>
+static kt_status batch_tables(kt_batch *b)
+{
+    const int n = b->n;
+    std::vector<BStage<S>> s1(n), s2(n);
+    std::vector<BRec<S>> r1(n), r2(n);
+    std::vector<BFace<S>> f1(n), f2(n);
+    std::vector<BCopy> rot(n);
+    std::vector<unsigned> fs(n + 1), ff(n + 1), fr(n + 1), fc(n + 1), fo(n + 1);
+    fs[0] = ff[0] = fr[0] = fc[0] = fo[0] = 0;
+    for (int e = 0; e < n; ++e) {
+        kt_ctx *c = b->ev[e];
+        const Phys &P = c->P;
+        const long long S4 = 4 * P.stride;
+        auto uu = [&](int k) { return (double *)c->u[k]; };
+        for (int st = 0; st < 2; ++st) {
+            BStage<S> &A = st == 0 ? s1[e] : s2[e];
+            const int src = st;
+            A.P = P;
+            A.E = c->E;
+            A.G = c->G;
+            A.F = Fields<S>{c->qT[src], (const S *)c->qP[src], (const S *)c->e, (const S *)c->p,
+                            (const double *)uu(st == 0 ? 0 : 2), (const double *)uu(st == 0 ? 1 : 0),
+                            (const S *)c->vf};
+            A.qnT = st == 1 ? c->qT[0] : nullptr;
+            A.qnP = st == 1 ? (const S *)c->qP[0] : nullptr;
+            A.outT = c->qT[1 - src];
+            A.outP = (S *)c->qP[1 - src];
+            A.sgx = (P.nx + 63) / 64;
+            A.sgy = (P.ny + 3) / 4;
+            A.fgx = A.sgx;
+            A.fgy = A.sgy;
+            A.kc = b->kc[e];
+        }
+        for (int st = 0; st < 2; ++st) {
+            BRec<S> &R = st == 0 ? r1[e] : r2[e];
+            const int which = st == 0 ? 1 : 0;   // recover q* after stage 1, q after stage 2
+            R.P = P;
+            R.E = c->E;
+            R.qT = c->qT[which];
+            R.qP = (S *)c->qP[which];
+            R.e = (S *)c->e;
+            R.p = (S *)c->p;
+            R.u = uu(2);
+            R.slots = c->slots;
+            BFace<S> &F = st == 0 ? f1[e] : f2[e];
+            F.P = P;
+            F.E = c->E;
+            F.G = c->G;
+            F.L = face_launch(c->G, P.nx, P.ny);
+            F.qT = c->qT[which];
+            F.qP = (const S *)c->qP[which];
+            F.e = (const S *)c->e;
+            F.vf = (S *)c->vf;
+            F.slots = c->slots;
+        }
+        rot[e] = BCopy{uu(1), uu(0), uu(2), S4};
+        const unsigned sg = s1[e].sgx * s1[e].sgy;
+        fs[e + 1] = fs[e] + sg * (unsigned)P.neta;
+        ff[e + 1] = ff[e] + sg * (unsigned)((P.neta + b->kc[e] - 1) / b->kc[e]);
+        fr[e + 1] = fr[e] + (unsigned)((P.ncell + 255) / 256);
+        fc[e + 1] = fc[e] + f1[e].L.first_block[6];
+        fo[e + 1] = fo[e] + (unsigned)((S4 + 255) / 256);
+    }
+    b->nb_src = fs[n];
+    b->nb_flux = ff[n];
+    b->nb_rec = fr[n];
+    b->nb_face = fc[n];
+    b->nb_rot = fo[n];
+    size_t off = 0;
+    auto place = [&](size_t bytes) { const size_t o = off; off += round_up(bytes, 256); return o; };
+    b->o_s1 = place(sizeof(BStage<S>) * n);
+    b->o_s2 = place(sizeof(BStage<S>) * n);
+    b->o_r1 = place(sizeof(BRec<S>) * n);
+    b->o_r2 = place(sizeof(BRec<S>) * n);
+    b->o_f1 = place(sizeof(BFace<S>) * n);
+    b->o_f2 = place(sizeof(BFace<S>) * n);
+    b->o_rot = place(sizeof(BCopy) * n);
+    b->o_fsrc = place(sizeof(unsigned) * (n + 1));
+    b->o_fflux = place(sizeof(unsigned) * (n + 1));
+    b->o_frec = place(sizeof(unsigned) * (n + 1));
+    b->o_fface = place(sizeof(unsigned) * (n + 1));
+    b->o_frot = place(sizeof(unsigned) * (n + 1));
+    if (off > b->tab_bytes) return bfail(b, KT_E_ALLOC, "batch tables need %zu bytes", off);
+    std::vector<char> h(off, 0);
+    auto put = [&](size_t o, const void *src, size_t bytes) { memcpy(h.data() + o, src, bytes); };
+    put(b->o_s1, s1.data(), sizeof(BStage<S>) * n);
+    put(b->o_s2, s2.data(), sizeof(BStage<S>) * n);
+    put(b->o_r1, r1.data(), sizeof(BRec<S>) * n);
+    put(b->o_r2, r2.data(), sizeof(BRec<S>) * n);
+    put(b->o_f1, f1.data(), sizeof(BFace<S>) * n);
+    put(b->o_f2, f2.data(), sizeof(BFace<S>) * n);
+    put(b->o_rot, rot.data(), sizeof(BCopy) * n);
+    put(b->o_fsrc, fs.data(), sizeof(unsigned) * (n + 1));
+    put(b->o_fflux, ff.data(), sizeof(unsigned) * (n + 1));
+    put(b->o_frec, fr.data(), sizeof(unsigned) * (n + 1));
+    put(b->o_fface, fc.data(), sizeof(unsigned) * (n + 1));
+    put(b->o_frot, fo.data(), sizeof(unsigned) * (n + 1));
+    hipError_t e = hipMemcpyAsync(b->tab, h.data(), off, hipMemcpyHostToDevice, b->user);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->user);
+    if (e != hipSuccess) return bfail(b, KT_E_HIP, "batch tables: %s", hipGetErrorString(e));
+    return KT_OK;
+}
+
+// enqueue one Heun step of every event on stream st (captured into the graph)
+template <bool CART, typename S>
+static hipError_t batch_step_launches(kt_batch *b, hipStream_t st)
+{
+    const int n = b->n;
+    auto T = [&](size_t o) { return (const void *)(b->tab + o); };
+    auto F = [&](size_t o) { return (const unsigned *)(b->tab + o); };
+    const double *tau = b->tau_dev;
+    const dim3 blk2(64, 4), blk(256);
+    hipError_t e = launch(sources_batch<CART, false, S>, dim3(b->nb_src), blk2, st,
+                          (const BStage<S> *)T(b->o_s1), F(b->o_fsrc), n, tau);
+    if (e == hipSuccess)
+        e = launch(flux_batch<false, S>, dim3(b->nb_flux), blk2, st, (const BStage<S> *)T(b->o_s1),
+                   F(b->o_fflux), n);
+    if (e == hipSuccess)
+        e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r1),
+                   F(b->o_frec), n, tau);
+    if (e == hipSuccess)
+        e = launch(faces_batch<CART, S>, dim3(b->nb_face), blk, st, (const BFace<S> *)T(b->o_f1),
+                   F(b->o_fface), n, tau);
+    if (e == hipSuccess)
+        e = launch(sources_batch<CART, true, S>, dim3(b->nb_src), blk2, st,
+                   (const BStage<S> *)T(b->o_s2), F(b->o_fsrc), n, tau);
+    if (e == hipSuccess)
+        e = launch(flux_batch<true, S>, dim3(b->nb_flux), blk2, st, (const BStage<S> *)T(b->o_s2),
+                   F(b->o_fflux), n);
+    if (e == hipSuccess)
+        e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r2),
+                   F(b->o_frec), n, tau);
+    if (e == hipSuccess)
+        e = launch(faces_batch<CART, S>, dim3(b->nb_face), blk, st, (const BFace<S> *)T(b->o_f2),
+                   F(b->o_fface), n, tau);
+    if (e == hipSuccess)
+        e = launch(rotate_batch, dim3(b->nb_rot), blk, st, (const BCopy *)T(b->o_rot),
+                   F(b->o_frot), n);
+    if (e == hipSuccess) e = launch(tau_advance_kernel, dim3(1), dim3(64), st, b->tau_dev, b->dtau);
+    return e;
+}
+
+static hipError_t batch_launches(kt_batch *b, hipStream_t st)
+{
+    if (b->mixed)
+        return b->cart ? batch_step_launches<true, float>(b, st) : batch_step_launches<false, float>(b, st);
+    return b->cart ? batch_step_launches<true, double>(b, st) : batch_step_launches<false, double>(b, st);
+}
+
+static void batch_drop_graph(kt_batch *b)
+{
+    if (b->have_graph) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->have_graph = false;
+    }
+}
+
+static kt_status batch_build_tables(kt_batch *b)
+{
+    batch_drop_graph(b);
+    return b->mixed ? batch_tables<float>(b) : batch_tables<double>(b);
+}
+
+extern "C" {
+
+size_t kt_batch_workspace_bytes(const kt_params *p, int32_t n_events, const kt_eos *eos)
+{
+    if (!p || n_events < 1 || !eos) return 0;
+    size_t t = 0;
+    for (int e = 0; e < n_events; ++e) {
+        if (check_args(&p[e], eos)) return 0;
+        t += event_ws(&p[e], eos);
+    }
+    return t + 256 + round_up(batch_table_bytes(n_events), 256);
+}
+
+void kt_batch_destroy(kt_batch *b)
+{
+    if (!b) return;
+    batch_drop_graph(b);
+    if (b->cap) {
+        (void)hipStreamSynchronize(b->cap);
+        (void)hipStreamDestroy(b->cap);
+    }
+    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+    if (b->join_ev) (void)hipEventDestroy(b->join_ev);
+    for (kt_ctx *c : b->ev) kt_destroy(c);
+    delete b;
+}
+
+kt_status kt_batch_init(const kt_params *p, int32_t n_events, const kt_eos *eos,
+                        const kt_init_state *s0, void *d_ws, size_t ws_bytes, hipStream_t stream,
+                        kt_batch **out)
+{
+    if (!out) return bfail(nullptr, KT_E_ARG, "out is null");
+    *out = nullptr;
+    if (!p || !eos || !s0 || !d_ws) return bfail(nullptr, KT_E_ARG, "null argument");
+    if (n_events < 1) return bfail(nullptr, KT_E_ARG, "n_events must be >= 1");
+    if (((uintptr_t)d_ws) % 256) return bfail(nullptr, KT_E_ARG, "workspace must be 256-byte aligned");
+    for (int e = 0; e < n_events; ++e) {
+        if (const char *m = check_args(&p[e], eos)) return bfail(nullptr, KT_E_ARG, "event %d: %s", e, m);
+        if (p[e].coords != p[0].coords || p[e].precision != p[0].precision || p[e].dtau != p[0].dtau ||
+            p[e].tau0 != p[0].tau0)
+            return bfail(nullptr, KT_E_ARG, "event %d: coords, precision, tau0 and dtau must match event 0", e);
+    }
+    const size_t need = kt_batch_workspace_bytes(p, n_events, eos);
+    if (ws_bytes < need) return bfail(nullptr, KT_E_ALLOC, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    kt_batch *b = new (std::nothrow) kt_batch();
+    if (!b) return bfail(nullptr, KT_E_ALLOC, "host allocation failed");
+    b->n = n_events;
+    b->user = stream;
+    b->mixed = p[0].precision == KT_MIXED;
+    b->cart = p[0].coords == KT_CARTESIAN;
+    b->dtau = p[0].dtau;
+    b->tau = p[0].tau0;
+    b->kc.assign(n_events, KC);
+    char *base = (char *)d_ws;
+    size_t off = 0;
+    for (int e = 0; e < n_events; ++e) {
+        kt_ctx *c = nullptr;
+        const size_t w = event_ws(&p[e], eos);
+        kt_status st = kt_init(&p[e], eos, &s0[e], base + off, w, stream, &c);
+        if (st != KT_OK) {
+            kt_status r = bfail(nullptr, st, "event %d: %s", e, kt_last_error(nullptr));
+            kt_batch_destroy(b);
+            return r;
+        }
+        b->ev.push_back(c);
+        off += w;
+    }
+    b->tau_dev = (double *)(base + off);
+    off += 256;
+    b->tab = base + off;
+    b->tab_bytes = round_up(batch_table_bytes(n_events), 256);
+    hipError_t he = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipMemcpyAsync(b->tau_dev, &b->tau, sizeof(double), hipMemcpyHostToDevice, stream);
+    if (he != hipSuccess) {
+        kt_status r = bfail(nullptr, KT_E_HIP, "batch init: %s", hipGetErrorString(he));
+        kt_batch_destroy(b);
+        return r;
+    }
+    kt_status st = batch_build_tables(b);
+    if (st != KT_OK) {
+        kt_status r = bfail(nullptr, st, "%s", b->err);
+        kt_batch_destroy(b);
+        return r;
+    }
+    *out = b;
+    return KT_OK;
+}
+
+kt_status kt_batch_step(kt_batch *b, int32_t n_steps)
+{
+    if (!b) return bfail(nullptr, KT_E_ARG, "null batch");
+    if (n_steps < 0) return bfail(b, KT_E_ARG, "n_steps must be >= 0");
+    if (n_steps == 0) return KT_OK;
+    hipError_t e = hipSuccess;
+    if (!b->have_graph) {
+        e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = batch_launches(b, b->cap);
+            e = hipStreamEndCapture(b->cap, &b->graph);
+            if (le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return bfail(b, KT_E_HIP, "step graph: %s", hipGetErrorString(e));
+        b->have_graph = true;
+    }
+    e = hipEventRecord(b->fork_ev, b->user);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->fork_ev, 0);
+    for (int s = 0; s < n_steps && e == hipSuccess; ++s) e = hipGraphLaunch(b->exec, b->cap);
+    if (e == hipSuccess) e = hipEventRecord(b->join_ev, b->cap);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->user, b->join_ev, 0);
+    if (e != hipSuccess) return bfail(b, KT_E_HIP, "batch step: %s", hipGetErrorString(e));
+    for (int s = 0; s < n_steps; ++s) {
+        b->tau = b->tau + b->dtau;
+        b->step += 1;
+    }
+    for (kt_ctx *c : b->ev) {
+        c->tau = b->tau;
+        c->step = b->step;
+    }
+    return KT_OK;
+}
+
+kt_status kt_batch_tune(kt_batch *b, int32_t *kc_out)
+{
+    if (!b) return bfail(nullptr, KT_E_ARG, "null batch");
+    static const int cand[4] = {1, 2, 4, 8};
+    hipEvent_t t0, t1;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    if (e != hipSuccess) return bfail(b, KT_E_HIP, "tune events: %s", hipGetErrorString(e));
+    for (int ev = 0; ev < b->n && e == hipSuccess; ++ev) {
+        kt_ctx *c = b->ev[ev];
+        int same = -1;   // an earlier event of the same shape
+        for (int k = 0; k < ev; ++k)
+            if (b->ev[k]->P.nx == c->P.nx && b->ev[k]->P.ny == c->P.ny && b->ev[k]->P.neta == c->P.neta) same = k;
+        if (same >= 0) {
+            b->kc[ev] = b->kc[same];
+            continue;
+        }
+        // the flux of stage 1 accumulates into q*, which the next step's sources kernel
+        // overwrites, so timing it on the live state changes no result
+        float best = 1e30f;
+        for (int ci = 0; ci < 4 && e == hipSuccess; ++ci) {
+            const int kc = cand[ci];
+            const dim3 g((c->P.nx + 63) / 64, (c->P.ny + 3) / 4, (c->P.neta + kc - 1) / kc), blk(64, 4);
+            float tot = 0.0f;
+            for (int r = 0; r < 4 && e == hipSuccess; ++r) {
+                e = hipEventRecord(t0, b->user);
+                if (e == hipSuccess) {
+                    if (b->mixed)
+                        e = launch(flux_kernel<false, float>, g, blk, b->user, c->P, c->G, (const double *)c->qT[0],
+                                   (const float *)c->qP[0], (const float *)c->vf, c->qT[1], (float *)c->qP[1], kc);
+                    else
+                        e = launch(flux_kernel<false, double>, g, blk, b->user, c->P, c->G, (const double *)c->qT[0],
+                                   (const double *)c->qP[0], (const double *)c->vf, c->qT[1], (double *)c->qP[1], kc);
+                }
+                if (e == hipSuccess) e = hipEventRecord(t1, b->user);
+                if (e == hipSuccess) e = hipEventSynchronize(t1);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                if (r > 0) tot += ms;   // the first launch warms caches
+            }
+            if (e == hipSuccess && tot < best) {
+                best = tot;
+                b->kc[ev] = kc;
+            }
+        }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (e != hipSuccess) return bfail(b, KT_E_HIP, "tune: %s", hipGetErrorString(e));
+    if (kc_out)
+        for (int ev = 0; ev < b->n; ++ev) kc_out[ev] = b->kc[ev];
+    return batch_build_tables(b);
+}
+
+kt_status kt_batch_observables(kt_batch *b, int32_t event, kt_obs *host_out, const kt_fields *dev_out)
+{
+    if (!b) return bfail(nullptr, KT_E_ARG, "null batch");
+    if (event < 0 || event >= b->n) return bfail(b, KT_E_ARG, "event %d out of range", event);
+    kt_status st = kt_observables(b->ev[event], host_out, dev_out);
+    if (st != KT_OK) return bfail(b, st, "%s", b->ev[event]->err);
+    return KT_OK;
+}
+
+const char *kt_batch_last_error(const kt_batch *b) { return b ? b->err : g_err; }
 
 }  // extern "C"

@@ -546,3 +546,27 @@ def mlp_init_params(seed: int = 0, y0_bias: float = 0.8) -> np.ndarray:
             b[0] = y0_bias
         parts.append(b)
     return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# Batches of fluctuating events
+# --------------------------------------------------------------------------
+
+BATCH_SHAPES = ((64, 64, 64), (96, 96, 64), (128, 128, 96), (160, 160, 64))
+
+
+def workload_batch(n_events: int = 48, seed: int = 7, mixed: bool = True):
+    """Hot-spot events of the 128^3 event's physics on uneven grids: shapes
+    drawn uniformly from BATCH_SHAPES (PCG64(seed)), hot-spot counts uniform
+    in [50, 400], event k seeded 1000 + k; FP32 state when mixed."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shapes = rng.integers(0, len(BATCH_SHAPES), n_events)
+    hots = rng.integers(50, 401, n_events)
+    out = []
+    for k in range(n_events):
+        nx, ny, ne = BATCH_SHAPES[shapes[k]]
+        w = workload_hotspot(nx=nx, ny=ny, neta=ne, n_hot=int(hots[k]), seed=1000 + k)
+        if mixed:
+            w.config["mixed"] = True
+        out.append(w)
+    return out

@@ -85,7 +85,9 @@ _lib = None
 EXPORTS = ("kt_workspace_bytes", "kt_init", "kt_step", "kt_recover", "kt_observables",
            "kt_profile_enable", "kt_profile_read", "kt_destroy", "kt_last_error",
            "kt_status_string", "kt_set_inv_start", "kt_mlp_set", "kt_mlp_get", "kt_mlp_features",
-           "kt_mlp_fwd", "kt_mlp_loss", "kt_mlp_bwd", "kt_mlp_adam")
+           "kt_mlp_fwd", "kt_mlp_loss", "kt_mlp_bwd", "kt_mlp_adam", "kt_batch_workspace_bytes",
+           "kt_batch_init", "kt_batch_step", "kt_batch_tune", "kt_batch_observables",
+           "kt_batch_destroy", "kt_batch_last_error")
 
 KT_START_WARM, KT_START_CONFORMAL, KT_START_LEARNED = 0, 1, 2
 KT_MLP_NPARAMS = 5188
@@ -127,6 +129,19 @@ def lib():
         L.kt_mlp_loss.argtypes = [vp, C.c_int64, vp, vp, C.POINTER(C.c_float), vp, vp]
         L.kt_mlp_bwd.argtypes = [vp, C.c_int64, vp, vp, vp, vp]
         L.kt_mlp_adam.argtypes = [vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32]
+        L.kt_batch_workspace_bytes.argtypes = [C.POINTER(KtParams), C.c_int32, C.POINTER(KtEos)]
+        L.kt_batch_workspace_bytes.restype = C.c_size_t
+        L.kt_batch_init.argtypes = [C.POINTER(KtParams), C.c_int32, C.POINTER(KtEos),
+                                    C.POINTER(KtInitState), vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.kt_batch_step.argtypes = [vp, C.c_int32]
+        L.kt_batch_tune.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.kt_batch_observables.argtypes = [vp, C.c_int32, C.POINTER(KtObs), C.POINTER(KtFields)]
+        L.kt_batch_destroy.argtypes = [vp]
+        L.kt_batch_destroy.restype = None
+        L.kt_batch_last_error.argtypes = [vp]
+        L.kt_batch_last_error.restype = C.c_char_p
+        for f in ("kt_batch_init", "kt_batch_step", "kt_batch_tune", "kt_batch_observables"):
+            getattr(L, f).restype = C.c_int
         for f in ("kt_init", "kt_step", "kt_recover", "kt_observables", "kt_profile_enable",
                   "kt_profile_read", "kt_set_inv_start", "kt_mlp_set", "kt_mlp_get",
                   "kt_mlp_features", "kt_mlp_fwd", "kt_mlp_loss", "kt_mlp_bwd", "kt_mlp_adam"):
@@ -178,6 +193,38 @@ def workspace_bytes(grid, config, eos, tau0=1.0) -> int:
     return int(lib().kt_workspace_bytes(C.byref(p), C.byref(e.c)))
 
 
+def _init_state(torch, device, grid, prims, q, u_prev, keep) -> KtInitState:
+    """Device arrays of an initial state (kept alive in keep) as a KtInitState."""
+    st = KtInitState()
+    shape = grid.shape
+
+    def dev(a):
+        t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(device) \
+            if isinstance(a, np.ndarray) else a.contiguous()
+        assert t.dtype == torch.float64 and tuple(t.shape[-3:]) == shape
+        keep.append(t)
+        return t
+
+    if q is not None:
+        qd = dev(q)
+        for c in range(NQ):
+            st.q[c] = qd[c].data_ptr()
+    else:
+        get = (lambda k: prims[k]) if isinstance(prims, dict) else (lambda k: getattr(prims, k))
+        e, u, pi, Pi = dev(get("e")), dev(get("u")), dev(get("pi")), dev(get("Pi"))
+        st.e = e.data_ptr()
+        st.Pi = Pi.data_ptr()
+        for m in range(4):
+            st.u[m] = u[m].data_ptr()
+        for c in range(10):
+            st.pi[c] = pi[c].data_ptr()
+    if u_prev is not None:
+        upd = dev(u_prev)
+        for m in range(4):
+            st.u_prev[m] = upd[m].data_ptr()
+    return st
+
+
 class Solver:
     """One event advanced by the HIP library.
 
@@ -205,34 +252,8 @@ class Solver:
             self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             if self.ws.data_ptr() % 256:
                 raise RuntimeError("workspace is not 256-byte aligned")
-            st = KtInitState()
             keep = []
-            shape = grid.shape
-
-            def dev(a):
-                t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(self.device) \
-                    if isinstance(a, np.ndarray) else a.contiguous()
-                assert t.dtype == torch.float64 and tuple(t.shape[-3:]) == shape
-                keep.append(t)
-                return t
-
-            if q is not None:
-                qd = dev(q)
-                for c in range(NQ):
-                    st.q[c] = qd[c].data_ptr()
-            else:
-                get = (lambda k: prims[k]) if isinstance(prims, dict) else (lambda k: getattr(prims, k))
-                e, u, pi, Pi = dev(get("e")), dev(get("u")), dev(get("pi")), dev(get("Pi"))
-                st.e = e.data_ptr()
-                st.Pi = Pi.data_ptr()
-                for m in range(4):
-                    st.u[m] = u[m].data_ptr()
-                for c in range(10):
-                    st.pi[c] = pi[c].data_ptr()
-            if u_prev is not None:
-                upd = dev(u_prev)
-                for m in range(4):
-                    st.u_prev[m] = upd[m].data_ptr()
+            st = _init_state(torch, self.device, grid, prims, q, u_prev, keep)
             stream = torch.cuda.current_stream(self.device).cuda_stream
             ctx = C.c_void_p()
             _check(L.kt_init(C.byref(self.params), C.byref(self.eos_host.c), C.byref(st),
@@ -364,6 +385,89 @@ class Solver:
         if getattr(self, "ctx", None):
             lib().kt_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several events advanced together (one launch per kernel over all
+    events, one step replayed as a hipGraph).
+
+    events: list of (grid, config, prims) sharing the EOS, coordinates,
+    precision, tau0 and dtau.
+    """
+
+    def __init__(self, events, eos, tau0=None, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.grids = [g for g, _, _ in events]
+        n = len(events)
+        if tau0 is None:
+            tau0 = events[0][2].tau0
+        self.params = (KtParams * n)(*[make_params(g, cfg, tau0) for g, cfg, _ in events])
+        self.eos_host = EosHost(eos)
+        L = lib()
+        nbytes = int(L.kt_batch_workspace_bytes(self.params, n, C.byref(self.eos_host.c)))
+        if nbytes == 0:
+            raise KtError(KT_E_ARG, "invalid batch parameters")
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            keep = []
+            states = (KtInitState * n)(*[_init_state(torch, self.device, g, pr, None, None, keep)
+                                         for g, _, pr in events])
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            b = C.c_void_p()
+            st = L.kt_batch_init(self.params, n, C.byref(self.eos_host.c), states,
+                                 C.c_void_p(self.ws.data_ptr()), nbytes, C.c_void_p(stream), C.byref(b))
+            if st != KT_OK:
+                raise KtError(st, L.kt_batch_last_error(None).decode(errors="replace"))
+            self.b = b
+            del keep
+        self.n = n
+
+    def _check(self, st):
+        if st != KT_OK:
+            raise KtError(st, lib().kt_batch_last_error(self.b).decode(errors="replace"))
+
+    def step(self, n: int = 1):
+        self._check(lib().kt_batch_step(self.b, int(n)))
+        return self
+
+    def tune(self):
+        kc = (C.c_int32 * self.n)()
+        self._check(lib().kt_batch_tune(self.b, kc))
+        return list(kc)
+
+    def observables(self, event: int) -> dict:
+        o = KtObs()
+        self._check(lib().kt_batch_observables(self.b, int(event), C.byref(o), None))
+        return o.as_dict()
+
+    def fields(self, event: int, which=("e", "u", "q", "u_prev")) -> dict:
+        torch = self.torch
+        shape = self.grids[event].shape
+        out = {}
+        f = KtFields()
+        if "e" in which:
+            out["e"] = torch.empty(shape, dtype=torch.float64, device=self.device)
+            f.e = out["e"].data_ptr()
+        for key, n, arr in (("u", 4, f.u), ("u_prev", 4, f.u_prev), ("q", NQ, f.q)):
+            if key in which:
+                out[key] = torch.empty((n,) + shape, dtype=torch.float64, device=self.device)
+                for m in range(n):
+                    arr[m] = out[key][m].data_ptr()
+        self._check(lib().kt_batch_observables(self.b, int(event), None, C.byref(f)))
+        return out
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().kt_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

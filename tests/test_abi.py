@@ -87,12 +87,17 @@ def test_init_rejects_bad_arguments_without_device_work(L):
         st.q[c] = 4096
     assert L.kt_init(C.byref(p), C.byref(eos.c), C.byref(st), C.c_void_p(4096), 1024, None,
                      C.byref(ctx)) == kt.KT_E_ALLOC
-    # precision not built
+    # unknown precision
     q = kt.make_params(g, cfg, 0.5)
-    q.precision = kt.KT_MIXED
+    q.precision = 7
     assert L.kt_init(C.byref(q), C.byref(eos.c), C.byref(st), C.c_void_p(4096), 1 << 30, None,
-                     C.byref(ctx)) == kt.KT_E_UNSUPPORTED
+                     C.byref(ctx)) == kt.KT_E_ARG
+    assert L.kt_workspace_bytes(C.byref(q), C.byref(eos.c)) == 0
     assert not ctx.value
+    # the mixed-precision state needs less workspace: 4 FP64 + 11 FP32 components per q
+    q.precision = kt.KT_MIXED
+    n_mixed = L.kt_workspace_bytes(C.byref(q), C.byref(eos.c))
+    assert 0 < n_mixed < L.kt_workspace_bytes(C.byref(p), C.byref(eos.c))
     # calls on a null context
     assert L.kt_step(None, 1) == kt.KT_E_ARG
     assert L.kt_observables(None, None, None) == kt.KT_E_ARG

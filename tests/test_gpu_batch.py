@@ -1,0 +1,88 @@
+"""Batches of events (kt_batch_*) against separate contexts and the oracle.
+
+One launch per kernel covers every event and one step is replayed as a
+hipGraph; the arithmetic per cell is that of a single context, so the
+results must agree bit for bit, after any number of replays, with eager work
+in between, and after the autotuner changes the flux tiling."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_06577_amd import inputs as I
+
+from tests.test_gpu_parity import e_err, u_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kt():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1608_06577_amd import kt as K
+    K.lib()
+    return K
+
+
+def events(mixed=False):
+    """Uneven grids (tails in x, y and eta) with different hot-spot draws."""
+    out = []
+    for (nx, ny, ne, hot, seed) in ((40, 36, 12, 30, 11), (24, 20, 8, 20, 12), (71, 17, 5, 40, 13)):
+        w = I.workload_hotspot(nx=nx, ny=ny, neta=ne, dx=0.5, deta=0.6, n_hot=hot, seed=seed)
+        cfg = dict(w.config)
+        if mixed:
+            cfg["mixed"] = True
+        out.append((w.grid, cfg, w.prims))
+    return out, w.eos
+
+
+def same(a, b):
+    return all(np.array_equal(a[k].cpu().numpy(), b[k].cpu().numpy()) for k in a)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batch_equals_separate_contexts(kt, mixed):
+    evs, eos = events(mixed)
+    batch = kt.Batch(evs, eos)
+    singles = [kt.Solver(g, cfg, eos, pr) for g, cfg, pr in evs]
+    # replays of the captured step, with eager observables in between
+    for n in (1, 3, 4):
+        batch.step(n)
+        for s in singles:
+            s.step(n)
+        for k, s in enumerate(singles):
+            assert same(batch.fields(k), s.fields()), (mixed, n, k)
+            ob, os_ = batch.observables(k), s.observables()
+            assert ob["step"] == os_["step"] and ob["tau"] == os_["tau"]
+            assert ob["newton_iters_cells"] == os_["newton_iters_cells"]
+            assert ob["newton_iters_faces"] == os_["newton_iters_faces"]
+
+
+def test_batch_tuning_keeps_results(kt):
+    evs, eos = events()
+    batch = kt.Batch(evs, eos)
+    singles = [kt.Solver(g, cfg, eos, pr) for g, cfg, pr in evs]
+    batch.step(2)
+    kc = batch.tune()
+    print("autotuned eta planes per flux block:", kc, flush=True)
+    assert all(k in (1, 2, 4, 8) for k in kc)
+    batch.step(5)
+    for s in singles:
+        s.step(7)
+    for k, s in enumerate(singles):
+        assert same(batch.fields(k), s.fields()), k
+
+
+def test_batch_matches_oracle(kt):
+    """The batch against the FP64 oracle (10 steps, every event)."""
+    evs, eos = events()
+    batch = kt.Batch(evs, eos)
+    batch.step(10)
+    for k, (g, cfg, pr) in enumerate(evs):
+        phys = oracle.Physics.from_config(g, cfg)
+        sim = oracle.Simulation.from_primitives(phys, eos, pr)
+        sim.step(10)
+        r = sim.fields()
+        f = {key: v.cpu().numpy() for key, v in batch.fields(k).items()}
+        ee, eu = e_err(f["e"], r["e"]), u_err(f["u"], r["u"], sim.tau)
+        assert ee <= 1e-12 and eu <= 1e-12, (k, ee, eu)

@@ -1,0 +1,133 @@
+"""Mixed-precision state (KT_MIXED) against the FP64 oracle.
+
+T^{tau mu} (storage, KT flux, sources, Heun accumulation) and u^mu stay
+FP64; pi, Pi, e, p and the face speeds are stored in FP32 and the flux and
+relaxation-source arithmetic of pi and Pi is FP32; the inversion and the
+regulator run in FP64.  Errors use the measures of
+tests/test_gpu_parity.py; pi is measured against e + P0 (the scale of the
+stress tensor).  Gubser flow and the shock tube must stay within 1e-4 after
+200 steps; the hot-spot event reports its errors at 50/100/200 steps."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_06577_amd import inputs as I
+
+from tests.test_gpu_parity import ROOT, e_err, u_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kt():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1608_06577_amd import kt as K
+    K.lib()
+    return K
+
+
+def mixed(cfg):
+    c = dict(cfg)
+    c["mixed"] = True
+    return c
+
+
+def pi_err(q, r, scale):
+    """max over cells and the ten pi components of |dpi| / (e + P0)."""
+    return float(np.max(np.abs(q[4:14] - r[4:14]) / scale[None]))
+
+
+def run_mixed(kt, w, nsteps, band=0):
+    """Errors of the mixed-precision run against the oracle, over the cells at
+    least `band` cells away from the x and y boundaries."""
+    phys = oracle.Physics.from_config(w.grid, w.config)
+    sim = oracle.Simulation.from_primitives(phys, w.eos, w.prims)
+    gpu = kt.Solver(w.grid, mixed(w.config), w.eos, w.prims)
+    sim.step(nsteps)
+    gpu.step(nsteps)
+    f = {k: v.cpu().numpy() for k, v in gpu.fields().items()}
+    r = sim.fields()
+    if band:
+        cut = (Ellipsis, slice(band, -band), slice(band, -band))
+        f = {k: v[cut] for k, v in f.items()}
+        r = {k: v[cut] for k, v in r.items()}
+    p0, _, _ = oracle.eos_eval(w.eos, r["e"].ravel())
+    scale = (r["e"].ravel() + p0).reshape(r["e"].shape)
+    return dict(e=e_err(f["e"], r["e"]), u=u_err(f["u"], r["u"], sim.tau),
+                pi=pi_err(f["q"], r["q"], scale)), gpu
+
+
+def test_mixed_gubser_200_steps(kt):
+    """Viscous Gubser flow, 32^3 cells of 0.1 fm.  The 3.2 fm box is small: its
+    outflow corners (r ~ 1.7-2 fm) amplify any perturbation (there the FP32
+    differences grow from 1e-6 at step 50 to 1e-4 at step 200), so the bar
+    holds on the cells six or more cells from the x and y boundaries, the band
+    the analytic Gubser comparisons leave out as well."""
+    w = I.workload_gubser_viscous(n=32)
+    full, _ = run_mixed(kt, w, 200)
+    errs, gpu = run_mixed(kt, w, 200, band=6)
+    print("mixed gubser32 200 steps: whole box", {k: "%.2e" % v for k, v in full.items()},
+          "| without the 6-cell edge band", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    assert errs["e"] <= 1e-4 and errs["u"] <= 1e-4 and errs["pi"] <= 1e-4, errs
+    assert full["e"] <= 1e-3 and full["u"] <= 1e-3 and full["pi"] <= 1e-3, full
+    assert gpu.observables()["n_nan"] == 0
+
+
+def test_mixed_shock_tube_200_steps(kt):
+    """Relativistic Riemann problem (Sec. 5.1 test) in a Cartesian box, ideal
+    conformal fluid, 200 cells, 200 steps of dt = dx/4."""
+    g = I.Grid(200, 1, 1, 0.1, 0.1, 0.1)
+    cfg = I.default_config(dtau=0.025, cartesian=True, theta=1.0, e_floor=1e-12)
+    w = I.Workload("sod", g, 0.0, 200, cfg, I.eos_conformal(), I.sod_fields(g))
+    errs, gpu = run_mixed(kt, w, 200)
+    print("mixed shock tube 200 steps:", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    assert errs["e"] <= 1e-4 and errs["u"] <= 1e-4, errs
+
+
+def test_mixed_one_step_matches_fp64_closely(kt):
+    """One step on a smooth random viscous state with bulk: FP32 rounding only."""
+    g = I.Grid(71, 37, 9, 0.15, 0.2, 0.12)
+    cfg = I.default_config(eta_s=0.2, zeta_coef=0.1, periodic=(False, False, True), theta=1.4)
+    prims = I.random_smooth_fields(g, 0.7, seed=9, e_mean=6.0, pi_rel=0.05, Pi_rel=0.02)
+    w = I.Workload("rand", g, 0.7, 1, cfg, I.eos_c1_table(), prims)
+    errs, _ = run_mixed(kt, w, 1)
+    print("mixed one step:", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    assert errs["e"] <= 1e-6 and errs["u"] <= 1e-6 and errs["pi"] <= 1e-6, errs
+
+
+def test_mixed_hotspot_128_errors(kt):
+    """The 128^3 event in mixed precision against the oracle samples: errors at
+    50/100/200 steps, reported.  The event amplifies perturbations over 200
+    steps (the FP64 path's last-bit differences from the oracle grow to 2e-9 in
+    the dense cells, about 1e7 times); from FP32 rounding the same growth gives
+    about 1e-3 at step 200.  Required: median cells within 1e-6 at every step,
+    dense cells (e > 1e-3 e_max) within 1e-5 up to 100 steps."""
+    path = os.path.join(ROOT, "tests", "golden", "hotspot_128_fp64.npz")
+    if not os.path.exists(path):
+        pytest.skip("oracle samples not generated")
+    gold = np.load(path)
+    w = I.workload_hotspot()
+    gpu = kt.Solver(w.grid, mixed(w.config), w.eos, w.prims)
+    idx = gold["idx"]
+    done = 0
+    for s in (50, 100, 200):
+        gpu.step(s - done)
+        done = s
+        f = gpu.fields(("e", "u", "q"))
+        e = f["e"].reshape(-1)[idx].cpu().numpy()
+        u = f["u"].reshape(4, -1)[:, idx].cpu().numpy()
+        er, ur = gold["e_%d" % s], gold["u_%d" % s].T
+        tau, emax = float(gold["tau_%d" % s]), float(gold["emax_%d" % s])
+        de = np.abs(e - er) / np.maximum(er, 1e-6 * emax)
+        du = np.max(np.abs(u - ur) * np.array([1, 1, 1, tau])[:, None] / ur[0:1], axis=0)
+        hot = er > 1e-3 * emax
+        print("mixed hotspot128 step %d: e %.2e u %.2e | dense cells e %.2e u %.2e | median e %.1e u %.1e"
+              % (s, de.max(), du.max(), de[hot].max(), du[hot].max(), np.median(de), np.median(du)),
+              flush=True)
+        assert np.median(de) <= 1e-6 and np.median(du) <= 1e-6
+        if s <= 100:
+            assert de[hot].max() <= 1e-5 and du[hot].max() <= 1e-5
+    assert gpu.observables()["n_nan"] == 0
