@@ -175,11 +175,15 @@ __device__ __forceinline__ R face_H(const T *q, idx_t co, R theta, idx_t s0, idx
 // q^+ = q_R - slope_R/2 from the cell on its right; each is inverted like a
 // cell (warm start: the e of the cell it was extrapolated from) and the
 // velocity component normal to the face is stored.
-// One thread per face and side.  The launch is cut into six segments of
-// whole blocks, (x, y, eta) x (minus, plus); a thread's index within its
-// segment is the face index of fidx_x / fidx_y / fidx_e.
+// One thread per face and side.
+// The launch is cut into six segments of whole blocks, (x, y, eta) x (minus,
+// plus), in that order; a thread's index within its segment is the face
+// index of fidx_x / fidx_y / fidx_e.  (Interleaving the segments block by
+// block shares cells in L2 and halves this kernel's fetches, but measured
+// slower.)
 struct FaceLaunch {
-    unsigned first_block[7];   // first block of each segment; [6] = total
+    unsigned first_block[6];    // first block of each segment
+    unsigned nblocks;           // total
     double inv_nx1, inv_nx, inv_ny1, inv_plane;   // 1/(nx+1), 1/nx, 1/(ny+1), 1/(nx ny)
 };
 
@@ -193,7 +197,7 @@ __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, co
     typedef S R;   // reconstruction arithmetic; the inversion itself is FP64
     int seg = 0;
 #pragma unroll
-    for (int t = 1; t < 6; ++t) seg += b >= L.first_block[t] ? 1 : 0;
+    for (int k = 1; k < 6; ++k) seg += b >= L.first_block[k] ? 1 : 0;
     const int d = seg >> 1, side = seg & 1;     // side 0: q^-, side 1: q^+
     const idx_t t = (idx_t)(b - L.first_block[seg]) * 256 + threadIdx.x;
     const long long nf = d == 0 ? G.nfx : (d == 1 ? G.nfy : G.nfe);
@@ -284,7 +288,7 @@ static FaceLaunch face_launch(const FaceGeo &G, int nx, int ny)
         L.first_block[s] = acc;
         acc += (unsigned)((nf[s >> 1] + 255) / 256);
     }
-    L.first_block[6] = acc;
+    L.nblocks = acc;
     return L;
 }
 
@@ -630,20 +634,10 @@ __global__ __launch_bounds__(256) void recover_kernel(Phys P, Eos E, double tau,
 
 // ------------------------------------------------------------- batches ---
 // One launch advances every event of a batch.  Block g of the launch (after
-// the XCD renumbering) belongs to the event e with first[e] <= g < first[e+1]
-// and is that event's block g - first[e]; the event's arguments sit in a
-// device table read with wave-uniform loads.  Events share tau (kept on the
-// device so that a captured step can be replayed) and the time step.
-__device__ __forceinline__ int batch_event(const unsigned *first, int n, unsigned g)
-{
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (first[mid] <= g) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
+// the XCD renumbering) belongs to event e = map[g] and is that event's block
+// g - first[e]; the event's arguments sit in a device table read with
+// wave-uniform loads.  Events share tau (kept on the device so that a
+// captured step can be replayed) and the time step.
 
 template <typename S>
 struct BStage {             // one event of a stage (sources + flux launches)
@@ -689,11 +683,12 @@ struct BCopy {              // u^{n-1} <- u^n, u^n <- u^{n+1} of one event (4 * 
 
 template <bool CART, bool STAGE2, typename S>
 __global__ __launch_bounds__(256) void sources_batch(const BStage<S> *__restrict__ tab,
-                                                     const unsigned *__restrict__ first, int n,
+                                                     const unsigned short *__restrict__ map,
+                                                     const unsigned *__restrict__ first,
                                                      const double *__restrict__ tau_dev)
 {
     const unsigned g = xcd_block(blockIdx.x, gridDim.x);
-    const int ev = batch_event(first, n, g);
+    const int ev = map[g];
     const BStage<S> &A = tab[ev];
     const unsigned lb = g - first[ev];
     const unsigned bx = lb % A.sgx, by = (lb / A.sgx) % A.sgy, bz = lb / (A.sgx * A.sgy);
@@ -703,12 +698,13 @@ __global__ __launch_bounds__(256) void sources_batch(const BStage<S> *__restrict
 
 template <bool STAGE2, typename S>
 __global__ __launch_bounds__(256) void flux_batch(const BStage<S> *__restrict__ tab,
-                                                  const unsigned *__restrict__ first, int n)
+                                                  const unsigned short *__restrict__ map,
+                                                  const unsigned *__restrict__ first)
 {
     __shared__ double HbT[PTT][256];
     __shared__ S Hb[NQ - PTT][256];
     const unsigned g = xcd_block(blockIdx.x, gridDim.x);
-    const int ev = batch_event(first, n, g);
+    const int ev = map[g];
     const BStage<S> &A = tab[ev];
     const unsigned lb = g - first[ev];
     const unsigned bx = lb % A.fgx, by = (lb / A.fgx) % A.fgy, bz = lb / (A.fgx * A.fgy);
@@ -717,11 +713,12 @@ __global__ __launch_bounds__(256) void flux_batch(const BStage<S> *__restrict__ 
 
 template <bool CART, typename S>
 __global__ __launch_bounds__(256) void recover_batch(const BRec<S> *__restrict__ tab,
-                                                     const unsigned *__restrict__ first, int n,
+                                                     const unsigned short *__restrict__ map,
+                                                     const unsigned *__restrict__ first,
                                                      const double *__restrict__ tau_dev)
 {
     const unsigned g = blockIdx.x;
-    const int ev = batch_event(first, n, g);
+    const int ev = map[g];
     const BRec<S> &A = tab[ev];
     const double tau = tau_dev[0] + A.P.dtau;
     recover_body<CART, false, S>(A.P, A.E, tau, A.qT, A.qP, A.e, A.p, A.u, 1, 1, nullptr, A.slots,
@@ -730,11 +727,12 @@ __global__ __launch_bounds__(256) void recover_batch(const BRec<S> *__restrict__
 
 template <bool CART, typename S>
 __global__ __launch_bounds__(256) void faces_batch(const BFace<S> *__restrict__ tab,
-                                                   const unsigned *__restrict__ first, int n,
+                                                   const unsigned short *__restrict__ map,
+                                                   const unsigned *__restrict__ first,
                                                    const double *__restrict__ tau_dev)
 {
     const unsigned g = xcd_block(blockIdx.x, gridDim.x);
-    const int ev = batch_event(first, n, g);
+    const int ev = map[g];
     const BFace<S> &A = tab[ev];
     const unsigned lb = g - first[ev];
     const double tau = tau_dev[0] + A.P.dtau;
@@ -743,10 +741,11 @@ __global__ __launch_bounds__(256) void faces_batch(const BFace<S> *__restrict__ 
 }
 
 __global__ __launch_bounds__(256) void rotate_batch(const BCopy *__restrict__ tab,
-                                                    const unsigned *__restrict__ first, int n)
+                                                    const unsigned short *__restrict__ map,
+                                                    const unsigned *__restrict__ first)
 {
     const unsigned g = blockIdx.x;
-    const int ev = batch_event(first, n, g);
+    const int ev = map[g];
     const BCopy &A = tab[ev];
     const long long i = (long long)(g - first[ev]) * 256 + threadIdx.x;
     if (i < A.n) {
@@ -1090,7 +1089,7 @@ static FaceGeo face_geo(const kt_params *p)
 
 static long long face_waves(const kt_params *p)
 {
-    return (long long)face_launch(face_geo(p), p->nx, p->ny).first_block[6] * 4;
+    return (long long)face_launch(face_geo(p), p->nx, p->ny).nblocks * 4;
 }
 
 static long long stage_waves(const kt_params *p)
@@ -1236,7 +1235,7 @@ static kt_status run_faces_t(kt_ctx *c, double tau, int which)
     hipError_t e = prof_mark(c, 2, true);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
     const FaceLaunch L = face_launch(c->G, c->P.nx, c->P.ny);
-    const dim3 g(L.first_block[6]), b(256);
+    const dim3 g(L.nblocks), b(256);
     const double *qT = c->qT[which];
     const S *qP = (const S *)c->qP[which], *ee = (const S *)c->e;
     e = cart ? launch(face_speeds_kernel<true, S>, g, b, c->stream, c->P, c->E, c->G, L, tau, qT, qP,
@@ -1777,6 +1776,7 @@ struct kt_batch {
     unsigned nb_src, nb_flux, nb_rec, nb_face, nb_rot;
     size_t o_s1, o_s2, o_r1, o_r2, o_f1, o_f2, o_rot;             // table offsets
     size_t o_fsrc, o_fflux, o_frec, o_fface, o_frot;              // first-block arrays
+    size_t o_msrc, o_mflux, o_mrec, o_mface, o_mrot;              // block -> event maps
     hipGraph_t graph;
     hipGraphExec_t exec;
     bool have_graph;
@@ -1795,7 +1795,8 @@ static kt_status bfail(kt_batch *b, kt_status s, const char *fmt, ...)
     return s;
 }
 
-// bytes of the device tables of n events (the larger, FP64 layout)
+// bytes of the device tables of n events (the larger, FP64 layout), not
+// counting the block -> event maps (2 bytes per block, event_blocks)
 static size_t batch_table_bytes(int n)
 {
     size_t t = 0;
@@ -1807,9 +1808,23 @@ static size_t batch_table_bytes(int n)
     return t;
 }
 
+// blocks of every launch kind of one event (flux at one eta plane per block, the most)
+static size_t event_blocks(const kt_params *p)
+{
+    const size_t sg = (size_t)((p->nx + 63) / 64) * ((p->ny + 3) / 4);
+    const size_t ncell = (size_t)p->nx * p->ny * p->neta;
+    return 2 * sg * p->neta + (ncell + 255) / 256 + (size_t)face_waves(p) / 4 + (4 * (size_t)cell_stride(p) + 255) / 256;
+}
+
 static size_t event_ws(const kt_params *p, const kt_eos *eos)
 {
     return round_up(layout(p, eos).total, 256);
+}
+
+// the batch's table region: argument tables plus the block -> event maps of nb blocks
+static size_t batch_tab_region(int n, size_t nb)
+{
+    return round_up(batch_table_bytes(n), 256) + round_up(nb * sizeof(unsigned short), 256) + 5 * 256;
 }
 
 // Build the per-event argument tables of one step and upload them (the
@@ -1877,7 +1892,7 @@ static kt_status batch_tables(kt_batch *b)
         fs[e + 1] = fs[e] + sg * (unsigned)P.neta;
         ff[e + 1] = ff[e] + sg * (unsigned)((P.neta + b->kc[e] - 1) / b->kc[e]);
         fr[e + 1] = fr[e] + (unsigned)((P.ncell + 255) / 256);
-        fc[e + 1] = fc[e] + f1[e].L.first_block[6];
+        fc[e + 1] = fc[e] + f1[e].L.nblocks;
         fo[e + 1] = fo[e] + (unsigned)((S4 + 255) / 256);
     }
     b->nb_src = fs[n];
@@ -1885,6 +1900,13 @@ static kt_status batch_tables(kt_batch *b)
     b->nb_rec = fr[n];
     b->nb_face = fc[n];
     b->nb_rot = fo[n];
+    auto mk = [&](const std::vector<unsigned> &f) {
+        std::vector<unsigned short> m(f[n]);
+        for (int e = 0; e < n; ++e)
+            for (unsigned g = f[e]; g < f[e + 1]; ++g) m[g] = (unsigned short)e;
+        return m;
+    };
+    const std::vector<unsigned short> ms = mk(fs), mf = mk(ff), mr = mk(fr), mc = mk(fc), mo = mk(fo);
     size_t off = 0;
     auto place = [&](size_t bytes) { const size_t o = off; off += round_up(bytes, 256); return o; };
     b->o_s1 = place(sizeof(BStage<S>) * n);
@@ -1899,6 +1921,11 @@ static kt_status batch_tables(kt_batch *b)
     b->o_frec = place(sizeof(unsigned) * (n + 1));
     b->o_fface = place(sizeof(unsigned) * (n + 1));
     b->o_frot = place(sizeof(unsigned) * (n + 1));
+    b->o_msrc = place(sizeof(unsigned short) * ms.size());
+    b->o_mflux = place(sizeof(unsigned short) * mf.size());
+    b->o_mrec = place(sizeof(unsigned short) * mr.size());
+    b->o_mface = place(sizeof(unsigned short) * mc.size());
+    b->o_mrot = place(sizeof(unsigned short) * mo.size());
     if (off > b->tab_bytes) return bfail(b, KT_E_ALLOC, "batch tables need %zu bytes", off);
     std::vector<char> h(off, 0);
     auto put = [&](size_t o, const void *src, size_t bytes) { memcpy(h.data() + o, src, bytes); };
@@ -1914,6 +1941,11 @@ static kt_status batch_tables(kt_batch *b)
     put(b->o_frec, fr.data(), sizeof(unsigned) * (n + 1));
     put(b->o_fface, fc.data(), sizeof(unsigned) * (n + 1));
     put(b->o_frot, fo.data(), sizeof(unsigned) * (n + 1));
+    put(b->o_msrc, ms.data(), sizeof(unsigned short) * ms.size());
+    put(b->o_mflux, mf.data(), sizeof(unsigned short) * mf.size());
+    put(b->o_mrec, mr.data(), sizeof(unsigned short) * mr.size());
+    put(b->o_mface, mc.data(), sizeof(unsigned short) * mc.size());
+    put(b->o_mrot, mo.data(), sizeof(unsigned short) * mo.size());
     hipError_t e = hipMemcpyAsync(b->tab, h.data(), off, hipMemcpyHostToDevice, b->user);
     if (e == hipSuccess) e = hipStreamSynchronize(b->user);
     if (e != hipSuccess) return bfail(b, KT_E_HIP, "batch tables: %s", hipGetErrorString(e));
@@ -1929,32 +1961,33 @@ static hipError_t batch_step_launches(kt_batch *b, hipStream_t st)
     auto F = [&](size_t o) { return (const unsigned *)(b->tab + o); };
     const double *tau = b->tau_dev;
     const dim3 blk2(64, 4), blk(256);
+    auto M = [&](size_t o) { return (const unsigned short *)(b->tab + o); };
     hipError_t e = launch(sources_batch<CART, false, S>, dim3(b->nb_src), blk2, st,
-                          (const BStage<S> *)T(b->o_s1), F(b->o_fsrc), n, tau);
+                          (const BStage<S> *)T(b->o_s1), M(b->o_msrc), F(b->o_fsrc), tau);
     if (e == hipSuccess)
         e = launch(flux_batch<false, S>, dim3(b->nb_flux), blk2, st, (const BStage<S> *)T(b->o_s1),
-                   F(b->o_fflux), n);
+                   M(b->o_mflux), F(b->o_fflux));
     if (e == hipSuccess)
         e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r1),
-                   F(b->o_frec), n, tau);
+                   M(b->o_mrec), F(b->o_frec), tau);
     if (e == hipSuccess)
         e = launch(faces_batch<CART, S>, dim3(b->nb_face), blk, st, (const BFace<S> *)T(b->o_f1),
-                   F(b->o_fface), n, tau);
+                   M(b->o_mface), F(b->o_fface), tau);
     if (e == hipSuccess)
         e = launch(sources_batch<CART, true, S>, dim3(b->nb_src), blk2, st,
-                   (const BStage<S> *)T(b->o_s2), F(b->o_fsrc), n, tau);
+                   (const BStage<S> *)T(b->o_s2), M(b->o_msrc), F(b->o_fsrc), tau);
     if (e == hipSuccess)
         e = launch(flux_batch<true, S>, dim3(b->nb_flux), blk2, st, (const BStage<S> *)T(b->o_s2),
-                   F(b->o_fflux), n);
+                   M(b->o_mflux), F(b->o_fflux));
     if (e == hipSuccess)
         e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r2),
-                   F(b->o_frec), n, tau);
+                   M(b->o_mrec), F(b->o_frec), tau);
     if (e == hipSuccess)
         e = launch(faces_batch<CART, S>, dim3(b->nb_face), blk, st, (const BFace<S> *)T(b->o_f2),
-                   F(b->o_fface), n, tau);
+                   M(b->o_mface), F(b->o_fface), tau);
     if (e == hipSuccess)
-        e = launch(rotate_batch, dim3(b->nb_rot), blk, st, (const BCopy *)T(b->o_rot),
-                   F(b->o_frot), n);
+        e = launch(rotate_batch, dim3(b->nb_rot), blk, st, (const BCopy *)T(b->o_rot), M(b->o_mrot),
+                   F(b->o_frot));
     if (e == hipSuccess) e = launch(tau_advance_kernel, dim3(1), dim3(64), st, b->tau_dev, b->dtau);
     return e;
 }
@@ -1986,12 +2019,14 @@ extern "C" {
 size_t kt_batch_workspace_bytes(const kt_params *p, int32_t n_events, const kt_eos *eos)
 {
     if (!p || n_events < 1 || !eos) return 0;
-    size_t t = 0;
+    if (n_events > 65535) return 0;
+    size_t t = 0, nb = 0;
     for (int e = 0; e < n_events; ++e) {
         if (check_args(&p[e], eos)) return 0;
         t += event_ws(&p[e], eos);
+        nb += event_blocks(&p[e]);
     }
-    return t + 256 + round_up(batch_table_bytes(n_events), 256);
+    return t + 256 + batch_tab_region(n_events, nb);
 }
 
 void kt_batch_destroy(kt_batch *b)
@@ -2015,7 +2050,7 @@ kt_status kt_batch_init(const kt_params *p, int32_t n_events, const kt_eos *eos,
     if (!out) return bfail(nullptr, KT_E_ARG, "out is null");
     *out = nullptr;
     if (!p || !eos || !s0 || !d_ws) return bfail(nullptr, KT_E_ARG, "null argument");
-    if (n_events < 1) return bfail(nullptr, KT_E_ARG, "n_events must be >= 1");
+    if (n_events < 1 || n_events > 65535) return bfail(nullptr, KT_E_ARG, "n_events must lie in [1, 65535]");
     if (((uintptr_t)d_ws) % 256) return bfail(nullptr, KT_E_ARG, "workspace must be 256-byte aligned");
     for (int e = 0; e < n_events; ++e) {
         if (const char *m = check_args(&p[e], eos)) return bfail(nullptr, KT_E_ARG, "event %d: %s", e, m);
@@ -2051,7 +2086,11 @@ kt_status kt_batch_init(const kt_params *p, int32_t n_events, const kt_eos *eos,
     b->tau_dev = (double *)(base + off);
     off += 256;
     b->tab = base + off;
-    b->tab_bytes = round_up(batch_table_bytes(n_events), 256);
+    {
+        size_t nb = 0;
+        for (int e = 0; e < n_events; ++e) nb += event_blocks(&p[e]);
+        b->tab_bytes = batch_tab_region(n_events, nb);
+    }
     hipError_t he = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (he == hipSuccess) he = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming);
     if (he == hipSuccess) he = hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming);
