@@ -35,6 +35,12 @@ STEP_VALUES = 103
 #   recover  reads q (15), e; writes e, p, u (4) and the 10 regulated pi           = 32
 #   faces    reads 9 components of q and e; writes v^-, v^+ of 3 faces (6)         = 16
 KERNEL_VALUES = {"flux": 45.0, "sources": 47.5, "recover": 32.0, "faces": 16.0}
+# HBM bytes per launch of the FP64 kernels on this event, from rocprofv3 FETCH_SIZE x 2.000 and
+# WRITE_SIZE x 1.000 (scale factors of a 256 MiB device copy), profiles/kt_step_hotspot128_fp64.md;
+# valid for the kernel sources whose hash is TRAFFIC_SOURCES (else the traffic is reported as null)
+TRAFFIC_SOURCES = "69b7fd7afb832a7d"
+TRAFFIC_BYTES = {"faces": 1.092e9 + 1.079e8, "flux": 1.409e9 + 2.517e8,
+                 "sources": 0.5 * (9.469e8 + 1.163e9) + 2.517e8, "recover": 2.705e8 + 3.169e8}
 KERNEL_NAMES = {"flux": "flux_kernel (KT flux divergence + stage update)",
                 "sources": "sources_kernel (App. B sources + stage update)",
                 "recover": "recover_kernel (Newton inversion + regulator)",
@@ -53,6 +59,15 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="grid cells per axis")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-events leg")
     return ap.parse_args()
+
+
+def kernel_sources_hash():
+    """First 16 hex digits of the SHA-256 of the kernel sources, concatenated."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kt_main.hip", "kt_device.hpp", "kt_mlp.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1608_06577_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def copy_probe():
@@ -125,8 +140,9 @@ def main():
     dom_avg_s = per[dom] * 1e-3
     dom_bytes = 8.0 * ncell * KERNEL_VALUES[dom]
     achieved = dom_bytes / dom_avg_s / 1e9
+    traffic = TRAFFIC_BYTES[dom] if kernel_sources_hash() == TRAFFIC_SOURCES else None
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": KERNEL_NAMES[dom], "bytes_per_launch": dom_bytes,
             "mean_launch_ms": per[dom],
             "per_launch_ms": per}
