@@ -38,9 +38,9 @@ KERNEL_VALUES = {"flux": 45.0, "sources": 47.5, "recover": 32.0, "faces": 16.0}
 # HBM bytes per launch of the FP64 kernels on this event, from rocprofv3 FETCH_SIZE x 2.000 and
 # WRITE_SIZE x 1.000 (scale factors of a 256 MiB device copy), profiles/kt_step_hotspot128_fp64.md;
 # valid for the kernel sources whose hash is TRAFFIC_SOURCES (else the traffic is reported as null)
-TRAFFIC_SOURCES = "69b7fd7afb832a7d"
-TRAFFIC_BYTES = {"faces": 1.092e9 + 1.079e8, "flux": 1.409e9 + 2.517e8,
-                 "sources": 0.5 * (9.469e8 + 1.163e9) + 2.517e8, "recover": 2.705e8 + 3.169e8}
+TRAFFIC_SOURCES = "9105ed76fb7ebc8e"
+TRAFFIC_BYTES = {"faces": 1.0835e9 + 1.079e8, "flux": 0.5 * (1.4083e9 + 1.4064e9) + 2.517e8,
+                 "sources": 0.5 * (9.503e8 + 1.1545e9) + 2.517e8, "recover": 2.705e8 + 3.170e8}
 KERNEL_NAMES = {"flux": "flux_kernel (KT flux divergence + stage update)",
                 "sources": "sources_kernel (App. B sources + stage update)",
                 "recover": "recover_kernel (Newton inversion + regulator)",

@@ -23,6 +23,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -841,22 +842,43 @@ __global__ __launch_bounds__(256) void recover_standalone_kernel(Phys P, Eos E, 
     if (R.flags) R.flags[s] = fl;
 }
 
-// sum of the counter slots (deterministic: one thread per counter)
-__global__ void slots_reduce_kernel(const unsigned long long *slots, long long nwaves,
-                                    unsigned long long *out)
+// sum of the counter slots: per-block partial sums, then one block adds them
+// (integer sums, so the result does not depend on the order)
+constexpr int SLOT_BLOCKS = 256;
+
+__global__ __launch_bounds__(256) void slots_partial_kernel(const unsigned long long *slots,
+                                                            long long nwaves,
+                                                            unsigned long long *partial)
 {
-    __shared__ unsigned long long part[C_COUNT][64];
-    const int c = threadIdx.y, l = threadIdx.x;
-    unsigned long long v = 0;
-    if (c < C_COUNT)
-        for (long long w = l; w < nwaves; w += 64) v += slots[w * C_COUNT + c];
-    if (c < C_COUNT) part[c][l] = v;
-    __syncthreads();
-    if (c < C_COUNT && l == 0) {
-        unsigned long long t = 0;
-        for (int k = 0; k < 64; ++k) t += part[c][k];
-        out[c] = t;
+    __shared__ unsigned long long red[4][C_COUNT];
+    unsigned long long v[C_COUNT];
+#pragma unroll
+    for (int c = 0; c < C_COUNT; ++c) v[c] = 0;
+    for (long long w = (long long)blockIdx.x * blockDim.x + threadIdx.x; w < nwaves;
+         w += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int c = 0; c < C_COUNT; ++c) v[c] += slots[w * C_COUNT + c];
     }
+#pragma unroll
+    for (int c = 0; c < C_COUNT; ++c) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_xor(v[c], off);
+    }
+    if ((threadIdx.x & 63) == 0)
+        for (int c = 0; c < C_COUNT; ++c) red[threadIdx.x >> 6][c] = v[c];
+    __syncthreads();
+    if (threadIdx.x < C_COUNT)
+        partial[(long long)blockIdx.x * C_COUNT + threadIdx.x] =
+            red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+__global__ void slots_final_kernel(const unsigned long long *partial, int nb, unsigned long long *out)
+{
+    const int c = threadIdx.x;
+    if (c >= C_COUNT) return;
+    unsigned long long t = 0;
+    for (int b = 0; b < nb; ++b) t += partial[(long long)b * C_COUNT + c];
+    out[c] = t;
 }
 
 // ---------------------------------------------------------- observables --
@@ -1124,7 +1146,10 @@ static Layout layout(const kt_params *p, const kt_eos *eos)
     L.nwaves = L.nwaves > fw ? L.nwaves : fw;
     L.slots = off; off += round_up((size_t)L.nwaves * C_COUNT * sizeof(unsigned long long), 256);
     L.ctr = off; off += 256;
-    L.partial = off; off += round_up((size_t)OBS_BLOCKS * O_COUNT * sizeof(double), 256);
+    // observables partials, reused afterwards for the counter partials
+    L.partial = off;
+    off += round_up(std::max((size_t)OBS_BLOCKS * O_COUNT * sizeof(double),
+                             (size_t)SLOT_BLOCKS * C_COUNT * sizeof(unsigned long long)), 256);
     L.obs = off; off += 256;
     L.mlp = off; off += round_up((size_t)3 * ktm::NP * sizeof(float), 256);
     L.mlp_part = off; off += round_up((size_t)ktm::BWD_BLOCKS * ktm::NP * sizeof(float), 256);
@@ -1563,8 +1588,11 @@ kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out)
         if (e == hipSuccess)
             e = launch(obs_final_kernel, dim3(1), dim3(64), c->stream, (const double *)c->partial, OBS_BLOCKS, c->obs);
         if (e == hipSuccess)
-            e = launch(slots_reduce_kernel, dim3(1), dim3(64, C_COUNT), c->stream,
-                       (const unsigned long long *)c->slots, c->nwaves, c->ctr);
+            e = launch(slots_partial_kernel, dim3(SLOT_BLOCKS), dim3(256), c->stream,
+                       (const unsigned long long *)c->slots, c->nwaves, (unsigned long long *)c->partial);
+        if (e == hipSuccess)
+            e = launch(slots_final_kernel, dim3(1), dim3(64), c->stream,
+                       (const unsigned long long *)c->partial, SLOT_BLOCKS, c->ctr);
         if (e == hipSuccess) e = hipMemcpyAsync(res, c->obs, sizeof(res), hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(ctr, c->ctr, sizeof(ctr), hipMemcpyDeviceToHost, c->stream);
     }

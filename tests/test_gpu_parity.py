@@ -231,3 +231,36 @@ def test_periodic_cartesian_conservation_on_gpu(kt):
     d = (q1[:4].sum(dim=(1, 2, 3)) - q0).abs().max().item()
     assert d <= 1e-13 * scale
     torch.cuda.synchronize()
+
+
+def test_observables_match_exported_fields(kt):
+    """The block reductions of kt_observables (sums, maxima, counts) against
+    numpy on the exported fields of the same state."""
+    w = I.workload_hotspot(nx=56, ny=52, neta=24, dx=0.4, deta=0.5, n_hot=60, seed=3)
+    gpu = kt.Solver(w.grid, w.config, w.eos, w.prims)
+    gpu.step(12)
+    obs = gpu.observables()
+    f = {k: v.cpu().numpy() for k, v in gpu.fields().items()}
+    tau, g = obs["tau"], w.grid
+    q, e, u = f["q"], f["e"], f["u"]
+    vol = g.dx * g.dy * g.deta * tau
+    rel = lambda a, b: abs(a - b) / max(abs(b), 1e-300)
+    assert rel(obs["energy"], q[0].sum() * vol) < 1e-12
+    for i in range(3):
+        # the momenta nearly cancel over the box: bound the summation-order
+        # difference by the sum of magnitudes
+        scale = np.abs(q[1 + i]).sum() * vol
+        assert abs(obs["momentum"][i] - q[1 + i].sum() * vol) <= 1e-13 * scale
+    assert obs["e_max"] == e.max()
+    _, _, T = oracle.eos_eval(w.eos, e.ravel())
+    assert rel(obs["T_max"], T.max()) < 1e-12
+    v = np.abs(u[1:] / u[:1])
+    v[2] *= tau
+    assert rel(obs["v_max"], v.max()) < 1e-13
+    cfl = w.config["dtau"] * max((np.abs(u[1] / u[0]) / g.dx).max(), (np.abs(u[2] / u[0]) / g.dy).max(),
+                                 (np.abs(u[3] / u[0]) / g.deta).max())
+    assert rel(obs["cfl"], cfl) < 1e-13
+    norm = u[0] ** 2 - u[1] ** 2 - u[2] ** 2 - tau * tau * u[3] ** 2
+    assert abs(obs["norm_err"] - np.abs(norm - 1).max()) < 1e-14
+    assert obs["n_nan"] == 0 and obs["n_recover_cells"] == g.ncells * (2 * 12 + 1)
+    assert obs["n_floor"] > 0 and obs["n_fallback"] == 0
