@@ -156,18 +156,14 @@ __device__ __forceinline__ void slot_add(unsigned long long *slots, long long wa
 __device__ __forceinline__ int iter_bits(const Phys &P) { return 32 - __clz(P.newton_max); }
 
 // ------------------------------------------------------------ KT flux ----
-// One face between the cells s1 (left) and s2 (right) with outer neighbours
-// s0 and s3 (Sec. 3.1): minmod slopes, half-cell extrapolations
-// q^- = q_L + slope_L/2 and q^+ = q_R - slope_R/2, the inversion of both
-// (face_speeds_kernel; Sec. 3.1 last paragraph), the local speed
-// a = max(|v^-|, |v^+|) and H = (v^+ q^+ + v^- q^-)/2 - a (q^+ - q^-)/2.
-template <typename R, typename T>
-__device__ __forceinline__ R face_H(const T *q, idx_t co, R theta, idx_t s0, idx_t s1, idx_t s2,
-                                    idx_t s3, R vm, R vp, R a)
+// One face between a left cell L and a right cell R (Sec. 3.1): with the
+// minmod slopes of both cells, the half-cell extrapolations
+// q^- = q_L + slope_L/2 and q^+ = q_R - slope_R/2, the velocities of their
+// inversions v^-, v^+ (face_speeds_kernel; Sec. 3.1 last paragraph), the
+// local speed a = max(|v^-|, |v^+|) and H = (v^+ q^+ + v^- q^-)/2 - a (q^+ - q^-)/2.
+template <typename R>
+__device__ __forceinline__ R face_H(R qm, R qp, R vm, R vp, R a)
 {
-    const R a0 = R(ld(q, co + s0)), a1 = R(ld(q, co + s1)), a2 = R(ld(q, co + s2)), a3 = R(ld(q, co + s3));
-    const R qm = a1 + R(0.5) * slope(a0, a1, a2, theta);
-    const R qp = a2 - R(0.5) * slope(a1, a2, a3, theta);
     return R(0.5) * (vp * qp + vm * qm) - R(0.5) * a * (qp - qm);
 }
 
@@ -512,22 +508,36 @@ __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const
         const idx_t e0 = col + (idx_t)zm2 * plane, e1 = col + (idx_t)zm1 * plane;
         const idx_t e3 = col + (idx_t)zp1 * plane, e4 = col + (idx_t)zp2 * plane;
         // divergence D of one component (array q, component offset co) in the
-        // arithmetic type RR, with the eta carry Hc
+        // arithmetic type RR, with the eta carry Hc.  The fourteen values of the
+        // stencil are loaded together (no load waits on a branch), and each
+        // cell's slope along a direction is computed once.
         auto divergence = [&](auto rtag, const auto *q, idx_t co, auto *Hc) {
             typedef decltype(rtag) RR;
-            const RR th = RR(P.theta);
-            // x
-            const RR Hx = face_H<RR>(q, co, th, rx + xm2, rx + xm1, rx + x0, rx + xp1, RR(vmx), RR(vpx), RR(ax));
-            RR Hr = __shfl_down(Hx, 1);
-            if (right)
-                Hr = face_H<RR>(q, co, th, rx + xm1, rx + x0, rx + xp1, rx + xp2, RR(vmr), RR(vpr), RR(axr));
-            RR D = (Hx - Hr) * RR(P.inv_dx);
+            const RR th = RR(P.theta), h = RR(0.5);
+            const RR xa = RR(ld(q, co + rx + xm2)), xb = RR(ld(q, co + rx + xm1)), xc = RR(ld(q, co + rx + x0));
+            const RR xd = RR(ld(q, co + rx + xp1)), xe = RR(ld(q, co + rx + xp2));
+            const RR ya = RR(ld(q, co + r0)), yb = RR(ld(q, co + r1)), yc = RR(ld(q, co + s));
+            const RR yd = RR(ld(q, co + r3)), ye = RR(ld(q, co + r4));
+            const RR ea = RR(ld(q, co + e0)), eb = RR(ld(q, co + e1));
+            const RR ed = RR(ld(q, co + e3)), ee = RR(ld(q, co + e4));
+            // x: the face left of the cell; the right one from lane l+1 (lane 63: its own)
+            const RR sxb = slope(xa, xb, xc, th), sxc = slope(xb, xc, xd, th), sxd = slope(xc, xd, xe, th);
+            const RR Hx = face_H<RR>(xb + h * sxb, xc - h * sxc, RR(vmx), RR(vpx), RR(ax));
+            const RR Hown = face_H<RR>(xc + h * sxc, xd - h * sxd, RR(vmr), RR(vpr), RR(axr));
+            const RR Hnb = __shfl_down(Hx, 1);
+            RR D = (Hx - (right ? Hown : Hnb)) * RR(P.inv_dx);
             // y
-            D += (face_H<RR>(q, co, th, r0, r1, s, r3, RR(vmy0), RR(vpy0), RR(ay0))
-                - face_H<RR>(q, co, th, r1, s, r3, r4, RR(vmy1), RR(vpy1), RR(ay1))) * RR(P.inv_dy);
-            // eta
-            const RR Hb0 = kk == 0 ? face_H<RR>(q, co, th, e0, e1, s, e3, RR(vmb), RR(vpb), RR(ab)) : Hc[tid];
-            const RR Ht = face_H<RR>(q, co, th, e1, s, e3, e4, RR(vme), RR(vpe), RR(ae));
+            const RR syb = slope(ya, yb, yc, th), syc = slope(yb, yc, yd, th), syd = slope(yc, yd, ye, th);
+            D += (face_H<RR>(yb + h * syb, yc - h * syc, RR(vmy0), RR(vpy0), RR(ay0))
+                - face_H<RR>(yc + h * syc, yd - h * syd, RR(vmy1), RR(vpy1), RR(ay1))) * RR(P.inv_dy);
+            // eta: the bottom face is carried from the plane below except in the first plane
+            const RR sec = slope(eb, yc, ed, th), sed = slope(yc, ed, ee, th);
+            RR Hb0;
+            if (kk == 0)
+                Hb0 = face_H<RR>(eb + h * slope(ea, eb, yc, th), yc - h * sec, RR(vmb), RR(vpb), RR(ab));
+            else
+                Hb0 = Hc[tid];
+            const RR Ht = face_H<RR>(yc + h * sec, ed - h * sed, RR(vme), RR(vpe), RR(ae));
             Hc[tid] = Ht;
             D += (Hb0 - Ht) * RR(P.inv_deta);
             return D;
@@ -535,18 +545,20 @@ __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const
 #pragma unroll 1
         for (int c = 0; c < PTT; ++c) {
             const idx_t co = (idx_t)c * SS;
+            const double prev = ld(outT, co + s);    // s is a cell of the grid for every lane
             const double D = divergence(0.0, qT, co, HbT[c]);
             if (out_ok) {
-                const double t = ld(outT, co + s) + f * D;
+                const double t = prev + f * D;
                 st(outT, co + s, STAGE2 ? 0.5 * t : t);
             }
         }
 #pragma unroll 1
         for (int c = c0; c < c1; ++c) {
             const idx_t co = (idx_t)(c - PTT) * SS;
+            const R prev = R(ld(outP, co + s));
             const R D = divergence(R(0), qP, co, Hb[c - PTT]);
             if (out_ok) {
-                const R t = R(ld(outP, co + s)) + R(f) * D;
+                const R t = prev + R(f) * D;
                 st(outP, co + s, STAGE2 ? R(0.5) * t : t);
             }
         }
