@@ -289,26 +289,47 @@ static FaceLaunch face_launch(const FaceGeo &G, int nx, int ny)
     return L;
 }
 
+// The values of a neighbour cell that the central differences along axis
+// i = d+1 need, loaded together (whether or not the fluid is viscous, so
+// that no load waits behind a branch)
+template <typename S>
+struct NbCell {
+    double u[4];      // u^mu
+    double p, Pi;     // p(e), Pi
+    double pt[4];     // pi^{tau mu}
+    double pi[3];     // pi^{i x}, pi^{i y}, pi^{i eta}
+    __device__ __forceinline__ void load(const Fields<S> &F, idx_t SS, idx_t s, int d)
+    {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) u[m] = ld(F.u, (idx_t)m * SS + s);
+        p = (double)ld(F.p, s);
+        Pi = (double)ld(F.qP, (idx_t)(BPI - PTT) * SS + s);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) pt[n] = (double)ld(F.qP, (idx_t)(pi_index(0, n) - PTT) * SS + s);
+#pragma unroll
+        for (int n = 1; n < 4; ++n) pi[n - 1] = (double)ld(F.qP, (idx_t)(pi_index(d + 1, n) - PTT) * SS + s);
+    }
+};
+
 // A^{i nu} = T^{i nu} - v^i T^{tau nu} of one cell for axis i = d+1 (Eqs. Ttt-Tij):
 //   A^{i tau} = P v^i + pi^{i tau} - v^i pi^{tau tau}
 //   A^{i j}   = -P g^{ij} + pi^{ij} - v^i pi^{tau j}
 // (FP64: it feeds the conservation law, whose central differences cancel digits)
 template <bool CART, typename S>
-__device__ __forceinline__ void nonadvective_row(const Phys &P, double tau, const Fields<S> &F,
-                                                 idx_t SS, idx_t s, int d, double A[4])
+__device__ __forceinline__ void nonadvective_row(const Phys &P, double tau, const NbCell<S> &N, int d,
+                                                 double A[4])
 {
-    const double Pc = (double)ld(F.p, s) + (P.bulk ? (double)ld(F.qP, (idx_t)(BPI - PTT) * SS + s) : 0.0);
-    const double v = ld(F.u, (idx_t)(d + 1) * SS + s) / ld(F.u, s);
+    const double Pc = N.p + (P.bulk ? N.Pi : 0.0);
     const int ii = d + 1;
+    const double v = N.u[ii] / N.u[0];
     const double gii = ii == 3 ? (CART ? -1.0 : -1.0 / (tau * tau)) : -1.0;
     A[0] = Pc * v;
 #pragma unroll
     for (int n = 1; n < 4; ++n) A[n] = n == ii ? -Pc * gii : 0.0;
     if (P.shear) {
-        auto pi = [&](int c) -> double { return (double)ld(F.qP, (idx_t)(c - PTT) * SS + s); };
-        A[0] += pi(pi_index(ii, 0)) - v * pi(PTT);
+        A[0] += N.pt[ii] - v * N.pt[0];
 #pragma unroll
-        for (int n = 1; n < 4; ++n) A[n] += pi(pi_index(ii, n)) - v * pi(pi_index(0, n));
+        for (int n = 1; n < 4; ++n) A[n] += N.pi[n - 1] - v * N.pt[n];
     }
 }
 
@@ -342,16 +363,26 @@ __device__ __forceinline__ void sources_body(const Phys &P, const Eos &E, double
         {col + (idx_t)wrap(k - 1, P.neta, P.periodic[2]) * plane,
          col + (idx_t)wrap(k + 1, P.neta, P.periodic[2]) * plane}};
     const double dt = P.dtau;
+    // stage 2: q^n, read before the first store (out is the q^n array itself, so
+    // a read placed after a store could not be issued early)
+    double qn4[4];
+    S qn11[NQ - PTT];
+    if (STAGE2) {
+#pragma unroll
+        for (int c = 0; c < PTT; ++c) qn4[c] = ld(qnT, (idx_t)c * SS + s);
+#pragma unroll
+        for (int c = 0; c < NQ - PTT; ++c) qn11[c] = ld(qnP, (idx_t)c * SS + s);
+    }
     // T^{tau mu}: FP64 value, source and accumulation
     auto emitT = [&](int c, double qc, double Jc) {
         const idx_t o = (idx_t)c * SS + s;
         const double t = qc + dt * Jc;
-        st(outT, o, STAGE2 ? ld(qnT, o) + t : t);
+        st(outT, o, STAGE2 ? qn4[c] + t : t);
     };
     auto emitP = [&](int c, R qc, R Jc) {
         const idx_t o = (idx_t)(c - PTT) * SS + s;
         const R t = qc + R(dt) * Jc;
-        st(outP, o, STAGE2 ? R(ld(qnP, o)) + t : t);
+        st(outP, o, STAGE2 ? R(qn11[c - PTT]) + t : t);
     };
     const double invhd[3] = {P.inv_dx, P.inv_dy, P.inv_deta};
     R u[4], C[4][4];
@@ -366,16 +397,16 @@ __device__ __forceinline__ void sources_body(const Phys &P, const Eos &E, double
     double Sc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const idx_t sm = nb[d][0], sp = nb[d][1];
         const double hh = 0.5 * invhd[d];
+        NbCell<S> Np, Nm;
+        Np.load(F, SS, nb[d][1], d);
+        Nm.load(F, SS, nb[d][0], d);
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
-            C[d + 1][m] = R((ld(F.u, (idx_t)m * SS + sp) - ld(F.u, (idx_t)m * SS + sm)) * hh);
-        divv += R((ld(F.u, (idx_t)(d + 1) * SS + sp) / ld(F.u, sp)
-                 - ld(F.u, (idx_t)(d + 1) * SS + sm) / ld(F.u, sm)) * hh);
+        for (int m = 0; m < 4; ++m) C[d + 1][m] = R((Np.u[m] - Nm.u[m]) * hh);
+        divv += R((Np.u[d + 1] / Np.u[0] - Nm.u[d + 1] / Nm.u[0]) * hh);
         double Ap[4], Am[4];
-        nonadvective_row<CART, S>(P, tau, F, SS, sp, d, Ap);
-        nonadvective_row<CART, S>(P, tau, F, SS, sm, d, Am);
+        nonadvective_row<CART, S>(P, tau, Np, d, Ap);
+        nonadvective_row<CART, S>(P, tau, Nm, d, Am);
 #pragma unroll
         for (int n = 0; n < 4; ++n) Sc[n] -= (Ap[n] - Am[n]) * hh;
     }
