@@ -249,18 +249,21 @@ kt_status kt_mlp_adam(kt_ctx *c, const float *grad, float lr, float b1, float b2
 kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
- * every launch of kt_step.  Kernel classes: 0 = KT flux divergence and
+ * the launches of kt_step.  Kernel classes: 0 = KT flux divergence and
  * stage update, 1 = cell recovery and regulator, 2 = inversion of the
- * reconstructed states at every face, 3 = source terms J of a stage.  kt_profile_enable(c, 1) starts
- * recording (events are pooled, created on first use); kt_profile_read
- * synchronises the stream, returns the totals since the last read and
- * resets them. */
+ * reconstructed states at every face, 3 = source terms J of a stage.
+ * kt_profile_enable(c, mask) times the launches of the classes whose bit is
+ * set in mask (KT_PROFILE_ALL: every class; 0 stops; a mask outside 0..15
+ * is KT_E_ARG).  Events are pooled, created on first use; each timed launch
+ * adds two event records to the stream.  kt_profile_read synchronises the
+ * stream, returns the totals since the last read and resets them. */
+#define KT_PROFILE_ALL 15
 typedef struct {
     double ms[4];                  /* summed launch durations per class */
     int64_t launches[4];
 } kt_profile;
 
-kt_status kt_profile_enable(kt_ctx *c, int32_t on);
+kt_status kt_profile_enable(kt_ctx *c, int32_t mask);
 kt_status kt_profile_read(kt_ctx *c, kt_profile *out);
 
 /* ---------------------------------------------------------------------

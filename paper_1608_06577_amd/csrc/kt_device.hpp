@@ -313,16 +313,17 @@ __device__ __forceinline__ double regulate(const Phys &P, double tau, double q[N
 // ---------------------------------------------------------------- minmod --
 // generalized minmod of Sec. 3.1 on undivided differences; sgn(0) = 0.
 // R is the arithmetic type (double, or float for the mixed-precision state).
-template <typename R>
-__device__ __forceinline__ R mm2(R x, R y)
-{
-    return (copysign(R(0.5), x) + copysign(R(0.5), y)) * fmin(fabs(x), fabs(y));
-}
-
+// The nested form minmod(theta a, minmod((a + b)/2, theta b)), a = q0 - qm,
+// b = qp - q0 (with a + b taken as qp - qm), equals
+// s min(theta |a|, |qp - qm|/2, theta |b|) with s = (sgn a + sgn b)/2: when a
+// and b share a sign so does qp - qm, and otherwise both forms give zero.
+// One sign factor and two minima instead of two of each.
 template <typename R>
 __device__ __forceinline__ R slope(R qm, R q0, R qp, R theta)
 {
-    return mm2(theta * (q0 - qm), mm2(R(0.5) * (qp - qm), theta * (qp - q0)));
+    const R a = q0 - qm, b = qp - q0;
+    const R s = copysign(R(0.5), a) + copysign(R(0.5), b);
+    return s * fmin(fmin(fabs(theta * a), fabs(R(0.5) * (qp - qm))), fabs(theta * b));
 }
 
 // ------------------------------------------------- relaxation sources ----

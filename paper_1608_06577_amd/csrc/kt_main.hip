@@ -131,14 +131,14 @@ __device__ __forceinline__ void xcd_block3(unsigned &bx, unsigned &by, unsigned 
     bz = L / (gx * gy);
 }
 
-// floor(t / d) for t < 2^32, d >= 1, through a double product and one correction
+// floor(t / d) for t < 2^32, 1 <= d < 2^30, through a double product and one
+// correction: the product is within 2^-20 of t / d, so q is off by at most
+// one, and t - q d (taken modulo 2^32) lies in (-d, 2d), inside int range.
 __device__ __forceinline__ idx_t udiv(idx_t t, idx_t d, double inv_d)
 {
-    idx_t q = (idx_t)((double)t * inv_d);
-    const long long r = (long long)t - (long long)q * d;
-    if (r < 0) q -= 1;
-    else if (r >= (long long)d) q += 1;
-    return q;
+    const idx_t q = (idx_t)((double)t * inv_d);
+    const int r = (int)(t - q * d);
+    return r < 0 ? q - 1 : (r >= (int)d ? q + 1 : q);
 }
 
 // counters: the wave's total of a small non-negative integer v < 2^nbits,
@@ -1081,7 +1081,7 @@ struct kt_ctx {
     long long step;
     char err[512];
     // profiling: pooled event pairs recorded around launches
-    bool prof;
+    int prof;                  // classes whose launches are timed (bit k: class k)
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_kind;
     size_t ev_used;
@@ -1089,7 +1089,7 @@ struct kt_ctx {
 
 static hipError_t prof_mark(kt_ctx *c, int kind, bool start)
 {
-    if (!c->prof) return hipSuccess;
+    if (!((c->prof >> kind) & 1)) return hipSuccess;
     if (start) {
         if (c->ev_used + 2 > c->ev.size()) {
             for (int k = 0; k < 2; ++k) {
@@ -1794,10 +1794,11 @@ kt_status kt_mlp_adam(kt_ctx *c, const float *grad, float lr, float b1, float b2
     return KT_OK;
 }
 
-kt_status kt_profile_enable(kt_ctx *c, int32_t on)
+kt_status kt_profile_enable(kt_ctx *c, int32_t mask)
 {
     if (!c) return fail(nullptr, KT_E_ARG, "null context");
-    c->prof = on != 0;
+    if (mask < 0 || mask > 15) return fail(c, KT_E_ARG, "profile class mask %d not in 0..15", mask);
+    c->prof = mask;
     return KT_OK;
 }
 

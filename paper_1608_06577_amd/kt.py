@@ -368,8 +368,15 @@ class Solver:
     def mlp_adam(self, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         _check(lib().kt_mlp_adam(self.ctx, _ptr(grad), lr, b1, b2, eps, int(t)), self.ctx)
 
-    def profile(self, on: bool):
-        _check(lib().kt_profile_enable(self.ctx, int(on)), self.ctx)
+    def profile(self, on, classes=None):
+        """Time the launches of kt_step per kernel class: every class when on is
+        true, only the named classes (of PROFILE_CLASSES) when given."""
+        mask = 0
+        if on:
+            names = PROFILE_CLASSES if classes is None else classes
+            for n in names:
+                mask |= 1 << PROFILE_CLASSES.index(n)
+        _check(lib().kt_profile_enable(self.ctx, mask), self.ctx)
 
     def profile_read(self) -> dict:
         """Summed kernel times (ms) and launch counts per class since the last read."""
