@@ -69,24 +69,43 @@ __host__ __device__ __forceinline__ int pi_index(int m, int n)
 // The bracket is found from a single-precision log2; the weight
 // t = ln(e/e_i)/dln comes from ln(1+z), z = e/e_i - 1, |z| < 2 dln, by its
 // series to z^8 (truncation below 1e-18 for dln <= 0.01), so no
-// double-precision logarithm is evaluated.
-__host__ __device__ __forceinline__ void eos_locate(const Eos &E, double e, int &i, double &t)
+// double-precision logarithm is evaluated.  Both nodes of the guessed
+// bracket are read together with 1/e_i (one memory round trip); only when
+// the weight falls outside [0, 1) is the bracket moved by one node and read
+// again.
+struct EosBracket {
+    double a[EOS_W], b[EOS_W];   // nodes i and i+1
+    double t;                    // weight of node i+1
+};
+
+__host__ __device__ __forceinline__ void eos_read(const Eos &E, int i, double a[EOS_W], double b[EOS_W])
+{
+    const double *r = E.tab + EOS_W * i;
+#pragma unroll
+    for (int k = 0; k < EOS_W; ++k) {
+        a[k] = r[k];
+        b[k] = r[EOS_W + k];
+    }
+}
+
+__host__ __device__ __forceinline__ void eos_locate(const Eos &E, double e, EosBracket &B)
 {
     const float lf = log2f((float)e);
     const double x = ((double)lf * 0.6931471805599453 - E.ln_e0) * E.inv_dln;
     if (!(x > -0.5)) {                 // below the table (or not a number)
-        i = 0;
-        t = 0.0;
+        eos_read(E, 0, B.a, B.b);
+        B.t = 0.0;
         return;
     }
     if (x > (double)(E.n - 1) + 0.5) {
-        i = E.n - 2;
-        t = 1.0;
+        eos_read(E, E.n - 2, B.a, B.b);
+        B.t = 1.0;
         return;
     }
-    i = (int)floor(x);
+    int i = (int)floor(x);
     i = i < 0 ? 0 : (i > E.n - 2 ? E.n - 2 : i);
-    const double z = fma(e, E.tab[EOS_W * i + 3], -1.0);
+    eos_read(E, i, B.a, B.b);
+    const double z = fma(e, B.a[3], -1.0);
     // ln(1+z) = z - z^2/2 + z^3/3 - ... - z^8/8
     double l = -1.0 / 8.0;
     l = fma(l, z, 1.0 / 7.0);
@@ -96,12 +115,19 @@ __host__ __device__ __forceinline__ void eos_locate(const Eos &E, double e, int 
     l = fma(l, z, 1.0 / 3.0);
     l = fma(l, z, -1.0 / 2.0);
     l = fma(l, z, 1.0);
-    t = l * z * E.inv_dln;
+    double t = l * z * E.inv_dln;
     if (t < 0.0) {
-        if (i > 0) { i -= 1; t += 1.0; } else t = 0.0;
+        if (i > 0) {
+            t += 1.0;
+            eos_read(E, i - 1, B.a, B.b);
+        } else t = 0.0;
     } else if (t >= 1.0) {
-        if (i < E.n - 2) { i += 1; t -= 1.0; } else t = 1.0;
+        if (i < E.n - 2) {
+            t -= 1.0;
+            eos_read(E, i + 1, B.a, B.b);
+        } else t = 1.0;
     }
+    B.t = t;
 }
 
 // p and c_s^2
@@ -112,12 +138,10 @@ __host__ __device__ __forceinline__ void eos_pc(const Eos &E, double e, double &
         cs2 = 1.0 / 3.0;
         return;
     }
-    int i;
-    double t;
-    eos_locate(E, e, i, t);
-    const double *a = E.tab + EOS_W * i;
-    p = (a[0] + t * (a[EOS_W] - a[0])) * e;
-    cs2 = a[2] + t * (a[EOS_W + 2] - a[2]);
+    EosBracket B;
+    eos_locate(E, e, B);
+    p = (B.a[0] + B.t * (B.b[0] - B.a[0])) * e;
+    cs2 = B.a[2] + B.t * (B.b[2] - B.a[2]);
 }
 
 // p, c_s^2 and T
@@ -130,13 +154,11 @@ __host__ __device__ __forceinline__ void eos_full(const Eos &E, double e, double
         T = e > 0.0 ? sqrt(sqrt(e * E.inv_a)) : 0.0;
         return;
     }
-    int i;
-    double t;
-    eos_locate(E, e, i, t);
-    const double *a = E.tab + EOS_W * i;
-    p = (a[0] + t * (a[EOS_W] - a[0])) * e;
-    cs2 = a[2] + t * (a[EOS_W + 2] - a[2]);
-    T = (a[1] + t * (a[EOS_W + 1] - a[1])) * sqrt(sqrt(e));
+    EosBracket B;
+    eos_locate(E, e, B);
+    p = (B.a[0] + B.t * (B.b[0] - B.a[0])) * e;
+    cs2 = B.a[2] + B.t * (B.b[2] - B.a[2]);
+    T = (B.a[1] + B.t * (B.b[1] - B.a[1])) * sqrt(sqrt(e));
 }
 
 __host__ __device__ __forceinline__ double eos_p(const Eos &E, double e)

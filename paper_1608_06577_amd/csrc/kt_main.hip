@@ -178,6 +178,8 @@ __device__ __forceinline__ R face_H(R qm, R qp, R vm, R vp, R a)
 // index of fidx_x / fidx_y / fidx_e.  (Interleaving the segments block by
 // block shares cells in L2 and halves this kernel's fetches, but measured
 // slower.)
+constexpr int FACE_BLOCK = 256;   // threads per block of the face kernels
+
 struct FaceLaunch {
     unsigned first_block[6];    // first block of each segment
     unsigned nblocks;           // total
@@ -196,7 +198,7 @@ __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, co
 #pragma unroll
     for (int k = 1; k < 6; ++k) seg += b >= L.first_block[k] ? 1 : 0;
     const int d = seg >> 1, side = seg & 1;     // side 0: q^-, side 1: q^+
-    const idx_t t = (idx_t)(b - L.first_block[seg]) * 256 + threadIdx.x;
+    const idx_t t = (idx_t)(b - L.first_block[seg]) * FACE_BLOCK + threadIdx.x;
     const long long nf = d == 0 ? G.nfx : (d == 1 ? G.nfy : G.nfe);
     int it = 0, fl = 0;
     const bool valid = (long long)t < nf;
@@ -263,13 +265,13 @@ __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, co
 }
 
 template <bool CART, typename S>
-__global__ __launch_bounds__(256) void face_speeds_kernel(Phys P, Eos E, FaceGeo G, FaceLaunch L,
+__global__ __launch_bounds__(FACE_BLOCK) void face_speeds_kernel(Phys P, Eos E, FaceGeo G, FaceLaunch L,
                                                           double tau, const double *qT, const S *qP,
                                                           const S *e, S *vf,
                                                           unsigned long long *slots)
 {
     face_speeds_body<CART, S>(P, E, G, L, tau, qT, qP, e, vf, slots, xcd_block(blockIdx.x, gridDim.x),
-                              (long long)blockIdx.x * 4 + (threadIdx.x >> 6));
+                              (long long)blockIdx.x * (FACE_BLOCK / 64) + (threadIdx.x >> 6));
 }
 
 static FaceLaunch face_launch(const FaceGeo &G, int nx, int ny)
@@ -283,7 +285,7 @@ static FaceLaunch face_launch(const FaceGeo &G, int nx, int ny)
     unsigned acc = 0;
     for (int s = 0; s < 6; ++s) {
         L.first_block[s] = acc;
-        acc += (unsigned)((nf[s >> 1] + 255) / 256);
+        acc += (unsigned)((nf[s >> 1] + FACE_BLOCK - 1) / FACE_BLOCK);
     }
     L.nblocks = acc;
     return L;
@@ -770,7 +772,7 @@ __global__ __launch_bounds__(256) void recover_batch(const BRec<S> *__restrict__
 }
 
 template <bool CART, typename S>
-__global__ __launch_bounds__(256) void faces_batch(const BFace<S> *__restrict__ tab,
+__global__ __launch_bounds__(FACE_BLOCK) void faces_batch(const BFace<S> *__restrict__ tab,
                                                    const unsigned short *__restrict__ map,
                                                    const unsigned *__restrict__ first,
                                                    const double *__restrict__ tau_dev)
@@ -781,7 +783,7 @@ __global__ __launch_bounds__(256) void faces_batch(const BFace<S> *__restrict__ 
     const unsigned lb = g - first[ev];
     const double tau = tau_dev[0] + A.P.dtau;
     face_speeds_body<CART, S>(A.P, A.E, A.G, A.L, tau, A.qT, A.qP, A.e, A.vf, A.slots, lb,
-                              (long long)lb * 4 + (threadIdx.x >> 6));
+                              (long long)lb * (FACE_BLOCK / 64) + (threadIdx.x >> 6));
 }
 
 __global__ __launch_bounds__(256) void rotate_batch(const BCopy *__restrict__ tab,
@@ -1154,7 +1156,7 @@ static FaceGeo face_geo(const kt_params *p)
 
 static long long face_waves(const kt_params *p)
 {
-    return (long long)face_launch(face_geo(p), p->nx, p->ny).nblocks * 4;
+    return (long long)face_launch(face_geo(p), p->nx, p->ny).nblocks * (FACE_BLOCK / 64);
 }
 
 static long long stage_waves(const kt_params *p)
@@ -1303,7 +1305,7 @@ static kt_status run_faces_t(kt_ctx *c, double tau, int which)
     hipError_t e = prof_mark(c, 2, true);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
     const FaceLaunch L = face_launch(c->G, c->P.nx, c->P.ny);
-    const dim3 g(L.nblocks), b(256);
+    const dim3 g(L.nblocks), b(FACE_BLOCK);
     const double *qT = c->qT[which];
     const S *qP = (const S *)c->qP[which], *ee = (const S *)c->e;
     e = cart ? launch(face_speeds_kernel<true, S>, g, b, c->stream, c->P, c->E, c->G, L, tau, qT, qP,
@@ -1885,7 +1887,8 @@ static size_t event_blocks(const kt_params *p)
 {
     const size_t sg = (size_t)((p->nx + 63) / 64) * ((p->ny + 3) / 4);
     const size_t ncell = (size_t)p->nx * p->ny * p->neta;
-    return 2 * sg * p->neta + (ncell + 255) / 256 + (size_t)face_waves(p) / 4 + (4 * (size_t)cell_stride(p) + 255) / 256;
+    return 2 * sg * p->neta + (ncell + 255) / 256 + (size_t)face_launch(face_geo(p), p->nx, p->ny).nblocks
+         + (4 * (size_t)cell_stride(p) + 255) / 256;
 }
 
 static size_t event_ws(const kt_params *p, const kt_eos *eos)
@@ -2043,7 +2046,7 @@ static hipError_t batch_step_launches(kt_batch *b, hipStream_t st)
         e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r1),
                    M(b->o_mrec), F(b->o_frec), tau);
     if (e == hipSuccess)
-        e = launch(faces_batch<CART, S>, dim3(b->nb_face), blk, st, (const BFace<S> *)T(b->o_f1),
+        e = launch(faces_batch<CART, S>, dim3(b->nb_face), dim3(FACE_BLOCK), st, (const BFace<S> *)T(b->o_f1),
                    M(b->o_mface), F(b->o_fface), tau);
     if (e == hipSuccess)
         e = launch(sources_batch<CART, true, S>, dim3(b->nb_src), blk2, st,
@@ -2055,7 +2058,7 @@ static hipError_t batch_step_launches(kt_batch *b, hipStream_t st)
         e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r2),
                    M(b->o_mrec), F(b->o_frec), tau);
     if (e == hipSuccess)
-        e = launch(faces_batch<CART, S>, dim3(b->nb_face), blk, st, (const BFace<S> *)T(b->o_f2),
+        e = launch(faces_batch<CART, S>, dim3(b->nb_face), dim3(FACE_BLOCK), st, (const BFace<S> *)T(b->o_f2),
                    M(b->o_mface), F(b->o_fface), tau);
     if (e == hipSuccess)
         e = launch(rotate_batch, dim3(b->nb_rot), blk, st, (const BCopy *)T(b->o_rot), M(b->o_mrot),
