@@ -88,6 +88,22 @@ __host__ __device__ __forceinline__ void eos_read(const Eos &E, int i, double a[
     }
 }
 
+// t = ln(e/e_i)/dln for the bracket B (node i = B.a)
+__host__ __device__ __forceinline__ double eos_weight(const Eos &E, const EosBracket &B, double e)
+{
+    const double z = fma(e, B.a[3], -1.0);
+    // ln(1+z) = z - z^2/2 + z^3/3 - ... - z^8/8
+    double l = -1.0 / 8.0;
+    l = fma(l, z, 1.0 / 7.0);
+    l = fma(l, z, -1.0 / 6.0);
+    l = fma(l, z, 1.0 / 5.0);
+    l = fma(l, z, -1.0 / 4.0);
+    l = fma(l, z, 1.0 / 3.0);
+    l = fma(l, z, -1.0 / 2.0);
+    l = fma(l, z, 1.0);
+    return l * z * E.inv_dln;
+}
+
 __host__ __device__ __forceinline__ void eos_locate(const Eos &E, double e, EosBracket &B)
 {
     const float lf = log2f((float)e);
@@ -105,17 +121,7 @@ __host__ __device__ __forceinline__ void eos_locate(const Eos &E, double e, EosB
     int i = (int)floor(x);
     i = i < 0 ? 0 : (i > E.n - 2 ? E.n - 2 : i);
     eos_read(E, i, B.a, B.b);
-    const double z = fma(e, B.a[3], -1.0);
-    // ln(1+z) = z - z^2/2 + z^3/3 - ... - z^8/8
-    double l = -1.0 / 8.0;
-    l = fma(l, z, 1.0 / 7.0);
-    l = fma(l, z, -1.0 / 6.0);
-    l = fma(l, z, 1.0 / 5.0);
-    l = fma(l, z, -1.0 / 4.0);
-    l = fma(l, z, 1.0 / 3.0);
-    l = fma(l, z, -1.0 / 2.0);
-    l = fma(l, z, 1.0);
-    double t = l * z * E.inv_dln;
+    double t = eos_weight(E, B, e);
     if (t < 0.0) {
         if (i > 0) {
             t += 1.0;
@@ -159,6 +165,28 @@ __host__ __device__ __forceinline__ void eos_full(const Eos &E, double e, double
     p = (B.a[0] + B.t * (B.b[0] - B.a[0])) * e;
     cs2 = B.a[2] + B.t * (B.b[2] - B.a[2]);
     T = (B.a[1] + B.t * (B.b[1] - B.a[1])) * sqrt(sqrt(e));
+}
+
+// p and c_s^2 at e, reusing the bracket B of an earlier evaluation when e
+// lies inside it (successive Newton iterates mostly do), so that no table
+// read is needed; have: B holds a bracket
+__host__ __device__ __forceinline__ void eos_pc_near(const Eos &E, double e, EosBracket &B, bool &have,
+                                                     double &p, double &cs2)
+{
+    if (E.conformal) {
+        p = e * (1.0 / 3.0);
+        cs2 = 1.0 / 3.0;
+        return;
+    }
+    const double t = have ? eos_weight(E, B, e) : -1.0;
+    if (t >= 0.0 && t < 1.0) {
+        B.t = t;
+    } else {
+        eos_locate(E, e, B);
+        have = true;
+    }
+    p = (B.a[0] + B.t * (B.b[0] - B.a[0])) * e;
+    cs2 = B.a[2] + B.t * (B.b[2] - B.a[2]);
 }
 
 __host__ __device__ __forceinline__ double eos_p(const Eos &E, double e)
@@ -219,10 +247,12 @@ __device__ __forceinline__ int invert_core(const Phys &P, const Eos &E, double t
         bool done = false;
         int n = 0;
         double cs2;
+        EosBracket B;
+        bool have = false;
         while (n < P.newton_max) {
             // f = x - E + M^2/A and f' = 1 - M^2 c_s^2 / A^2 with A = E + p(x) + Pi > 0,
             // scaled by A and A^2 so that the step f/f' takes one division
-            eos_pc(E, x, p, cs2);
+            eos_pc_near(E, x, B, have, p, cs2);
             const double A = EE + p + Pi;
             const double fA = fma(x - EE, A, M2);
             const double dfA2 = fma(-M2, cs2, A * A);
@@ -246,7 +276,7 @@ __device__ __forceinline__ int invert_core(const Phys &P, const Eos &E, double t
             }
             flags |= F_FALLBACK;
         }
-        p = eos_p(E, x);
+        eos_pc_near(E, x, B, have, p, cs2);
     }
     e = x;
     p_out = p;

@@ -179,6 +179,8 @@ __device__ __forceinline__ R face_H(R qm, R qp, R vm, R vp, R a)
 // block shares cells in L2 and halves this kernel's fetches, but measured
 // slower.)
 constexpr int FACE_BLOCK = 256;   // threads per block of the face kernels
+// The face kernels are latency-bound (dependent EOS table reads inside each
+// Newton solve): they are held to 64 VGPRs, i.e. 8 waves per SIMD.
 
 struct FaceLaunch {
     unsigned first_block[6];    // first block of each segment
@@ -265,7 +267,7 @@ __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, co
 }
 
 template <bool CART, typename S>
-__global__ __launch_bounds__(FACE_BLOCK) void face_speeds_kernel(Phys P, Eos E, FaceGeo G, FaceLaunch L,
+__global__ __launch_bounds__(FACE_BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void face_speeds_kernel(Phys P, Eos E, FaceGeo G, FaceLaunch L,
                                                           double tau, const double *qT, const S *qP,
                                                           const S *e, S *vf,
                                                           unsigned long long *slots)
@@ -772,7 +774,7 @@ __global__ __launch_bounds__(256) void recover_batch(const BRec<S> *__restrict__
 }
 
 template <bool CART, typename S>
-__global__ __launch_bounds__(FACE_BLOCK) void faces_batch(const BFace<S> *__restrict__ tab,
+__global__ __launch_bounds__(FACE_BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void faces_batch(const BFace<S> *__restrict__ tab,
                                                    const unsigned short *__restrict__ map,
                                                    const unsigned *__restrict__ first,
                                                    const double *__restrict__ tau_dev)
