@@ -38,9 +38,9 @@ KERNEL_VALUES = {"flux": 45.0, "sources": 47.5, "recover": 32.0, "faces": 16.0}
 # HBM bytes per launch of the FP64 kernels on this event, from rocprofv3 FETCH_SIZE x 2.000 and
 # WRITE_SIZE x 1.000 (scale factors of a 256 MiB device copy), profiles/kt_step_hotspot128_fp64.md;
 # valid for the kernel sources whose hash is TRAFFIC_SOURCES (else the traffic is reported as null)
-TRAFFIC_SOURCES = "9105ed76fb7ebc8e"
-TRAFFIC_BYTES = {"faces": 1.0835e9 + 1.079e8, "flux": 0.5 * (1.4083e9 + 1.4064e9) + 2.517e8,
-                 "sources": 0.5 * (9.503e8 + 1.1545e9) + 2.517e8, "recover": 2.705e8 + 3.170e8}
+TRAFFIC_SOURCES = "ed3ec54374d36aeb"
+TRAFFIC_BYTES = {"faces": 1.0862e9 + 1.078e8, "flux": 0.5 * (1.3914e9 + 1.3930e9) + 2.517e8,
+                 "sources": 0.5 * (9.621e8 + 1.2261e9) + 2.517e8, "recover": 2.706e8 + 3.202e8}
 KERNEL_NAMES = {"flux": "flux_kernel (KT flux divergence + stage update)",
                 "sources": "sources_kernel (App. B sources + stage update)",
                 "recover": "recover_kernel (Newton inversion + regulator)",
