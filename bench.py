@@ -37,10 +37,11 @@ STEP_VALUES = 103
 KERNEL_VALUES = {"flux": 45.0, "sources": 47.5, "recover": 32.0, "faces": 16.0}
 # HBM bytes per launch of the FP64 kernels on this event, from rocprofv3 FETCH_SIZE x 2.000 and
 # WRITE_SIZE x 1.000 (scale factors of a 256 MiB device copy), profiles/kt_step_hotspot128_fp64.md;
-# valid for the kernel sources whose hash is TRAFFIC_SOURCES (else the traffic is reported as null)
-TRAFFIC_SOURCES = "ed3ec54374d36aeb"
-TRAFFIC_BYTES = {"faces": 1.0862e9 + 1.078e8, "flux": 0.5 * (1.3914e9 + 1.3930e9) + 2.517e8,
-                 "sources": 0.5 * (9.621e8 + 1.2261e9) + 2.517e8, "recover": 2.706e8 + 3.202e8}
+# valid for the kernel sources and compiler flags whose hash is TRAFFIC_SOURCES (else the traffic
+# is reported as null)
+TRAFFIC_SOURCES = "494aa17f165528d7"
+TRAFFIC_BYTES = {"faces": 1.0863e9 + 1.078e8, "flux": 0.5 * (1.3569e9 + 1.3601e9) + 2.517e8,
+                 "sources": 0.5 * (9.634e8 + 1.2246e9) + 2.517e8, "recover": 2.706e8 + 3.200e8}
 KERNEL_NAMES = {"flux": "flux_kernel (KT flux divergence + stage update)",
                 "sources": "sources_kernel (App. B sources + stage update)",
                 "recover": "recover_kernel (Newton inversion + regulator)",
@@ -62,11 +63,14 @@ def parse():
 
 
 def kernel_sources_hash():
-    """First 16 hex digits of the SHA-256 of the kernel sources, concatenated."""
+    """First 16 hex digits of the SHA-256 of the kernel sources, concatenated, and
+    of the compiler flags they are built with."""
     import hashlib
+    from paper_1608_06577_amd import build
     h = hashlib.sha256()
     for f in ("kt_main.hip", "kt_device.hpp", "kt_mlp.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1608_06577_amd", "csrc", f), "rb").read())
+    h.update(" ".join(build.HIPCC_FLAGS).encode())
     return h.hexdigest()[:16]
 
 

@@ -12,6 +12,10 @@ DEPENDS = SOURCES + [os.path.join(_HERE, "csrc", "kt_device.hpp"),
 LIB = os.path.join(_HERE, "libkt.so")
 
 HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+               # a*b + c is fused where the source writes it, never across statements: the
+               # rounding then does not depend on how a device function is inlined, so the
+               # batched kernels reproduce the single-event kernels bit for bit
+               "-ffp-contract=on",
                # no packed FP32 instructions in any kernel
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
