@@ -96,6 +96,44 @@ def test_recover_matches_oracle(kt):
     assert d.max() <= 1 and np.mean(d == 0) > 0.99
 
 
+def test_recover_whole_table_range(kt):
+    """Cell inversion with the tabulated EOS at energy densities spread
+    log-uniformly from just above the floor to ten times the last table node
+    (the end-node ratios hold beyond it), with flows up to u^tau ~ 30: the
+    Newton iterates cross many table brackets (the lookup reuses the bracket of
+    the previous iterate only while the iterate stays inside it)."""
+    import torch
+    from tests.test_oracle_algebra import pack_pi, random_state
+    tau = 1.3
+    eos = I.eos_c1_table()
+    w = I.workload_hotspot(nx=4, ny=4, neta=4)
+    cfg = dict(w.config)
+    phys = oracle.Physics.from_config(w.grid, cfg)
+    n = 4000
+    e0, u, pi, Pi = random_state(tau, n, u_scale=6.0)     # pi ~ 0.1 e0, Pi ~ 0.05 e0
+    ln_lo = np.log(2.0 * cfg["e_floor"])
+    e_last = np.exp(eos.ln_e0 + eos.dln_e * (len(eos.p) - 1))
+    e = np.exp(np.random.default_rng(5).uniform(ln_lo, np.log(10.0 * e_last), n))
+    r = e / e0
+    q = oracle.tmunu(phys, eos, tau, e, u, pack_pi(pi * r[:, None, None]), Pi * r)
+    eo, uo, ito, flo = oracle.recover(phys, eos, tau, q)
+    gpu = kt.Solver(w.grid, cfg, eos, w.prims)
+    ins = [torch.tensor(q[:, k], device="cuda") for k in (0, 1, 2, 3, 4, 5, 6, 7, 14)]
+    eg, ug, itg, flg = gpu.recover(ins, tau)
+    eg, ug = eg.cpu().numpy(), ug.cpu().numpy().T
+    assert np.array_equal(flg.cpu().numpy(), flo)
+    # e = E - M^2/(E + P) loses digits as v -> 1: a last-bit difference of the
+    # two sides' p(e) (polynomial logarithm here, libm's in the oracle) grows
+    # like (u^tau)^2, so the bar scales with it
+    g2 = np.maximum(uo[:, 0] ** 2, 1.0)
+    de = np.abs(eg - eo) / eo / g2
+    du = np.max(np.abs(ug - uo) / uo[:, :1], axis=1) / g2
+    print("whole-table inversion: max |de|/e/(u^tau)^2 %.2e, max |du|/u^tau/(u^tau)^2 %.2e, max u^tau %.1f"
+          % (de.max(), du.max(), uo[:, 0].max()), flush=True)
+    assert de.max() < 1e-14 and du.max() < 1e-13
+    assert e.max() > e_last and np.mean(e > e_last) > 0.05     # beyond the last node
+
+
 def test_init_matches_oracle(kt):
     w = I.workload_hotspot(nx=20, ny=17, neta=6, dx=0.8, deta=0.8)
     errs, gpu, sim, f, r = run_pair(kt, w, 0)
