@@ -280,9 +280,10 @@ kt_status kt_profile_read(kt_ctx *c, kt_profile *out);
  * n_events entries; kt_batch_init synchronises the stream.
  * kt_batch_step enqueues n_steps steps (asynchronous; the graph runs on a
  * stream of the batch ordered after and before the caller's stream).
- * kt_batch_tune times the flux kernel of every distinct grid shape with 1,
+ * kt_batch_tune times the batched flux launch, all events together, with 1,
  * 2, 4 and 8 eta planes per block on the live state (which it does not
- * change), keeps the fastest (kc_out[n_events], nullable) and synchronises.
+ * change), keeps the fastest for every event (kc_out[n_events], nullable)
+ * and synchronises.
  * kt_batch_observables is kt_observables of one event.
  * --------------------------------------------------------------------- */
 typedef struct kt_batch kt_batch;

@@ -2069,6 +2069,27 @@ static hipError_t batch_step_launches(kt_batch *b, hipStream_t st)
     return e;
 }
 
+// stage 1 of the batch without its recovery: the sources and flux launches
+// (timed by kt_batch_tune; they only write q*, which every step rewrites)
+template <bool CART, typename S>
+static hipError_t batch_stage1_t(kt_batch *b, hipStream_t st)
+{
+    const BStage<S> *tab = (const BStage<S> *)(const void *)(b->tab + b->o_s1);
+    hipError_t e = launch(sources_batch<CART, false, S>, dim3(b->nb_src), dim3(64, 4), st, tab,
+                          (const unsigned short *)(b->tab + b->o_msrc), (const unsigned *)(b->tab + b->o_fsrc),
+                          (const double *)b->tau_dev);
+    if (e == hipSuccess)
+        e = launch(flux_batch<false, S>, dim3(b->nb_flux), dim3(64, 4), st, tab,
+                   (const unsigned short *)(b->tab + b->o_mflux), (const unsigned *)(b->tab + b->o_fflux));
+    return e;
+}
+
+static hipError_t batch_stage1(kt_batch *b, hipStream_t st)
+{
+    if (b->mixed) return b->cart ? batch_stage1_t<true, float>(b, st) : batch_stage1_t<false, float>(b, st);
+    return b->cart ? batch_stage1_t<true, double>(b, st) : batch_stage1_t<false, double>(b, st);
+}
+
 static hipError_t batch_launches(kt_batch *b, hipStream_t st)
 {
     if (b->mixed)
@@ -2229,47 +2250,38 @@ kt_status kt_batch_tune(kt_batch *b, int32_t *kc_out)
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     if (e != hipSuccess) return bfail(b, KT_E_HIP, "tune events: %s", hipGetErrorString(e));
-    for (int ev = 0; ev < b->n && e == hipSuccess; ++ev) {
-        kt_ctx *c = b->ev[ev];
-        int same = -1;   // an earlier event of the same shape
-        for (int k = 0; k < ev; ++k)
-            if (b->ev[k]->P.nx == c->P.nx && b->ev[k]->P.ny == c->P.ny && b->ev[k]->P.neta == c->P.neta) same = k;
-        if (same >= 0) {
-            b->kc[ev] = b->kc[same];
-            continue;
+    // The batched stage 1 (sources, then flux: the flux kernel finds the caches as
+    // it does in a step) is timed as a whole for each candidate, the same number
+    // of eta planes per block for every event: the launch shares the chip among
+    // all events, so timing each grid shape alone would choose for a different
+    // load.  Both launches only write q*, which the next step's sources kernel
+    // overwrites, so timing them on the live state changes no result.
+    float best = 1e30f;
+    int best_kc = KC;
+    kt_status st = KT_OK;
+    for (int ci = 0; ci < 4 && e == hipSuccess && st == KT_OK; ++ci) {
+        b->kc.assign(b->n, cand[ci]);
+        st = batch_build_tables(b);
+        float tot = 0.0f;
+        for (int r = 0; r < 4 && e == hipSuccess && st == KT_OK; ++r) {
+            e = hipEventRecord(t0, b->user);
+            if (e == hipSuccess) e = batch_stage1(b, b->user);
+            if (e == hipSuccess) e = hipEventRecord(t1, b->user);
+            if (e == hipSuccess) e = hipEventSynchronize(t1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+            if (r > 0) tot += ms;   // the first launch warms caches
         }
-        // the flux of stage 1 accumulates into q*, which the next step's sources kernel
-        // overwrites, so timing it on the live state changes no result
-        float best = 1e30f;
-        for (int ci = 0; ci < 4 && e == hipSuccess; ++ci) {
-            const int kc = cand[ci];
-            const dim3 g((c->P.nx + 63) / 64, (c->P.ny + 3) / 4, (c->P.neta + kc - 1) / kc), blk(64, 4);
-            float tot = 0.0f;
-            for (int r = 0; r < 4 && e == hipSuccess; ++r) {
-                e = hipEventRecord(t0, b->user);
-                if (e == hipSuccess) {
-                    if (b->mixed)
-                        e = launch(flux_kernel<false, float>, g, blk, b->user, c->P, c->G, (const double *)c->qT[0],
-                                   (const float *)c->qP[0], (const float *)c->vf, c->qT[1], (float *)c->qP[1], kc);
-                    else
-                        e = launch(flux_kernel<false, double>, g, blk, b->user, c->P, c->G, (const double *)c->qT[0],
-                                   (const double *)c->qP[0], (const double *)c->vf, c->qT[1], (double *)c->qP[1], kc);
-                }
-                if (e == hipSuccess) e = hipEventRecord(t1, b->user);
-                if (e == hipSuccess) e = hipEventSynchronize(t1);
-                float ms = 0.0f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-                if (r > 0) tot += ms;   // the first launch warms caches
-            }
-            if (e == hipSuccess && tot < best) {
-                best = tot;
-                b->kc[ev] = kc;
-            }
+        if (e == hipSuccess && st == KT_OK && tot < best) {
+            best = tot;
+            best_kc = cand[ci];
         }
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
+    if (st != KT_OK) return st;
     if (e != hipSuccess) return bfail(b, KT_E_HIP, "tune: %s", hipGetErrorString(e));
+    b->kc.assign(b->n, best_kc);
     if (kc_out)
         for (int ev = 0; ev < b->n; ++ev) kc_out[ev] = b->kc[ev];
     return batch_build_tables(b);

@@ -65,7 +65,7 @@ def test_batch_tuning_keeps_results(kt):
     batch.step(2)
     kc = batch.tune()
     print("autotuned eta planes per flux block:", kc, flush=True)
-    assert all(k in (1, 2, 4, 8) for k in kc)
+    assert all(k in (1, 2, 4, 8) for k in kc) and len(set(kc)) == 1
     batch.step(5)
     for s in singles:
         s.step(7)
