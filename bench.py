@@ -51,14 +51,16 @@ KERNEL_NAMES = {"flux": "flux_kernel (KT flux divergence + stage update)",
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (for counter scaling)")
     ap.add_argument("--n", type=int, default=128, help="grid cells per axis")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-events leg")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-start leg")
+    ap.add_argument("--learn-steps", type=int, default=3000, help="Adam steps of the start network")
     return ap.parse_args()
 
 
@@ -103,6 +105,67 @@ def cpu_baseline(w, budget_s):
             "sample": "%d Heun step(s) of the same %dx%dx%d event from its initial state "
                       "(%.1f s, plus %.1f s initial recovery)" % (steps, w.grid.nx, w.grid.ny,
                                                                   w.grid.neta, dt, t_init)}
+
+
+def learned_leg(args, kt, I, torch):
+    """Learned inversion start on a 200 x 200 x 96 hot-spot event in mixed
+    precision (FP32 state): the start network is trained on the event's own
+    states by the library's kernels, then the same steps are timed from the
+    same initial state with the plain warm start, the conformal start and the
+    learned start.  Every start is polished by the same Newton iteration to the
+    same tolerance, so the fields agree to rounding."""
+    from paper_1608_06577_amd import learned
+    w = I.workload_hotspot(nx=200, ny=200, neta=96, seed=11)
+    cfg = dict(w.config)
+    cfg["mixed"] = True
+    ncell = w.grid.ncells
+    print("bench: learned start, %s, mixed precision: training" % "x".join(map(str, w.grid.shape[::-1])),
+          file=sys.stderr, flush=True)
+    t0 = time.time()
+    trainer = kt.Solver(w.grid, cfg, w.eos, w.prims, device="cuda:0")
+    trainer.mlp_set(torch.tensor(I.mlp_init_params(0), device="cuda:0"))
+    X, T = learned.collect_pairs(trainer, cfg["e_floor"], n_snap=6, steps_between=10, max_pairs=2_000_000)
+    n_pairs = X.shape[1]
+    losses = learned.train(trainer, X, T, steps=args.learn_steps)
+    params = trainer.mlp_get()
+    trainer.close()
+    del X, T
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out, fields = {}, {}
+    for mode, code in (("plain_warm", kt.KT_START_WARM), ("conformal", kt.KT_START_CONFORMAL),
+                       ("learned", kt.KT_START_LEARNED)):
+        s = kt.Solver(w.grid, cfg, w.eos, w.prims, device="cuda:0")
+        if code == kt.KT_START_LEARNED:
+            s.mlp_set(params)
+        s.set_inv_start(code)
+        s.step(args.warmup)
+        o0 = s.observables()
+        torch.cuda.synchronize()
+        start.record()
+        s.step(args.steps)
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / args.steps
+        o1 = s.observables()
+        iters = (o1["newton_iters_cells"] - o0["newton_iters_cells"]) / max(1, o1["n_recover_cells"] - o0["n_recover_cells"])
+        fields[mode] = s.fields(("e",))["e"].double()
+        out[mode] = {"ms_per_step": ms, "value": ncell / (ms * 1e-3), "newton_iters_per_cell": iters,
+                     "n_fallback": o1["n_fallback"]}
+        s.close()
+        print("bench: learned-start leg, %s start: %.3f ms/step, %.3f Newton iterations per cell"
+              % (mode, ms, iters), file=sys.stderr, flush=True)
+    ref = fields["plain_warm"]
+    dense = ref > 1e-3 * ref.max()
+    for mode in ("conformal", "learned"):
+        d = (fields[mode] - ref).abs() / ref
+        out[mode]["max_rel_diff_e_vs_plain_dense_cells"] = d[dense].max().item()
+    out.update({"workload": "hotspot_viscous_200x200x96", "state": "mixed precision",
+                "training": {"pairs": int(n_pairs), "adam_steps": args.learn_steps,
+                             "loss_first_last": [losses[0], losses[-1]], "seconds": t_train},
+                "network": "11-64-64-4 GELU, FP32; start = y_0 * conformal root; Newton polish to 1e-12"})
+    return out
 
 
 def main():
@@ -167,7 +230,7 @@ def main():
                    "dx_fm": w.grid.dx, "deta": w.grid.deta, "tau0": w.tau0,
                    "dtau": w.config["dtau"], "eta_over_s": w.config["eta_s"],
                    "zeta_over_s": "0.1 (1/3 - c_s^2)", "eos": "tabulated, 4096 nodes",
-                   "precision": "fp64", "inversion_start": "conformal closed form",
+                   "precision": "fp64", "inversion_start": "previous e of the cell (warm start)",
                    "step_hbm_frac": STEP_VALUES * 8.0 * value / (HBM_PEAK_GBS * 1e9),
                    "paper_context_ms_per_step": {"gtx980ti_fp32_128cube_table": 244.45,
                                                  "gtx980ti_program_summary": 38400.0}},
@@ -216,6 +279,8 @@ def main():
         batch.close()
         print("bench: batch of 48 events %.3f ms/step (%.3g cell-updates/s)" % (ms_b, ncb / (ms_b * 1e-3)),
               file=sys.stderr, flush=True)
+    if not args.no_learned:
+        rec["variants"]["learned_start"] = learned_leg(args, kt, I, torch)
     if not args.no_cpu:
         print("bench: CPU oracle baseline (bounded sample)", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

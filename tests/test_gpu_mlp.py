@@ -120,43 +120,6 @@ def test_loss_and_adam_match_oracle(kt):
     assert np.max(np.abs(got - th)) < 2e-6
 
 
-LOSS_W = (1.0, 0.05, 0.05, 0.05)   # the start uses y_0 only; the velocity is a diagnostic
-
-
-def train_on_solver_states(kt, gpu, w, n_snap, steps, batch=8192, lr=2e-3, seed=0):
-    """Training pairs from the solver's own states: snapshots of q (floor cells
-    left out) and their inversion by the library (q is regulated after the
-    step's recovery, so the pairs come from a fresh inversion of q)."""
-    import torch
-    xs, ts = [], []
-    for s in range(n_snap):
-        f = gpu.fields(("q",))
-        q = f["q"].reshape(15, -1)
-        keep = q[0] > 10 * w.config["e_floor"]
-        ins = [q[k][keep].contiguous() for k in (0, 1, 2, 3, 4, 5, 6, 7, 14)]
-        tau = gpu.observables()["tau"]
-        e, u, _, _ = gpu.recover(ins, tau, with_iters=False)
-        x, t = gpu.mlp_features(ins, tau, e, u)
-        xs.append(x)
-        ts.append(t)
-        gpu.step(10)
-    X, T = torch.cat(xs, 1), torch.cat(ts, 1)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
-    losses = []
-    for it in range(1, steps + 1):
-        idx = torch.randint(0, X.shape[1], (batch,), device="cuda", generator=gen)
-        xb, tb = X[:, idx].contiguous(), T[:, idx].contiguous()
-        y, act = gpu.mlp_fwd(xb, keep_act=True)
-        L, dy = gpu.mlp_loss(y, tb, LOSS_W)
-        g = gpu.mlp_bwd(xb, act, dy)
-        # cosine decay of the step size to a tenth
-        gpu.mlp_adam(g, it, lr=lr * (0.55 + 0.45 * np.cos(np.pi * it / steps)))
-        if it % 100 == 0 or it == 1:
-            losses.append(L.item())
-    return losses
-
-
 def test_learned_start_against_conformal_start(kt):
     """Train on a hot-spot event's own states, then invert held-out states of
     a different event.  The inversion results equal the oracle's whatever the
@@ -169,7 +132,9 @@ def test_learned_start_against_conformal_start(kt):
     w = I.workload_hotspot(nx=40, ny=40, neta=16, dx=0.4, deta=0.5, n_hot=40, seed=5)
     gpu = kt.Solver(w.grid, w.config, w.eos, w.prims)
     gpu.mlp_set(dev(I.mlp_init_params(0)))
-    losses = train_on_solver_states(kt, gpu, w, n_snap=6, steps=3000)
+    from paper_1608_06577_amd import learned
+    X, T = learned.collect_pairs(gpu, w.config["e_floor"], n_snap=6, steps_between=10)
+    losses = learned.train(gpu, X, T, steps=3000)
     print("training loss:", ["%.2e" % l for l in losses], flush=True)
     assert losses[-1] < 0.01 * losses[0]
     # held-out states: another event, later time
