@@ -724,11 +724,6 @@ struct BFace {              // one event of a face-speed launch
     unsigned long long *slots;
 };
 
-struct BCopy {              // u^{n-1} <- u^n, u^n <- u^{n+1} of one event (4 * stride elements)
-    double *up, *u, *un;
-    long long n;
-};
-
 template <bool CART, bool STAGE2, typename S>
 __global__ __launch_bounds__(256) void sources_batch(const BStage<S> *__restrict__ tab,
                                                      const unsigned short *__restrict__ map,
@@ -786,20 +781,6 @@ __global__ __launch_bounds__(FACE_BLOCK) __attribute__((amdgpu_waves_per_eu(8)))
     const double tau = tau_dev[0] + A.P.dtau;
     face_speeds_body<CART, S>(A.P, A.E, A.G, A.L, tau, A.qT, A.qP, A.e, A.vf, A.slots, lb,
                               (long long)lb * (FACE_BLOCK / 64) + (threadIdx.x >> 6));
-}
-
-__global__ __launch_bounds__(256) void rotate_batch(const BCopy *__restrict__ tab,
-                                                    const unsigned short *__restrict__ map,
-                                                    const unsigned *__restrict__ first)
-{
-    const unsigned g = blockIdx.x;
-    const int ev = map[g];
-    const BCopy &A = tab[ev];
-    const long long i = (long long)(g - first[ev]) * 256 + threadIdx.x;
-    if (i < A.n) {
-        A.up[i] = A.u[i];
-        A.u[i] = A.un[i];
-    }
 }
 
 // tau^{n+1} = tau^n + dtau, one thread (part of the captured step)
@@ -1849,12 +1830,12 @@ struct kt_batch {
     char *tab;                   // device tables (see batch_tables)
     size_t tab_bytes;
     std::vector<int> kc;         // eta planes per flux block, per event
-    unsigned nb_src, nb_flux, nb_rec, nb_face, nb_rot;
-    size_t o_s1, o_s2, o_r1, o_r2, o_f1, o_f2, o_rot;             // table offsets
-    size_t o_fsrc, o_fflux, o_frec, o_fface, o_frot;              // first-block arrays
-    size_t o_msrc, o_mflux, o_mrec, o_mface, o_mrot;              // block -> event maps
-    hipGraph_t graph;
-    hipGraphExec_t exec;
+    unsigned nb_src, nb_flux, nb_rec, nb_face;
+    size_t o_s1[2], o_s2[2], o_r1[2], o_r2[2], o_f1, o_f2;  // table offsets ([step parity])
+    size_t o_fsrc, o_fflux, o_frec, o_fface;                // first-block arrays
+    size_t o_msrc, o_mflux, o_mrec, o_mface;                // block -> event maps
+    hipGraph_t graph[2];         // one captured step per step parity
+    hipGraphExec_t exec[2];
     bool have_graph;
     double tau;
     long long step;
@@ -1876,11 +1857,10 @@ static kt_status bfail(kt_batch *b, kt_status s, const char *fmt, ...)
 static size_t batch_table_bytes(int n)
 {
     size_t t = 0;
-    t += 2 * round_up(sizeof(BStage<double>) * n, 256);
-    t += 2 * round_up(sizeof(BRec<double>) * n, 256);
+    t += 4 * round_up(sizeof(BStage<double>) * n, 256);
+    t += 4 * round_up(sizeof(BRec<double>) * n, 256);
     t += 2 * round_up(sizeof(BFace<double>) * n, 256);
-    t += round_up(sizeof(BCopy) * n, 256);
-    t += 5 * round_up(sizeof(unsigned) * (n + 1), 256);
+    t += 4 * round_up(sizeof(unsigned) * (n + 1), 256);
     return t;
 }
 
@@ -1889,8 +1869,7 @@ static size_t event_blocks(const kt_params *p)
 {
     const size_t sg = (size_t)((p->nx + 63) / 64) * ((p->ny + 3) / 4);
     const size_t ncell = (size_t)p->nx * p->ny * p->neta;
-    return 2 * sg * p->neta + (ncell + 255) / 256 + (size_t)face_launch(face_geo(p), p->nx, p->ny).nblocks
-         + (4 * (size_t)cell_stride(p) + 255) / 256;
+    return 2 * sg * p->neta + (ncell + 255) / 256 + (size_t)face_launch(face_geo(p), p->nx, p->ny).nblocks;
 }
 
 static size_t event_ws(const kt_params *p, const kt_eos *eos)
@@ -1901,58 +1880,70 @@ static size_t event_ws(const kt_params *p, const kt_eos *eos)
 // the batch's table region: argument tables plus the block -> event maps of nb blocks
 static size_t batch_tab_region(int n, size_t nb)
 {
-    return round_up(batch_table_bytes(n), 256) + round_up(nb * sizeof(unsigned short), 256) + 5 * 256;
+    return round_up(batch_table_bytes(n), 256) + round_up(nb * sizeof(unsigned short), 256) + 4 * 256;
 }
 
-// Build the per-event argument tables of one step and upload them (the
+// Build the per-event argument tables of a step and upload them (the
 // caller's stream, synchronised).  Buffers of every event: q (index 0) and
-// q* (1); u[0] = u^n, u[1] = u^{n-1}, u[2] = u* and then u^{n+1}, which the
-// rotation copies into u[0] after moving u[0] into u[1].
+// q* (1); u[2] = u*; at even steps u[0] = u^n and u[1] = u^{n-1}, at odd
+// steps the reverse: u^{n+1} is written over u^{n-1}, so the two buffers swap
+// roles every step and a table set (and a captured graph) exists for each
+// step parity; no u is copied.
 template <typename S>
 static kt_status batch_tables(kt_batch *b)
 {
     const int n = b->n;
-    std::vector<BStage<S>> s1(n), s2(n);
-    std::vector<BRec<S>> r1(n), r2(n);
+    std::vector<BStage<S>> s1[2], s2[2];
+    std::vector<BRec<S>> r1[2], r2[2];
     std::vector<BFace<S>> f1(n), f2(n);
-    std::vector<BCopy> rot(n);
-    std::vector<unsigned> fs(n + 1), ff(n + 1), fr(n + 1), fc(n + 1), fo(n + 1);
-    fs[0] = ff[0] = fr[0] = fc[0] = fo[0] = 0;
+    for (int par = 0; par < 2; ++par) {
+        s1[par].resize(n);
+        s2[par].resize(n);
+        r1[par].resize(n);
+        r2[par].resize(n);
+    }
+    std::vector<unsigned> fs(n + 1), ff(n + 1), fr(n + 1), fc(n + 1);
+    fs[0] = ff[0] = fr[0] = fc[0] = 0;
     for (int e = 0; e < n; ++e) {
         kt_ctx *c = b->ev[e];
         const Phys &P = c->P;
-        const long long S4 = 4 * P.stride;
         auto uu = [&](int k) { return (double *)c->u[k]; };
-        for (int st = 0; st < 2; ++st) {
-            BStage<S> &A = st == 0 ? s1[e] : s2[e];
-            const int src = st;
-            A.P = P;
-            A.E = c->E;
-            A.G = c->G;
-            A.F = Fields<S>{c->qT[src], (const S *)c->qP[src], (const S *)c->e, (const S *)c->p,
-                            (const double *)uu(st == 0 ? 0 : 2), (const double *)uu(st == 0 ? 1 : 0),
-                            (const S *)c->vf};
-            A.qnT = st == 1 ? c->qT[0] : nullptr;
-            A.qnP = st == 1 ? (const S *)c->qP[0] : nullptr;
-            A.outT = c->qT[1 - src];
-            A.outP = (S *)c->qP[1 - src];
-            A.sgx = (P.nx + 63) / 64;
-            A.sgy = (P.ny + 3) / 4;
-            A.fgx = A.sgx;
-            A.fgy = A.sgy;
-            A.kc = b->kc[e];
+        for (int par = 0; par < 2; ++par) {
+            // u buffers at this step parity: u^n in cur, u^{n-1} in prev, u* in 2;
+            // u^{n+1} goes to prev, which makes the roles swap for the next step
+            const int cur = par, prev = 1 - par;
+            for (int st = 0; st < 2; ++st) {
+                BStage<S> &A = st == 0 ? s1[par][e] : s2[par][e];
+                const int src = st;
+                A.P = P;
+                A.E = c->E;
+                A.G = c->G;
+                A.F = Fields<S>{c->qT[src], (const S *)c->qP[src], (const S *)c->e, (const S *)c->p,
+                                (const double *)uu(st == 0 ? cur : 2), (const double *)uu(st == 0 ? prev : cur),
+                                (const S *)c->vf};
+                A.qnT = st == 1 ? c->qT[0] : nullptr;
+                A.qnP = st == 1 ? (const S *)c->qP[0] : nullptr;
+                A.outT = c->qT[1 - src];
+                A.outP = (S *)c->qP[1 - src];
+                A.sgx = (P.nx + 63) / 64;
+                A.sgy = (P.ny + 3) / 4;
+                A.fgx = A.sgx;
+                A.fgy = A.sgy;
+                A.kc = b->kc[e];
+                BRec<S> &R = st == 0 ? r1[par][e] : r2[par][e];
+                const int which = st == 0 ? 1 : 0;   // recover q* after stage 1, q after stage 2
+                R.P = P;
+                R.E = c->E;
+                R.qT = c->qT[which];
+                R.qP = (S *)c->qP[which];
+                R.e = (S *)c->e;
+                R.p = (S *)c->p;
+                R.u = uu(st == 0 ? 2 : prev);
+                R.slots = c->slots;
+            }
         }
         for (int st = 0; st < 2; ++st) {
-            BRec<S> &R = st == 0 ? r1[e] : r2[e];
-            const int which = st == 0 ? 1 : 0;   // recover q* after stage 1, q after stage 2
-            R.P = P;
-            R.E = c->E;
-            R.qT = c->qT[which];
-            R.qP = (S *)c->qP[which];
-            R.e = (S *)c->e;
-            R.p = (S *)c->p;
-            R.u = uu(2);
-            R.slots = c->slots;
+            const int which = st == 0 ? 1 : 0;   // faces of q* after stage 1, of q after stage 2
             BFace<S> &F = st == 0 ? f1[e] : f2[e];
             F.P = P;
             F.E = c->E;
@@ -1964,74 +1955,70 @@ static kt_status batch_tables(kt_batch *b)
             F.vf = (S *)c->vf;
             F.slots = c->slots;
         }
-        rot[e] = BCopy{uu(1), uu(0), uu(2), S4};
-        const unsigned sg = s1[e].sgx * s1[e].sgy;
+        const unsigned sg = s1[0][e].sgx * s1[0][e].sgy;
         fs[e + 1] = fs[e] + sg * (unsigned)P.neta;
         ff[e + 1] = ff[e] + sg * (unsigned)((P.neta + b->kc[e] - 1) / b->kc[e]);
         fr[e + 1] = fr[e] + (unsigned)((P.ncell + 255) / 256);
         fc[e + 1] = fc[e] + f1[e].L.nblocks;
-        fo[e + 1] = fo[e] + (unsigned)((S4 + 255) / 256);
     }
     b->nb_src = fs[n];
     b->nb_flux = ff[n];
     b->nb_rec = fr[n];
     b->nb_face = fc[n];
-    b->nb_rot = fo[n];
     auto mk = [&](const std::vector<unsigned> &f) {
         std::vector<unsigned short> m(f[n]);
         for (int e = 0; e < n; ++e)
             for (unsigned g = f[e]; g < f[e + 1]; ++g) m[g] = (unsigned short)e;
         return m;
     };
-    const std::vector<unsigned short> ms = mk(fs), mf = mk(ff), mr = mk(fr), mc = mk(fc), mo = mk(fo);
+    const std::vector<unsigned short> ms = mk(fs), mf = mk(ff), mr = mk(fr), mc = mk(fc);
     size_t off = 0;
     auto place = [&](size_t bytes) { const size_t o = off; off += round_up(bytes, 256); return o; };
-    b->o_s1 = place(sizeof(BStage<S>) * n);
-    b->o_s2 = place(sizeof(BStage<S>) * n);
-    b->o_r1 = place(sizeof(BRec<S>) * n);
-    b->o_r2 = place(sizeof(BRec<S>) * n);
+    for (int par = 0; par < 2; ++par) {
+        b->o_s1[par] = place(sizeof(BStage<S>) * n);
+        b->o_s2[par] = place(sizeof(BStage<S>) * n);
+        b->o_r1[par] = place(sizeof(BRec<S>) * n);
+        b->o_r2[par] = place(sizeof(BRec<S>) * n);
+    }
     b->o_f1 = place(sizeof(BFace<S>) * n);
     b->o_f2 = place(sizeof(BFace<S>) * n);
-    b->o_rot = place(sizeof(BCopy) * n);
     b->o_fsrc = place(sizeof(unsigned) * (n + 1));
     b->o_fflux = place(sizeof(unsigned) * (n + 1));
     b->o_frec = place(sizeof(unsigned) * (n + 1));
     b->o_fface = place(sizeof(unsigned) * (n + 1));
-    b->o_frot = place(sizeof(unsigned) * (n + 1));
     b->o_msrc = place(sizeof(unsigned short) * ms.size());
     b->o_mflux = place(sizeof(unsigned short) * mf.size());
     b->o_mrec = place(sizeof(unsigned short) * mr.size());
     b->o_mface = place(sizeof(unsigned short) * mc.size());
-    b->o_mrot = place(sizeof(unsigned short) * mo.size());
     if (off > b->tab_bytes) return bfail(b, KT_E_ALLOC, "batch tables need %zu bytes", off);
     std::vector<char> h(off, 0);
     auto put = [&](size_t o, const void *src, size_t bytes) { memcpy(h.data() + o, src, bytes); };
-    put(b->o_s1, s1.data(), sizeof(BStage<S>) * n);
-    put(b->o_s2, s2.data(), sizeof(BStage<S>) * n);
-    put(b->o_r1, r1.data(), sizeof(BRec<S>) * n);
-    put(b->o_r2, r2.data(), sizeof(BRec<S>) * n);
+    for (int par = 0; par < 2; ++par) {
+        put(b->o_s1[par], s1[par].data(), sizeof(BStage<S>) * n);
+        put(b->o_s2[par], s2[par].data(), sizeof(BStage<S>) * n);
+        put(b->o_r1[par], r1[par].data(), sizeof(BRec<S>) * n);
+        put(b->o_r2[par], r2[par].data(), sizeof(BRec<S>) * n);
+    }
     put(b->o_f1, f1.data(), sizeof(BFace<S>) * n);
     put(b->o_f2, f2.data(), sizeof(BFace<S>) * n);
-    put(b->o_rot, rot.data(), sizeof(BCopy) * n);
     put(b->o_fsrc, fs.data(), sizeof(unsigned) * (n + 1));
     put(b->o_fflux, ff.data(), sizeof(unsigned) * (n + 1));
     put(b->o_frec, fr.data(), sizeof(unsigned) * (n + 1));
     put(b->o_fface, fc.data(), sizeof(unsigned) * (n + 1));
-    put(b->o_frot, fo.data(), sizeof(unsigned) * (n + 1));
     put(b->o_msrc, ms.data(), sizeof(unsigned short) * ms.size());
     put(b->o_mflux, mf.data(), sizeof(unsigned short) * mf.size());
     put(b->o_mrec, mr.data(), sizeof(unsigned short) * mr.size());
     put(b->o_mface, mc.data(), sizeof(unsigned short) * mc.size());
-    put(b->o_mrot, mo.data(), sizeof(unsigned short) * mo.size());
     hipError_t e = hipMemcpyAsync(b->tab, h.data(), off, hipMemcpyHostToDevice, b->user);
     if (e == hipSuccess) e = hipStreamSynchronize(b->user);
     if (e != hipSuccess) return bfail(b, KT_E_HIP, "batch tables: %s", hipGetErrorString(e));
     return KT_OK;
 }
 
-// enqueue one Heun step of every event on stream st (captured into the graph)
+// enqueue one Heun step of every event on stream st (captured into the graph
+// of step parity par)
 template <bool CART, typename S>
-static hipError_t batch_step_launches(kt_batch *b, hipStream_t st)
+static hipError_t batch_step_launches(kt_batch *b, hipStream_t st, int par)
 {
     const int n = b->n;
     auto T = [&](size_t o) { return (const void *)(b->tab + o); };
@@ -2040,31 +2027,28 @@ static hipError_t batch_step_launches(kt_batch *b, hipStream_t st)
     const dim3 blk2(64, 4), blk(256);
     auto M = [&](size_t o) { return (const unsigned short *)(b->tab + o); };
     hipError_t e = launch(sources_batch<CART, false, S>, dim3(b->nb_src), blk2, st,
-                          (const BStage<S> *)T(b->o_s1), M(b->o_msrc), F(b->o_fsrc), tau);
+                          (const BStage<S> *)T(b->o_s1[par]), M(b->o_msrc), F(b->o_fsrc), tau);
     if (e == hipSuccess)
-        e = launch(flux_batch<false, S>, dim3(b->nb_flux), blk2, st, (const BStage<S> *)T(b->o_s1),
+        e = launch(flux_batch<false, S>, dim3(b->nb_flux), blk2, st, (const BStage<S> *)T(b->o_s1[par]),
                    M(b->o_mflux), F(b->o_fflux));
     if (e == hipSuccess)
-        e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r1),
+        e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r1[par]),
                    M(b->o_mrec), F(b->o_frec), tau);
     if (e == hipSuccess)
         e = launch(faces_batch<CART, S>, dim3(b->nb_face), dim3(FACE_BLOCK), st, (const BFace<S> *)T(b->o_f1),
                    M(b->o_mface), F(b->o_fface), tau);
     if (e == hipSuccess)
         e = launch(sources_batch<CART, true, S>, dim3(b->nb_src), blk2, st,
-                   (const BStage<S> *)T(b->o_s2), M(b->o_msrc), F(b->o_fsrc), tau);
+                   (const BStage<S> *)T(b->o_s2[par]), M(b->o_msrc), F(b->o_fsrc), tau);
     if (e == hipSuccess)
-        e = launch(flux_batch<true, S>, dim3(b->nb_flux), blk2, st, (const BStage<S> *)T(b->o_s2),
+        e = launch(flux_batch<true, S>, dim3(b->nb_flux), blk2, st, (const BStage<S> *)T(b->o_s2[par]),
                    M(b->o_mflux), F(b->o_fflux));
     if (e == hipSuccess)
-        e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r2),
+        e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r2[par]),
                    M(b->o_mrec), F(b->o_frec), tau);
     if (e == hipSuccess)
         e = launch(faces_batch<CART, S>, dim3(b->nb_face), dim3(FACE_BLOCK), st, (const BFace<S> *)T(b->o_f2),
                    M(b->o_mface), F(b->o_fface), tau);
-    if (e == hipSuccess)
-        e = launch(rotate_batch, dim3(b->nb_rot), blk, st, (const BCopy *)T(b->o_rot), M(b->o_mrot),
-                   F(b->o_frot));
     if (e == hipSuccess) e = launch(tau_advance_kernel, dim3(1), dim3(64), st, b->tau_dev, b->dtau);
     return e;
 }
@@ -2074,7 +2058,7 @@ static hipError_t batch_step_launches(kt_batch *b, hipStream_t st)
 template <bool CART, typename S>
 static hipError_t batch_stage1_t(kt_batch *b, hipStream_t st)
 {
-    const BStage<S> *tab = (const BStage<S> *)(const void *)(b->tab + b->o_s1);
+    const BStage<S> *tab = (const BStage<S> *)(const void *)(b->tab + b->o_s1[b->step & 1]);
     hipError_t e = launch(sources_batch<CART, false, S>, dim3(b->nb_src), dim3(64, 4), st, tab,
                           (const unsigned short *)(b->tab + b->o_msrc), (const unsigned *)(b->tab + b->o_fsrc),
                           (const double *)b->tau_dev);
@@ -2090,18 +2074,20 @@ static hipError_t batch_stage1(kt_batch *b, hipStream_t st)
     return b->cart ? batch_stage1_t<true, double>(b, st) : batch_stage1_t<false, double>(b, st);
 }
 
-static hipError_t batch_launches(kt_batch *b, hipStream_t st)
+static hipError_t batch_launches(kt_batch *b, hipStream_t st, int par)
 {
     if (b->mixed)
-        return b->cart ? batch_step_launches<true, float>(b, st) : batch_step_launches<false, float>(b, st);
-    return b->cart ? batch_step_launches<true, double>(b, st) : batch_step_launches<false, double>(b, st);
+        return b->cart ? batch_step_launches<true, float>(b, st, par) : batch_step_launches<false, float>(b, st, par);
+    return b->cart ? batch_step_launches<true, double>(b, st, par) : batch_step_launches<false, double>(b, st, par);
 }
 
 static void batch_drop_graph(kt_batch *b)
 {
     if (b->have_graph) {
-        (void)hipGraphExecDestroy(b->exec);
-        (void)hipGraphDestroy(b->graph);
+        for (int par = 0; par < 2; ++par) {
+            (void)hipGraphExecDestroy(b->exec[par]);
+            (void)hipGraphDestroy(b->graph[par]);
+        }
         b->have_graph = false;
     }
 }
@@ -2215,19 +2201,35 @@ kt_status kt_batch_step(kt_batch *b, int32_t n_steps)
     if (n_steps == 0) return KT_OK;
     hipError_t e = hipSuccess;
     if (!b->have_graph) {
-        e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            hipError_t le = batch_launches(b, b->cap);
-            e = hipStreamEndCapture(b->cap, &b->graph);
-            if (le != hipSuccess) e = le;
+        // the u buffers swap roles every step, so there is one graph per step parity
+        int made = 0;
+        for (int par = 0; par < 2 && e == hipSuccess; ++par) {
+            e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t le = batch_launches(b, b->cap, par);
+                e = hipStreamEndCapture(b->cap, &b->graph[par]);
+                if (le != hipSuccess && e == hipSuccess) {
+                    (void)hipGraphDestroy(b->graph[par]);
+                    e = le;
+                } else if (e == hipSuccess) {
+                    e = hipGraphInstantiate(&b->exec[par], b->graph[par], nullptr, nullptr, 0);
+                    if (e == hipSuccess) made += 1;
+                    else (void)hipGraphDestroy(b->graph[par]);
+                }
+            }
         }
-        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) return bfail(b, KT_E_HIP, "step graph: %s", hipGetErrorString(e));
+        if (e != hipSuccess) {
+            for (int par = 0; par < made; ++par) {
+                (void)hipGraphExecDestroy(b->exec[par]);
+                (void)hipGraphDestroy(b->graph[par]);
+            }
+            return bfail(b, KT_E_HIP, "step graph: %s", hipGetErrorString(e));
+        }
         b->have_graph = true;
     }
     e = hipEventRecord(b->fork_ev, b->user);
     if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->fork_ev, 0);
-    for (int s = 0; s < n_steps && e == hipSuccess; ++s) e = hipGraphLaunch(b->exec, b->cap);
+    for (int s = 0; s < n_steps && e == hipSuccess; ++s) e = hipGraphLaunch(b->exec[(b->step + s) & 1], b->cap);
     if (e == hipSuccess) e = hipEventRecord(b->join_ev, b->cap);
     if (e == hipSuccess) e = hipStreamWaitEvent(b->user, b->join_ev, 0);
     if (e != hipSuccess) return bfail(b, KT_E_HIP, "batch step: %s", hipGetErrorString(e));
@@ -2238,6 +2240,8 @@ kt_status kt_batch_step(kt_batch *b, int32_t n_steps)
     for (kt_ctx *c : b->ev) {
         c->tau = b->tau;
         c->step = b->step;
+        c->ucur = (int)(b->step & 1);   // u^n, u^{n-1} for kt_observables
+        c->uprev = 1 - c->ucur;
     }
     return KT_OK;
 }
