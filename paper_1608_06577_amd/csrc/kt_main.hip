@@ -238,9 +238,8 @@ __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, co
         const R h = side ? R(-0.5) : R(0.5);
         const R theta = R(P.theta);
         const idx_t SS = (idx_t)P.stride;
-        double m[9];
-#pragma unroll
-        for (int r = 0; r < 9; ++r) {
+        // component r (0..8: T^{tau mu}, pi^{tau mu}, Pi) of the reconstructed state
+        auto recon = [&](int r) -> double {
             R a0, a1, a2;
             if (r < 4) {
                 const idx_t co = (idx_t)r * SS;
@@ -249,17 +248,31 @@ __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, co
                 const idx_t co = (idx_t)(r < 8 ? r - PTT : BPI - PTT) * SS;
                 a0 = R(ld(qP, co + sm)); a1 = R(ld(qP, co + s0)); a2 = R(ld(qP, co + sp));
             }
-            m[r] = (double)(a1 + h * slope(a0, a1, a2, theta));
-        }
-        // v^d = u^d / u^tau = M^d / (E + P) (Sec. 2.4), 0 on the floor
-        double ee, pe, EE, M[3];
-        const double Pi = P.bulk ? m[8] : 0.0;
-        fl = invert_core<CART>(P, E, tau, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], Pi,
-                               (double)ld(e, s0), ee, pe, EE, M, it);
-        const double Md = d == 0 ? M[0] : (d == 1 ? M[1] : M[2]);
-        const double v = (fl & F_FLOOR) ? 0.0 : Md / (EE + pe + Pi);
+            return (double)(a1 + h * slope(a0, a1, a2, theta));
+        };
         const long long off = (d == 0 ? G.ox : (d == 1 ? G.oy : G.oe)) + (side ? nf : 0);
-        st(vf + off, t, (S)v);
+        double m[9];
+        m[0] = recon(0);
+        m[4] = recon(PTT);
+        // A state with E = T^{tau tau} - pi^{tau tau} <= e_floor is the floor state
+        // whatever its other components (the inversion's first guard).  Vacuum
+        // regions make whole waves of such states; they skip the rest.
+        if (__all(!(m[0] - m[4] > P.e_floor))) {
+            fl = F_FLOOR;
+            st(vf + off, t, (S)0.0);
+        } else {
+#pragma unroll
+            for (int r = 1; r < 9; ++r)
+                if (r != PTT) m[r] = recon(r);
+            // v^d = u^d / u^tau = M^d / (E + P) (Sec. 2.4), 0 on the floor
+            double ee, pe, EE, M[3];
+            const double Pi = P.bulk ? m[8] : 0.0;
+            fl = invert_core<CART>(P, E, tau, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], Pi,
+                                   (double)ld(e, s0), ee, pe, EE, M, it);
+            const double Md = d == 0 ? M[0] : (d == 1 ? M[1] : M[2]);
+            const double v = (fl & F_FLOOR) ? 0.0 : Md / (EE + pe + Pi);
+            st(vf + off, t, (S)v);
+        }
     }
     slot_add(slots, wave, C_ITERS_FACES, it, iter_bits(P));
     slot_add(slots, wave, C_REC_FACES, valid ? 1 : 0);
