@@ -638,7 +638,24 @@ __device__ __forceinline__ void recover_body(const Phys &P, const Eos &E, double
     const idx_t SS = (idx_t)P.stride;
     int it = 0, fl = 0;
     const bool valid = (long long)s < P.ncell;
-    if (valid) {
+    // E = T^{tau tau} - pi^{tau tau} <= e_floor gives the floor state whatever the
+    // other components (the inversion's first guard); with the floor reset on, a
+    // wave of such cells (vacuum) writes that state without reading the rest or
+    // evaluating the network (measured: no gain without the network, where the
+    // extra registers cost the batched kernel a wave per SIMD)
+    const bool vacuum = LEARNED && valid && P.floor_reset
+                     && __all(!(ld(qT, s) - ldq(qT, qP, PTT, SS, s) > P.e_floor));
+    if (vacuum) {
+        fl = F_FLOOR;
+        st(e_io, s, (S)P.e_floor);
+        st(p_out, s, (S)P.p_floor);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) st(u_out, (idx_t)(m) * SS + s, m == 0 ? 1.0 : 0.0);
+#pragma unroll
+        for (int c = 0; c < PTT; ++c) st(qT, (idx_t)c * SS + s, c == TT ? P.e_floor : 0.0);
+#pragma unroll
+        for (int c = PTT; c < NQ; ++c) st(qP, (idx_t)(c - PTT) * SS + s, (S)0);
+    } else if (valid) {
         double es = warm ? (double)ld(e_io, s) : -1.0;
         if (LEARNED) {   // before the cell's state is held in registers
             const double Ttt = ld(qT, s), ptt = ldq(qT, qP, PTT, SS, s);
