@@ -171,7 +171,7 @@ def learned_leg(args, kt, I, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr, flush=True)
         sys.exit(2)
     import torch

@@ -59,7 +59,7 @@ typedef enum {
     KT_E_ALLOC = 2,        /* workspace too small */
     KT_E_HIP = 3,          /* HIP runtime or device error */
     KT_E_STATE = 4,        /* call not valid in the context's state */
-    KT_E_UNSUPPORTED = 5   /* valid request this build does not implement */
+    KT_E_UNSUPPORTED = 5   /* valid request the library does not implement */
 } kt_status;
 
 enum { KT_FP64 = 0, KT_MIXED = 1 };           /* kt_params.precision */
