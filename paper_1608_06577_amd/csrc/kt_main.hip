@@ -155,6 +155,31 @@ __device__ __forceinline__ void slot_add(unsigned long long *slots, long long wa
 // bits needed for Newton iteration counts (at most newton_max)
 __device__ __forceinline__ int iter_bits(const Phys &P) { return 32 - __clz(P.newton_max); }
 
+// Lane shifts within a wave (DPP wave shifts, VALU operations): lane l gets
+// the value of lane l+1 (lane_next; lane 63 keeps its own) or of lane l-1
+// (lane_prev; lane 0 keeps its own).  Every lane of the wave must be active.
+__device__ __forceinline__ int dpp_wave_shift(int v, bool next)
+{
+    return next ? __builtin_amdgcn_update_dpp(v, v, 0x130, 0xF, 0xF, false)    // wave_shl:1
+                : __builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false);   // wave_shr:1
+}
+
+__device__ __forceinline__ double lane_shift(double v, bool next)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)dpp_wave_shift((int)(unsigned)b, next);
+    const unsigned hi = (unsigned)dpp_wave_shift((int)(unsigned)(b >> 32), next);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ float lane_shift(float v, bool next)
+{
+    return __int_as_float(dpp_wave_shift(__float_as_int(v), next));
+}
+
+template <typename T> __device__ __forceinline__ T lane_next(T v) { return lane_shift(v, true); }
+template <typename T> __device__ __forceinline__ T lane_prev(T v) { return lane_shift(v, false); }
+
 // ------------------------------------------------------------ KT flux ----
 // One face between a left cell L and a right cell R (Sec. 3.1): with the
 // minmod slopes of both cells, the half-cell extrapolations
@@ -506,6 +531,7 @@ __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const
     const int ifc = i <= P.nx ? i : P.nx;     // x face index of this lane
     const bool out_ok = i < P.nx && j < P.ny;
     const bool right = lane == 63 && out_ok;  // this lane also computes its right x face
+    const bool xper = P.periodic[0] != 0;
     const int xm2 = wrap(i - 2, P.nx, P.periodic[0]), xm1 = wrap(i - 1, P.nx, P.periodic[0]);
     const int x0 = wrap(i, P.nx, P.periodic[0]), xp1 = wrap(i + 1, P.nx, P.periodic[0]);
     const int xp2 = wrap(i + 2, P.nx, P.periodic[0]);
@@ -562,17 +588,32 @@ __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const
         auto divergence = [&](auto rtag, const auto *q, idx_t co, auto *Hc) {
             typedef decltype(rtag) RR;
             const RR th = RR(P.theta), h = RR(0.5);
-            const RR xa = RR(ld(q, co + rx + xm2)), xb = RR(ld(q, co + rx + xm1)), xc = RR(ld(q, co + rx + x0));
-            const RR xd = RR(ld(q, co + rx + xp1)), xe = RR(ld(q, co + rx + xp2));
             const RR ya = RR(ld(q, co + r0)), yb = RR(ld(q, co + r1)), yc = RR(ld(q, co + s));
             const RR yd = RR(ld(q, co + r3)), ye = RR(ld(q, co + r4));
-            const RR ea = RR(ld(q, co + e0)), eb = RR(ld(q, co + e1));
-            const RR ed = RR(ld(q, co + e3)), ee = RR(ld(q, co + e4));
+            const RR eb = RR(ld(q, co + e1)), ed = RR(ld(q, co + e3)), ee = RR(ld(q, co + e4));
+            // x neighbours: the row is spread over the wave's lanes, so they come
+            // from lane shifts of the cell's own value; lanes 0 and 63 read the
+            // two cells beyond the row's ends.  (The cell's value at the wrapped
+            // x index equals yc unless x is periodic.)
+            RR edge1 = RR(0), edge2 = RR(0);
+            if (lane == 0 || lane == 63) {
+                edge1 = RR(ld(q, co + rx + (lane == 0 ? xm1 : xp1)));
+                edge2 = RR(ld(q, co + rx + (lane == 0 ? xm2 : xp2)));
+            }
+            const RR xc = xper ? RR(ld(q, co + rx + x0)) : yc;
+            // (each shift is taken by every lane before the select: an inactive
+            // source lane would hand back the lane's own value)
+            const RR sb = lane_prev(xc), sd = lane_next(xc);
+            const RR xb = lane == 0 ? edge1 : sb;
+            const RR xd = lane == 63 ? edge1 : sd;
+            const RR sa = lane_prev(xb), se = lane_next(xd);
+            const RR xa = lane == 0 ? edge2 : sa;
+            const RR xe = lane == 63 ? edge2 : se;
             // x: the face left of the cell; the right one from lane l+1 (lane 63: its own)
             const RR sxb = slope(xa, xb, xc, th), sxc = slope(xb, xc, xd, th), sxd = slope(xc, xd, xe, th);
             const RR Hx = face_H<RR>(xb + h * sxb, xc - h * sxc, RR(vmx), RR(vpx), RR(ax));
             const RR Hown = face_H<RR>(xc + h * sxc, xd - h * sxd, RR(vmr), RR(vpr), RR(axr));
-            const RR Hnb = __shfl_down(Hx, 1);
+            const RR Hnb = lane_next(Hx);
             RR D = (Hx - (right ? Hown : Hnb)) * RR(P.inv_dx);
             // y
             const RR syb = slope(ya, yb, yc, th), syc = slope(yb, yc, yd, th), syd = slope(yc, yd, ye, th);
@@ -581,10 +622,12 @@ __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const
             // eta: the bottom face is carried from the plane below except in the first plane
             const RR sec = slope(eb, yc, ed, th), sed = slope(yc, ed, ee, th);
             RR Hb0;
-            if (kk == 0)
+            if (kk == 0) {
+                const RR ea = RR(ld(q, co + e0));
                 Hb0 = face_H<RR>(eb + h * slope(ea, eb, yc, th), yc - h * sec, RR(vmb), RR(vpb), RR(ab));
-            else
+            } else {
                 Hb0 = Hc[tid];
+            }
             const RR Ht = face_H<RR>(yc + h * sec, ed - h * sed, RR(vme), RR(vpe), RR(ae));
             Hc[tid] = Ht;
             D += (Hb0 - Ht) * RR(P.inv_deta);
