@@ -39,9 +39,9 @@ KERNEL_VALUES = {"flux": 45.0, "sources": 47.5, "recover": 32.0, "faces": 16.0}
 # WRITE_SIZE x 1.000 (scale factors of a 256 MiB device copy), profiles/kt_step_hotspot128_fp64.md;
 # valid for the kernel sources and compiler flags whose hash is TRAFFIC_SOURCES (else the traffic
 # is reported as null)
-TRAFFIC_SOURCES = "f8c4b62fb7e2b908"
-TRAFFIC_BYTES = {"faces": 1.0857e9 + 1.078e8, "flux": 0.5 * (1.3566e9 + 1.3592e9) + 2.517e8,
-                 "sources": 0.5 * (9.458e8 + 1.2252e9) + 2.517e8, "recover": 2.706e8 + 3.199e8}
+TRAFFIC_SOURCES = "023d7414c86d1521"
+TRAFFIC_BYTES = {"faces": 8.985e8 + 1.079e8, "flux": 0.5 * (1.3674e9 + 1.3710e9) + 2.517e8,
+                 "sources": 0.5 * (9.528e8 + 1.2137e9) + 2.517e8, "recover": 2.706e8 + 3.198e8}
 KERNEL_NAMES = {"flux": "flux_kernel (KT flux divergence + stage update)",
                 "sources": "sources_kernel (App. B sources + stage update)",
                 "recover": "recover_kernel (Newton inversion + regulator)",
