@@ -155,30 +155,48 @@ __device__ __forceinline__ void slot_add(unsigned long long *slots, long long wa
 // bits needed for Newton iteration counts (at most newton_max)
 __device__ __forceinline__ int iter_bits(const Phys &P) { return 32 - __clz(P.newton_max); }
 
-// Lane shifts within a wave (DPP wave shifts, VALU operations): lane l gets
-// the value of lane l+1 (lane_next; lane 63 keeps its own) or of lane l-1
-// (lane_prev; lane 0 keeps its own).  Every lane of the wave must be active.
-__device__ __forceinline__ int dpp_wave_shift(int v, bool next)
+// Lane exchanges of the flux kernel, whose wave holds 4 rows of 16 cells
+// (lane = 16 row + column).  Every lane of the wave must be active.
+//   row_next / row_prev: lane l gets lane l+1 / l-1 of its own row of 16 (DPP
+//     row shifts, VALU); the last / first lane of a row keeps its own value;
+//   half_swap: lane l gets lane l^32 (v_permlane32_swap, VALU);
+//   row_down / row_up: lane l gets lane l-16 / l+16 modulo 64 (ds_bpermute).
+template <int CTRL> __device__ __forceinline__ int dpp_i(int v)
 {
-    return next ? __builtin_amdgcn_update_dpp(v, v, 0x130, 0xF, 0xF, false)    // wave_shl:1
-                : __builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false);   // wave_shr:1
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
 }
+__device__ __forceinline__ int half_swap_i(int v)
+{
+    const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    // p[0] holds lanes 0-31 of v in both halves, p[1] lanes 32-63
+    return (__lane_id() & 32) ? (int)p[0] : (int)p[1];
+}
+__device__ __forceinline__ int read_lane_i(int v, int src) { return __builtin_amdgcn_ds_bpermute((src & 63) << 2, v); }
 
-__device__ __forceinline__ double lane_shift(double v, bool next)
+template <typename F> __device__ __forceinline__ double per_word(double v, F f)
 {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = (unsigned)dpp_wave_shift((int)(unsigned)b, next);
-    const unsigned hi = (unsigned)dpp_wave_shift((int)(unsigned)(b >> 32), next);
+    const unsigned lo = (unsigned)f((int)(unsigned)b);
+    const unsigned hi = (unsigned)f((int)(unsigned)(b >> 32));
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
-
-__device__ __forceinline__ float lane_shift(float v, bool next)
+template <typename F> __device__ __forceinline__ float per_word(float v, F f)
 {
-    return __int_as_float(dpp_wave_shift(__float_as_int(v), next));
+    return __int_as_float(f(__float_as_int(v)));
 }
-
-template <typename T> __device__ __forceinline__ T lane_next(T v) { return lane_shift(v, true); }
-template <typename T> __device__ __forceinline__ T lane_prev(T v) { return lane_shift(v, false); }
+template <typename T> __device__ __forceinline__ T row_next(T v) { return per_word(v, dpp_i<0x101>); }  // row_shl:1
+template <typename T> __device__ __forceinline__ T row_prev(T v) { return per_word(v, dpp_i<0x111>); }  // row_shr:1
+template <typename T> __device__ __forceinline__ T half_swap(T v) { return per_word(v, half_swap_i); }
+template <typename T> __device__ __forceinline__ T row_down(T v)
+{
+    const int src = (int)__lane_id() - 16;
+    return per_word(v, [src](int w) { return read_lane_i(w, src); });
+}
+template <typename T> __device__ __forceinline__ T row_up(T v)
+{
+    const int src = (int)__lane_id() + 16;
+    return per_word(v, [src](int w) { return read_lane_i(w, src); });
+}
 
 // ------------------------------------------------------------ KT flux ----
 // One face between a left cell L and a right cell R (Sec. 3.1): with the
@@ -506,11 +524,15 @@ __global__ __launch_bounds__(256) void sources_kernel(Phys P, Eos E, double tau,
 // component (Sec. 3.1), then
 //   stage 1: out = out + dtau D;   stage 2: out = (out + dtau D) / 2,
 // which with sources_kernel gives q + dtau C[q] and (qn + q + dtau C[q]) / 2.
-// Face speeds come from face_speeds_kernel.  x faces: lane l computes the
-// face on the left of its cell and takes the right one from lane l+1 (lane
-// 63 computes its right face itself); eta faces: the top face of plane k is
-// the bottom face of plane k+1 (kept in LDS per thread); y faces: two per
-// cell.  Components are processed one at a time.
+// Face speeds come from face_speeds_kernel.  Each wave holds 16 x 4 cells
+// (x by y; lane = 16 row + column), so that a cell's y neighbours are mostly
+// other lanes' cells: every lane loads its own cell and one cell of the four
+// halo rows (y0-2, y0-1, y0+4, y0+5), and the stencil is assembled by lane
+// exchanges.  x faces: lane l computes the face on the left of its cell and
+// takes the right one from the next lane of its row (the last lane of a row
+// computes its right face itself); eta faces: the top face of plane k is the
+// bottom face of plane k+1 (kept in LDS per thread); y faces: two per cell.
+// Components are processed one at a time.
 // Hb: the block's LDS carry of the eta faces; kc: eta planes per block
 template <bool STAGE2, typename S>
 __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const double *qT, const S *qP,
@@ -520,23 +542,25 @@ __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const
     typedef S R;   // flux arithmetic of pi and Pi; T^{tau mu} is done in FP64
     const int lane = threadIdx.x;
     const int tid = threadIdx.y * 64 + lane;
-    const int i = bx * 64 + lane;
-    const int j = by * 4 + threadIdx.y;
+    const int xl = lane & 15, r = lane >> 4;     // column and row of the lane in its wave
+    const int i = bx * 64 + threadIdx.y * 16 + xl;
+    const int j0 = by * 4;
+    const int j = j0 + r;
     const int k0 = bz * kc;
     const idx_t plane = (idx_t)P.nx * P.ny;
     const idx_t SS = (idx_t)P.stride;
-    // lanes outside the grid compute on clamped cells; their results are not stored
-    const int ic = i < P.nx ? i : P.nx - 1;
-    const int jc = j < P.ny ? j : P.ny - 1;
+    // lanes outside the grid compute on the cell their index wraps to (the last
+    // cell of a non-periodic direction); their results are not stored.  Cells
+    // that are in the grid then find their wrapped neighbours in the lanes
+    // next to them.
+    const int ic = wrap(i, P.nx, P.periodic[0]);
+    const int jc = wrap(j, P.ny, P.periodic[1]);
+    const int jh = wrap(j0 + (r < 2 ? r - 2 : r + 2), P.ny, P.periodic[1]);   // this lane's halo row
     const int ifc = i <= P.nx ? i : P.nx;     // x face index of this lane
     const bool out_ok = i < P.nx && j < P.ny;
-    const bool right = lane == 63 && out_ok;  // this lane also computes its right x face
-    const bool xper = P.periodic[0] != 0;
+    const bool right = xl == 15 && out_ok;   // this lane also computes its right x face
     const int xm2 = wrap(i - 2, P.nx, P.periodic[0]), xm1 = wrap(i - 1, P.nx, P.periodic[0]);
-    const int x0 = wrap(i, P.nx, P.periodic[0]), xp1 = wrap(i + 1, P.nx, P.periodic[0]);
-    const int xp2 = wrap(i + 2, P.nx, P.periodic[0]);
-    const int ym2 = wrap(jc - 2, P.ny, P.periodic[1]), ym1 = wrap(jc - 1, P.ny, P.periodic[1]);
-    const int yp1 = wrap(jc + 1, P.ny, P.periodic[1]), yp2 = wrap(jc + 2, P.ny, P.periodic[1]);
+    const int xp1 = wrap(i + 1, P.nx, P.periodic[0]), xp2 = wrap(i + 2, P.nx, P.periodic[0]);
     const S *vfx = vf + G.ox, *vfy = vf + G.oy, *vfe = vf + G.oe;
     const double f = P.dtau;
     // evolved dissipative components: pi (if shear) and Pi (if bulk)
@@ -551,7 +575,7 @@ __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const
         const idx_t col = (idx_t)jc * P.nx + ic;
         const int zm2 = wrap(k - 2, P.neta, P.periodic[2]), zm1 = wrap(k - 1, P.neta, P.periodic[2]);
         const int zp1 = wrap(k + 1, P.neta, P.periodic[2]), zp2 = wrap(k + 2, P.neta, P.periodic[2]);
-        // face speeds: x (left face, and the right one for lane 63), y (both), eta (top)
+        // face speeds: x (left face, and the right one for the last lane of a row), y (both), eta (top)
         const idx_t fx = fidx_x(P.nx, P.ny, ifc, jc, k);
         const R vmx = R(ld(vfx, fx)), vpx = R(ld(vfx + G.nfx, fx));
         const R ax = fmax(fabs(vmx), fabs(vpx));
@@ -576,44 +600,45 @@ __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const
         }
         const R ab = fmax(fabs(vmb), fabs(vpb));
         const idx_t rx = kp + (idx_t)jc * P.nx;
-        const idx_t bb = kp + ic;
-        const idx_t r0 = bb + (idx_t)ym2 * P.nx, r1 = bb + (idx_t)ym1 * P.nx;
-        const idx_t r3 = bb + (idx_t)yp1 * P.nx, r4 = bb + (idx_t)yp2 * P.nx;
+        const idx_t rh = kp + (idx_t)jh * P.nx + ic;
         const idx_t e0 = col + (idx_t)zm2 * plane, e1 = col + (idx_t)zm1 * plane;
         const idx_t e3 = col + (idx_t)zp1 * plane, e4 = col + (idx_t)zp2 * plane;
         // divergence D of one component (array q, component offset co) in the
-        // arithmetic type RR, with the eta carry Hc.  The fourteen values of the
-        // stencil are loaded together (no load waits on a branch), and each
-        // cell's slope along a direction is computed once.
+        // arithmetic type RR, with the eta carry Hc.  The loads are issued
+        // together (no load waits on a branch), and each cell's slope along a
+        // direction is computed once.
         auto divergence = [&](auto rtag, const auto *q, idx_t co, auto *Hc) {
             typedef decltype(rtag) RR;
             const RR th = RR(P.theta), h = RR(0.5);
-            const RR ya = RR(ld(q, co + r0)), yb = RR(ld(q, co + r1)), yc = RR(ld(q, co + s));
-            const RR yd = RR(ld(q, co + r3)), ye = RR(ld(q, co + r4));
+            const RR yc = RR(ld(q, co + s)), yh = RR(ld(q, co + rh));
             const RR eb = RR(ld(q, co + e1)), ed = RR(ld(q, co + e3)), ee = RR(ld(q, co + e4));
-            // x neighbours: the row is spread over the wave's lanes, so they come
-            // from lane shifts of the cell's own value; lanes 0 and 63 read the
-            // two cells beyond the row's ends.  (The cell's value at the wrapped
-            // x index equals yc unless x is periodic.)
+            // the first and last lane of a row read the two cells beyond its ends
             RR edge1 = RR(0), edge2 = RR(0);
-            if (lane == 0 || lane == 63) {
-                edge1 = RR(ld(q, co + rx + (lane == 0 ? xm1 : xp1)));
-                edge2 = RR(ld(q, co + rx + (lane == 0 ? xm2 : xp2)));
+            if (xl == 0 || xl == 15) {
+                edge1 = RR(ld(q, co + rx + (xl == 0 ? xm1 : xp1)));
+                edge2 = RR(ld(q, co + rx + (xl == 0 ? xm2 : xp2)));
             }
-            const RR xc = xper ? RR(ld(q, co + rx + x0)) : yc;
-            // (each shift is taken by every lane before the select: an inactive
-            // source lane would hand back the lane's own value)
-            const RR sb = lane_prev(xc), sd = lane_next(xc);
-            const RR xb = lane == 0 ? edge1 : sb;
-            const RR xd = lane == 63 ? edge1 : sd;
-            const RR sa = lane_prev(xb), se = lane_next(xd);
-            const RR xa = lane == 0 ? edge2 : sa;
-            const RR xe = lane == 63 ? edge2 : se;
-            // x: the face left of the cell; the right one from lane l+1 (lane 63: its own)
+            // y neighbours j-2, j-1, j+1, j+2: rows r-2 .. r+2 of the wave where
+            // they exist, else halo rows (every exchange is taken by all lanes
+            // before any select)
+            const RR o32 = half_swap(yc), h32 = half_swap(yh);
+            const RR ya = r < 2 ? yh : o32;
+            const RR ye = r < 2 ? o32 : yh;
+            const RR mb = r == 3 ? h32 : yc, md = r == 0 ? h32 : yc;
+            const RR yb = row_down(mb), yd = row_up(md);
+            // x neighbours from the lanes of the row
+            const RR sb = row_prev(yc), sd = row_next(yc);
+            const RR xb = xl == 0 ? edge1 : sb;
+            const RR xd = xl == 15 ? edge1 : sd;
+            const RR sa = row_prev(xb), se = row_next(xd);
+            const RR xa = xl == 0 ? edge2 : sa;
+            const RR xe = xl == 15 ? edge2 : se;
+            const RR xc = yc;
+            // x: the face left of the cell; the right one from the next lane (the row's last lane: its own)
             const RR sxb = slope(xa, xb, xc, th), sxc = slope(xb, xc, xd, th), sxd = slope(xc, xd, xe, th);
             const RR Hx = face_H<RR>(xb + h * sxb, xc - h * sxc, RR(vmx), RR(vpx), RR(ax));
             const RR Hown = face_H<RR>(xc + h * sxc, xd - h * sxd, RR(vmr), RR(vpr), RR(axr));
-            const RR Hnb = lane_next(Hx);
+            const RR Hnb = row_next(Hx);
             RR D = (Hx - (right ? Hown : Hnb)) * RR(P.inv_dx);
             // y
             const RR syb = slope(ya, yb, yc, th), syc = slope(yb, yc, yd, th), syd = slope(yc, yd, ye, th);
