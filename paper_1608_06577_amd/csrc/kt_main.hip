@@ -215,18 +215,17 @@ __device__ __forceinline__ R face_H(R qm, R qp, R vm, R vp, R a)
 // q^+ = q_R - slope_R/2 from the cell on its right; each is inverted like a
 // cell (warm start: the e of the cell it was extrapolated from) and the
 // velocity component normal to the face is stored.
-// One thread per face and side.
-// The launch is cut into six segments of whole blocks, (x, y, eta) x (minus,
-// plus), in that order; a thread's index within its segment is the face
-// index of fidx_x / fidx_y / fidx_e.  (Interleaving the segments block by
-// block shares cells in L2 and halves this kernel's fetches, but measured
-// slower.)
+// One thread per face: it reads the four cells of the face's line that the
+// two slopes need and inverts q^- and then q^+.
+// The launch is cut into three segments of whole blocks, x, y and eta faces,
+// in that order; a thread's index within its segment is the face index of
+// fidx_x / fidx_y / fidx_e.
 constexpr int FACE_BLOCK = 256;   // threads per block of the face kernels
 // The face kernels are latency-bound (dependent EOS table reads inside each
 // Newton solve): they are held to 64 VGPRs, i.e. 8 waves per SIMD.
 
 struct FaceLaunch {
-    unsigned first_block[6];    // first block of each segment
+    unsigned first_block[3];    // first block of each segment
     unsigned nblocks;           // total
     double inv_nx1, inv_nx, inv_ny1, inv_plane;   // 1/(nx+1), 1/nx, 1/(ny+1), 1/(nx ny)
 };
@@ -236,16 +235,14 @@ template <bool CART, typename S>
 __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, const FaceGeo G,
                                                  const FaceLaunch L, double tau, const double *qT,
                                                  const S *qP, const S *e, S *vf,
-                                                 unsigned long long *slots, unsigned b, long long wave)
+                                                 unsigned long long *slots, unsigned b, long long wave,
+                                                 double (*qpark)[FACE_BLOCK])
 {
     typedef S R;   // reconstruction arithmetic; the inversion itself is FP64
-    int seg = 0;
-#pragma unroll
-    for (int k = 1; k < 6; ++k) seg += b >= L.first_block[k] ? 1 : 0;
-    const int d = seg >> 1, side = seg & 1;     // side 0: q^-, side 1: q^+
-    const idx_t t = (idx_t)(b - L.first_block[seg]) * FACE_BLOCK + threadIdx.x;
+    const int d = (b >= L.first_block[1] ? 1 : 0) + (b >= L.first_block[2] ? 1 : 0);
+    const idx_t t = (idx_t)(b - L.first_block[d]) * FACE_BLOCK + threadIdx.x;
     const long long nf = d == 0 ? G.nfx : (d == 1 ? G.nfy : G.nfe);
-    int it = 0, fl = 0;
+    int it = 0, nfb = 0;
     const bool valid = (long long)t < nf;
     if (valid) {
         // (i, j, k) of the face, the line of cells through it along d
@@ -273,53 +270,74 @@ __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, co
             n = P.neta;
             per = P.periodic[2];
         }
-        // face pos lies between cells pos-1 and pos; the state comes from cell c
-        const int c = pos - 1 + side;
-        const idx_t sm = base + (idx_t)wrap(c - 1, n, per) * step;
-        const idx_t s0 = base + (idx_t)wrap(c, n, per) * step;
-        const idx_t sp = base + (idx_t)wrap(c + 1, n, per) * step;
-        const R h = side ? R(-0.5) : R(0.5);
+        // face pos lies between cells pos-1 (L) and pos (R)
+        const idx_t c0 = base + (idx_t)wrap(pos - 2, n, per) * step;
+        const idx_t cL = base + (idx_t)wrap(pos - 1, n, per) * step;
+        const idx_t cR = base + (idx_t)wrap(pos, n, per) * step;
+        const idx_t c3 = base + (idx_t)wrap(pos + 1, n, per) * step;
         const R theta = R(P.theta);
         const idx_t SS = (idx_t)P.stride;
-        // component r (0..8: T^{tau mu}, pi^{tau mu}, Pi) of the reconstructed state
-        auto recon = [&](int r) -> double {
-            R a0, a1, a2;
+        // component r (0..8: T^{tau mu}, pi^{tau mu}, Pi) of q^- and q^+
+        auto recon = [&](int r, double &qm, double &qp) {
+            R a0, a1, a2, a3;
             if (r < 4) {
                 const idx_t co = (idx_t)r * SS;
-                a0 = R(ld(qT, co + sm)); a1 = R(ld(qT, co + s0)); a2 = R(ld(qT, co + sp));
+                a0 = R(ld(qT, co + c0)); a1 = R(ld(qT, co + cL));
+                a2 = R(ld(qT, co + cR)); a3 = R(ld(qT, co + c3));
             } else {
                 const idx_t co = (idx_t)(r < 8 ? r - PTT : BPI - PTT) * SS;
-                a0 = R(ld(qP, co + sm)); a1 = R(ld(qP, co + s0)); a2 = R(ld(qP, co + sp));
+                a0 = R(ld(qP, co + c0)); a1 = R(ld(qP, co + cL));
+                a2 = R(ld(qP, co + cR)); a3 = R(ld(qP, co + c3));
             }
-            return (double)(a1 + h * slope(a0, a1, a2, theta));
+            qm = (double)(a1 + R(0.5) * slope(a0, a1, a2, theta));
+            qp = (double)(a2 - R(0.5) * slope(a1, a2, a3, theta));
         };
-        const long long off = (d == 0 ? G.ox : (d == 1 ? G.oy : G.oe)) + (side ? nf : 0);
-        double m[9];
-        m[0] = recon(0);
-        m[4] = recon(PTT);
+        const long long off = d == 0 ? G.ox : (d == 1 ? G.oy : G.oe);
+        // q^+ waits in the block's LDS (qpark, this thread's column) while q^- is inverted
+        const int tx = threadIdx.x;
+        double mm[9], mp[9];
+        recon(0, mm[0], mp[0]);
+        recon(PTT, mm[4], mp[4]);
         // A state with E = T^{tau tau} - pi^{tau tau} <= e_floor is the floor state
         // whatever its other components (the inversion's first guard).  Vacuum
         // regions make whole waves of such states; they skip the rest.
-        if (__all(!(m[0] - m[4] > P.e_floor))) {
-            fl = F_FLOOR;
+        if (__all(!(mm[0] - mm[4] > P.e_floor) && !(mp[0] - mp[4] > P.e_floor))) {
             st(vf + off, t, (S)0.0);
+            st(vf + off + nf, t, (S)0.0);
         } else {
+            qpark[0][tx] = mp[0];
+            qpark[4][tx] = mp[4];
 #pragma unroll
             for (int r = 1; r < 9; ++r)
-                if (r != PTT) m[r] = recon(r);
+                if (r != PTT) {
+                    double x;
+                    recon(r, mm[r], x);
+                    qpark[r][tx] = x;
+                }
             // v^d = u^d / u^tau = M^d / (E + P) (Sec. 2.4), 0 on the floor
-            double ee, pe, EE, M[3];
-            const double Pi = P.bulk ? m[8] : 0.0;
-            fl = invert_core<CART>(P, E, tau, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], Pi,
-                                   (double)ld(e, s0), ee, pe, EE, M, it);
-            const double Md = d == 0 ? M[0] : (d == 1 ? M[1] : M[2]);
-            const double v = (fl & F_FLOOR) ? 0.0 : Md / (EE + pe + Pi);
-            st(vf + off, t, (S)v);
+            auto speed = [&](const double *m, double e0, int &its) -> double {
+                double ee, pe, EE, M[3];
+                const double Pi = P.bulk ? m[8] : 0.0;
+                const int fl = invert_core<CART>(P, E, tau, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7],
+                                                 Pi, e0, ee, pe, EE, M, its);
+                nfb += (fl & F_FALLBACK) ? 1 : 0;
+                const double Md = d == 0 ? M[0] : (d == 1 ? M[1] : M[2]);
+                return (fl & F_FLOOR) ? 0.0 : Md / (EE + pe + Pi);
+            };
+            // (a compiler barrier: the parked values are not carried in registers)
+            asm volatile("" ::: "memory");
+            int it2 = 0;
+            st(vf + off, t, (S)speed(mm, (double)ld(e, cL), it));
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int r = 0; r < 9; ++r) mp[r] = qpark[r][tx];
+            st(vf + off + nf, t, (S)speed(mp, (double)ld(e, cR), it2));
+            it += it2;
         }
     }
-    slot_add(slots, wave, C_ITERS_FACES, it, iter_bits(P));
-    slot_add(slots, wave, C_REC_FACES, valid ? 1 : 0);
-    slot_add(slots, wave, C_FALLBACK_FACES, (fl & F_FALLBACK) ? 1 : 0);
+    slot_add(slots, wave, C_ITERS_FACES, it, iter_bits(P) + 1);
+    slot_add(slots, wave, C_REC_FACES, valid ? 2 : 0, 2);
+    slot_add(slots, wave, C_FALLBACK_FACES, nfb, 2);
 }
 
 template <bool CART, typename S>
@@ -328,8 +346,9 @@ __global__ __launch_bounds__(FACE_BLOCK) __attribute__((amdgpu_waves_per_eu(8)))
                                                           const S *e, S *vf,
                                                           unsigned long long *slots)
 {
+    __shared__ double qpark[9][FACE_BLOCK];
     face_speeds_body<CART, S>(P, E, G, L, tau, qT, qP, e, vf, slots, xcd_block(blockIdx.x, gridDim.x),
-                              (long long)blockIdx.x * (FACE_BLOCK / 64) + (threadIdx.x >> 6));
+                              (long long)blockIdx.x * (FACE_BLOCK / 64) + (threadIdx.x >> 6), qpark);
 }
 
 static FaceLaunch face_launch(const FaceGeo &G, int nx, int ny)
@@ -341,9 +360,9 @@ static FaceLaunch face_launch(const FaceGeo &G, int nx, int ny)
     L.inv_plane = 1.0 / ((double)nx * ny);
     const long long nf[3] = {G.nfx, G.nfy, G.nfe};
     unsigned acc = 0;
-    for (int s = 0; s < 6; ++s) {
+    for (int s = 0; s < 3; ++s) {
         L.first_block[s] = acc;
-        acc += (unsigned)((nf[s >> 1] + FACE_BLOCK - 1) / FACE_BLOCK);
+        acc += (unsigned)((nf[s] + FACE_BLOCK - 1) / FACE_BLOCK);
     }
     L.nblocks = acc;
     return L;
@@ -877,8 +896,9 @@ __global__ __launch_bounds__(FACE_BLOCK) __attribute__((amdgpu_waves_per_eu(8)))
     const BFace<S> &A = tab[ev];
     const unsigned lb = g - first[ev];
     const double tau = tau_dev[0] + A.P.dtau;
+    __shared__ double qpark[9][FACE_BLOCK];
     face_speeds_body<CART, S>(A.P, A.E, A.G, A.L, tau, A.qT, A.qP, A.e, A.vf, A.slots, lb,
-                              (long long)lb * (FACE_BLOCK / 64) + (threadIdx.x >> 6));
+                              (long long)lb * (FACE_BLOCK / 64) + (threadIdx.x >> 6), qpark);
 }
 
 // tau^{n+1} = tau^n + dtau, one thread (part of the captured step)
