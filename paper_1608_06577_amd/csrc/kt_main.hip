@@ -388,6 +388,28 @@ struct NbCell {
 #pragma unroll
         for (int n = 1; n < 4; ++n) pi[n - 1] = (double)ld(F.qP, (idx_t)(pi_index(d + 1, n) - PTT) * SS + s);
     }
+    template <typename Tile>
+    __device__ __forceinline__ void from_tile(const Tile &T, int ty, int tx, int d)
+    {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) u[m] = T.v[m][ty][tx];
+        p = T.v[4][ty][tx];
+        Pi = T.v[5][ty][tx];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) pt[n] = T.v[6 + n][ty][tx];
+#pragma unroll
+        for (int n = 1; n < 4; ++n) pi[n - 1] = T.v[6 + pi_index(d + 1, n) - PTT][ty][tx];
+    }
+};
+
+// The sources kernel's block (64 x 4 cells of one eta plane) with the cells
+// on its four sides, in LDS: tile cell (ty, tx) is the cell at x = x0-1+tx,
+// y = y0-1+ty (indices wrapped as the boundary conditions say; the four
+// corners are not used).  Per cell: u^mu, p, Pi and pi^{tau tau} .. pi^{y eta},
+// i.e. qP components 0..8 (all that the x and y differences need).
+constexpr int SRC_TX = 66, SRC_TY = 6, SRC_NV = 15;
+struct SrcTile {
+    double v[SRC_NV][SRC_TY][SRC_TX];
 };
 
 // A^{i nu} = T^{i nu} - v^i T^{tau nu} of one cell for axis i = d+1 (Eqs. Ttt-Tij):
@@ -418,29 +440,54 @@ __device__ __forceinline__ void nonadvective_row(const Phys &P, double tau, cons
 // J = S_c + G_c for T^{tau mu} and the relaxation terms for pi and Pi.
 // flux_kernel then adds the flux divergence and completes the stage.  Each
 // component is written as soon as its J is known.  J is computed in the
-// storage type S; T^{tau mu} is accumulated in FP64.
+// storage type S; T^{tau mu} is accumulated in FP64.  The x and y neighbours
+// come from the block's LDS tile T (every thread of the block must call this).
 template <bool CART, bool STAGE2, typename S>
 __device__ __forceinline__ void sources_body(const Phys &P, const Eos &E, double tau, const Fields<S> &F,
                                              const double *qnT, const S *qnP, double *outT, S *outP,
-                                             unsigned bx, unsigned by, unsigned bz)
+                                             unsigned bx, unsigned by, unsigned bz, SrcTile &T)
 {
     typedef S R;
-    const int i = bx * 64 + threadIdx.x;
-    const int j = by * 4 + threadIdx.y;
+    const int x0 = bx * 64, y0 = by * 4;
+    const int i = x0 + threadIdx.x;
+    const int j = y0 + threadIdx.y;
     const int k = bz;
-    if (i >= P.nx || j >= P.ny) return;
     const idx_t SS = (idx_t)P.stride;
     const idx_t plane = (idx_t)P.nx * P.ny;
     const idx_t kp = (idx_t)k * plane;
+    // the tile: every thread stages its own cell (threads outside the grid the
+    // cell their index wraps to), and threads 0..135 of the first three waves
+    // the 64 cells below and above the block and the 8 left and right of it
+    {
+        auto stage = [&](int ty, int tx, int gx, int gy) {
+            const idx_t g = kp + (idx_t)wrap(gy, P.ny, P.periodic[1]) * P.nx + wrap(gx, P.nx, P.periodic[0]);
+            double w[SRC_NV];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) w[m] = ld(F.u, (idx_t)m * SS + g);
+            w[4] = (double)ld(F.p, g);
+            w[5] = (double)ld(F.qP, (idx_t)(BPI - PTT) * SS + g);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) w[6 + c] = (double)ld(F.qP, (idx_t)c * SS + g);
+#pragma unroll
+            for (int c = 0; c < SRC_NV; ++c) T.v[c][ty][tx] = w[c];
+        };
+        stage(threadIdx.y + 1, threadIdx.x + 1, i, j);
+        const int h = threadIdx.y * 64 + threadIdx.x;
+        if (h < 64) stage(0, h + 1, x0 + h, y0 - 1);
+        else if (h < 128) stage(5, h - 63, x0 + h - 64, y0 + 4);
+        else if (h < 136) {
+            const int q = h - 128, right = q & 1, r = q >> 1;
+            stage(r + 1, right ? 65 : 0, right ? x0 + 64 : x0 - 1, y0 + r);
+        }
+    }
+    __syncthreads();
+    if (i >= P.nx || j >= P.ny) return;
+    const int tx = threadIdx.x + 1, ty = threadIdx.y + 1;
     const idx_t rowc = kp + (idx_t)j * P.nx;
     const idx_t s = rowc + i;
     const idx_t col = (idx_t)j * P.nx + i;
-    const idx_t nb[3][2] = {
-        {rowc + wrap(i - 1, P.nx, P.periodic[0]), rowc + wrap(i + 1, P.nx, P.periodic[0])},
-        {kp + (idx_t)wrap(j - 1, P.ny, P.periodic[1]) * P.nx + i,
-         kp + (idx_t)wrap(j + 1, P.ny, P.periodic[1]) * P.nx + i},
-        {col + (idx_t)wrap(k - 1, P.neta, P.periodic[2]) * plane,
-         col + (idx_t)wrap(k + 1, P.neta, P.periodic[2]) * plane}};
+    const idx_t nbe[2] = {col + (idx_t)wrap(k - 1, P.neta, P.periodic[2]) * plane,
+                          col + (idx_t)wrap(k + 1, P.neta, P.periodic[2]) * plane};
     const double dt = P.dtau;
     // stage 2: q^n, read before the first store (out is the q^n array itself, so
     // a read placed after a store could not be issued early)
@@ -467,7 +514,7 @@ __device__ __forceinline__ void sources_body(const Phys &P, const Eos &E, double
     R u[4], C[4][4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        const double um = ld(F.u, (idx_t)m * SS + s);
+        const double um = T.v[m][ty][tx];
         u[m] = R(um);
         C[0][m] = R((um - ld(F.up, (idx_t)m * SS + s)) * P.inv_dtau);
     }
@@ -478,8 +525,16 @@ __device__ __forceinline__ void sources_body(const Phys &P, const Eos &E, double
     for (int d = 0; d < 3; ++d) {
         const double hh = 0.5 * invhd[d];
         NbCell<S> Np, Nm;
-        Np.load(F, SS, nb[d][1], d);
-        Nm.load(F, SS, nb[d][0], d);
+        if (d == 0) {
+            Np.from_tile(T, ty, tx + 1, 0);
+            Nm.from_tile(T, ty, tx - 1, 0);
+        } else if (d == 1) {
+            Np.from_tile(T, ty + 1, tx, 1);
+            Nm.from_tile(T, ty - 1, tx, 1);
+        } else {
+            Np.load(F, SS, nbe[1], 2);
+            Nm.load(F, SS, nbe[0], 2);
+        }
 #pragma unroll
         for (int m = 0; m < 4; ++m) C[d + 1][m] = R((Np.u[m] - Nm.u[m]) * hh);
         divv += R((Np.u[d + 1] / Np.u[0] - Nm.u[d + 1] / Nm.u[0]) * hh);
@@ -490,12 +545,13 @@ __device__ __forceinline__ void sources_body(const Phys &P, const Eos &E, double
         for (int n = 0; n < 4; ++n) Sc[n] -= (Ap[n] - Am[n]) * hh;
     }
     const R e = R(ld(F.e, s));
-    const R p0 = R(ld(F.p, s));
-    const R Pim = R(ld(F.qP, (idx_t)(BPI - PTT) * SS + s));
+    const R p0 = R(T.v[4][ty][tx]);
+    const R Pim = R(T.v[5][ty][tx]);
     const R Pi = P.bulk ? Pim : R(0);
     R pv[10];
 #pragma unroll
-    for (int c = 0; c < 10; ++c) pv[c] = R(ld(F.qP, (idx_t)c * SS + s));
+    for (int c = 0; c < 9; ++c) pv[c] = R(T.v[6 + c][ty][tx]);
+    pv[9] = R(ld(F.qP, (idx_t)9 * SS + s));
     // conservation law: geometric source (App. B) G^tau = -(T^tt + tau^2 T^ee)/tau,
     // G^x = -T^tx/tau, G^y = -T^ty/tau, G^eta = -3 T^te/tau, with
     // tau^2 T^ee = tau^2 v^eta (T^te - pi^te) + P + tau^2 pi^ee.
@@ -505,9 +561,9 @@ __device__ __forceinline__ void sources_body(const Phys &P, const Eos &E, double
         for (int n = 0; n < 4; ++n) qt[n] = ld(F.qT, (idx_t)n * SS + s);
         if (!CART) {
             const double inv_tau = 1.0 / tau, t2 = tau * tau;
-            const double ve = ld(F.u, 3 * SS + s) / ld(F.u, s);
+            const double ve = T.v[3][ty][tx] / T.v[0][ty][tx];
             const double pte = P.shear ? (double)pv[PTE - PTT] : 0.0, pee = P.shear ? (double)pv[PEE - PTT] : 0.0;
-            const double t2Tee = t2 * (ve * (qt[TE] - pte) + pee) + ((double)ld(F.p, s) + (double)Pi);
+            const double t2Tee = t2 * (ve * (qt[TE] - pte) + pee) + (T.v[4][ty][tx] + (double)Pi);
             emitT(TT, qt[TT], Sc[0] - (qt[TT] + t2Tee) * inv_tau);
             emitT(TX, qt[TX], Sc[1] - qt[TX] * inv_tau);
             emitT(TY, qt[TY], Sc[2] - qt[TY] * inv_tau);
@@ -533,9 +589,10 @@ __global__ __launch_bounds__(256) void sources_kernel(Phys P, Eos E, double tau,
                                                       const double *qnT, const S *qnP,
                                                       double *outT, S *outP)
 {
+    __shared__ SrcTile T;
     unsigned bx, by, bz;
     xcd_block3(bx, by, bz);
-    sources_body<CART, STAGE2, S>(P, E, tau, F, qnT, qnP, outT, outP, bx, by, bz);
+    sources_body<CART, STAGE2, S>(P, E, tau, F, qnT, qnP, outT, outP, bx, by, bz, T);
 }
 
 // Flux part of one Euler stage: for a 64 x 4 x KC block of cells, the KT
@@ -853,7 +910,8 @@ __global__ __launch_bounds__(256) void sources_batch(const BStage<S> *__restrict
     const unsigned lb = g - first[ev];
     const unsigned bx = lb % A.sgx, by = (lb / A.sgx) % A.sgy, bz = lb / (A.sgx * A.sgy);
     const double tau = STAGE2 ? tau_dev[0] + A.P.dtau : tau_dev[0];
-    sources_body<CART, STAGE2, S>(A.P, A.E, tau, A.F, A.qnT, A.qnP, A.outT, A.outP, bx, by, bz);
+    __shared__ SrcTile T;
+    sources_body<CART, STAGE2, S>(A.P, A.E, tau, A.F, A.qnT, A.qnP, A.outT, A.outP, bx, by, bz, T);
 }
 
 template <bool STAGE2, typename S>
