@@ -39,9 +39,9 @@ KERNEL_VALUES = {"flux": 45.0, "sources": 47.5, "recover": 32.0, "faces": 16.0}
 # WRITE_SIZE x 1.000 (scale factors of a 256 MiB device copy), profiles/kt_step_hotspot128_fp64.md;
 # valid for the kernel sources and compiler flags whose hash is TRAFFIC_SOURCES (else the traffic
 # is reported as null)
-TRAFFIC_SOURCES = "023d7414c86d1521"
-TRAFFIC_BYTES = {"faces": 8.985e8 + 1.079e8, "flux": 0.5 * (1.3674e9 + 1.3710e9) + 2.517e8,
-                 "sources": 0.5 * (9.528e8 + 1.2137e9) + 2.517e8, "recover": 2.706e8 + 3.198e8}
+TRAFFIC_SOURCES = "a73a6d58cb5a3200"
+TRAFFIC_BYTES = {"faces": 6.536e8 + 1.185e8, "flux": 0.5 * (1.3831e9 + 1.3834e9) + 2.517e8,
+                 "sources": 0.5 * (7.465e8 + 1.1015e9) + 2.517e8, "recover": 2.706e8 + 3.201e8}
 KERNEL_NAMES = {"flux": "flux_kernel (KT flux divergence + stage update)",
                 "sources": "sources_kernel (App. B sources + stage update)",
                 "recover": "recover_kernel (Newton inversion + regulator)",

@@ -239,8 +239,10 @@ __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, co
                                                  double (*qpark)[FACE_BLOCK])
 {
     typedef S R;   // reconstruction arithmetic; the inversion itself is FP64
+    // (selects, not an index into L: a run-time index would put L in scratch memory)
     const int d = (b >= L.first_block[1] ? 1 : 0) + (b >= L.first_block[2] ? 1 : 0);
-    const idx_t t = (idx_t)(b - L.first_block[d]) * FACE_BLOCK + threadIdx.x;
+    const unsigned fb = d == 0 ? L.first_block[0] : (d == 1 ? L.first_block[1] : L.first_block[2]);
+    const idx_t t = (idx_t)(b - fb) * FACE_BLOCK + threadIdx.x;
     const long long nf = d == 0 ? G.nfx : (d == 1 ? G.nfy : G.nfe);
     int it = 0, nfb = 0;
     const bool valid = (long long)t < nf;
