@@ -59,6 +59,7 @@ def parse():
                     help="only run a plain device copy of known size (for counter scaling)")
     ap.add_argument("--n", type=int, default=128, help="grid cells per axis")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-events leg")
+    ap.add_argument("--no-lattice", action="store_true", help="skip the lattice-QCD EOS leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start leg")
     ap.add_argument("--learn-steps", type=int, default=3000, help="Adam steps of the start network")
     return ap.parse_args()
@@ -168,6 +169,32 @@ def learned_leg(args, kt, I, torch):
     return out
 
 
+def lattice_leg(args, rec, w, ncell, start, stop):
+    """The headline event and step count in FP64 with the lattice-QCD EOS
+    table (Sec. 2) instead of the synthetic one."""
+    import torch
+    from paper_1608_06577_amd import inputs as I
+    from paper_1608_06577_amd import kt
+
+    eos_l = I.eos_lattice_table()
+    sl = kt.Solver(w.grid, w.config, eos_l, w.prims, device="cuda:0")
+    sl.step(args.warmup)
+    torch.cuda.synchronize()
+    start.record()
+    sl.step(args.steps)
+    stop.record()
+    torch.cuda.synchronize()
+    ms_l = start.elapsed_time(stop) / args.steps
+    obs_l = sl.observables()
+    rec["variants"]["lattice_eos"] = {
+        "ms_per_step": ms_l, "value": ncell / (ms_l * 1e-3), "state": "FP64",
+        "eos": "lattice-QCD trace-anomaly fit, 4096 nodes",
+        "newton_iters_per_cell": obs_l["newton_iters_cells"] / max(1, obs_l["n_recover_cells"]),
+        "n_nan": obs_l["n_nan"]}
+    sl.close()
+    print("bench: lattice-QCD EOS %.3f ms/step" % ms_l, file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -257,6 +284,9 @@ def main():
         "state": "T^{tau mu} FP64; pi, Pi, e, p, u, face speeds FP32; inversion FP64"}}
     sm.close()
     print("bench: mixed precision %.3f ms/step" % ms_m, file=sys.stderr, flush=True)
+    # the same event and step count, FP64, with the lattice-QCD EOS table (Sec. 2)
+    if not args.no_lattice:
+        lattice_leg(args, rec, w, ncell, start, stop)
     if not args.no_batch:
         # 48 hot-spot events on uneven grids, FP32 state, one launch per kernel for all
         # events, one step replayed as a hipGraph, flux tiling autotuned per grid shape

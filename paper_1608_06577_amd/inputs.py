@@ -153,6 +153,86 @@ def eos_conformal_table(n: int = 4096, e_min: float = 1e-6, e_max: float = 1e4,
                p=e / 3.0, cs2=np.full(n, 1.0 / 3.0), T=(e / a_sb) ** 0.25)
 
 
+#: 2+1-flavour lattice-QCD trace anomaly I/T^4 (Wuppertal-Budapest fit of
+#: Sec. 2, Eq. traceAnomaly, with the small alpha > 0 that makes the pressure
+#: approach the Stefan-Boltzmann limit), t = T / 0.2 GeV
+WB_FIT = dict(h0=0.1396, h1=-0.1800, h2=0.0350, f0=2.76, f1=6.79, f2=-5.29, g1=-0.47, g2=1.04,
+              alpha=0.01)
+
+#: Stefan-Boltzmann e = a T^4 of massless quarks and gluons, N_c = 3, N_f = 3 (Sec. 2)
+A_SB_QCD = 3.0 * (2.0 * (3 ** 2 - 1) + 3.5 * 3 * 3) * math.pi ** 2 / 90.0
+
+
+def wb_trace_anomaly(T_gev, h1_sign: float = -1.0):
+    """I(T)/T^4 of the fit (also for complex T, which the derivative uses).
+
+    The exponential factor is exp(h1_sign h1 / t - h2 / t^2).  The equation as
+    printed has h1_sign = +1; with h1 = -0.18 that caps p/T^4 at 0.63 of the
+    Stefan-Boltzmann value, against a text that has the pressure approach it.
+    The default -1 (the cited fit's form) gives 0.87 and a trace-anomaly peak
+    of 4.1 near T = 0.2 GeV.
+    """
+    f = WB_FIT
+    t = np.asarray(T_gev) / 0.2
+    core = (f["h0"] / (1.0 + f["alpha"] * t * t)
+            + f["f0"] * (np.tanh(f["f1"] * t + f["f2"]) + 1.0) / (1.0 + f["g1"] * t + f["g2"] * t * t))
+    return core * np.exp(h1_sign * f["h1"] / t - f["h2"] / (t * t))
+
+
+def eos_lattice_table(n: int = 4096, e_min_gev: float = 1e-7, e_max_gev: float = 1e3,
+                      h1_sign: float = -1.0) -> EOS:
+    """The lattice-QCD EOS (Sec. 2, equation of state for nuclear collisions)
+    as a table on n ln-uniform points of e in [e_min, e_max] GeV/fm^3
+    (h1_sign: see wb_trace_anomaly).
+
+    With P = p/T^4 and phi = I/T^4, dP/d ln T = phi (P vanishes as T -> 0,
+    where phi falls like exp(-h2 / t^2)); e = 3p + I; T(e_i) is the root of
+    ln e(T) = ln e_i; c_s^2 = dp/de = s / (de/dT), s = (e + p)/T and
+    de/dT = 3 s + dI/dT.  Units: e, p in fm^-4, T in fm^-1.
+    """
+    from scipy.integrate import solve_ivp
+    from scipy.optimize import brentq
+    lnT0, lnT1 = math.log(0.004), math.log(20.0)        # GeV; P(4 MeV) < 1e-40
+    sol = solve_ivp(lambda x, P: [float(wb_trace_anomaly(math.exp(x), h1_sign))], (lnT0, lnT1), [0.0],
+                    method="DOP853", rtol=1e-13, atol=1e-300, dense_output=True)
+
+    def P(lnT):
+        return float(sol.sol(lnT)[0])
+
+    def ln_e_gev4(lnT):
+        T = math.exp(lnT)
+        return 4.0 * lnT + math.log(3.0 * P(lnT) + float(wb_trace_anomaly(T, h1_sign)))
+
+    ln_e0 = math.log(e_min_gev / HBARC)
+    dln = (math.log(e_max_gev / HBARC) - ln_e0) / (n - 1)
+    ln_nodes = ln_e0 + dln * np.arange(n) + 4.0 * math.log(HBARC)    # ln e in GeV^4
+    # bracket each node on a grid of ln T, then solve
+    grid = np.linspace(math.log(0.006), lnT1, 4001)
+    lne_grid = np.array([ln_e_gev4(x) for x in grid])
+    if not np.all(np.diff(lne_grid) > 0.0):
+        raise ValueError("e(T) of the lattice fit is not increasing on the table's range")
+    if not (lne_grid[0] < ln_nodes[0] and ln_nodes[-1] < lne_grid[-1]):
+        raise ValueError("table range outside the temperatures covered")
+    k = np.searchsorted(lne_grid, ln_nodes)
+    T = np.empty(n)
+    p = np.empty(n)
+    cs2 = np.empty(n)
+    h = 1e-30
+    for i in range(n):
+        lnT = brentq(lambda x: ln_e_gev4(x) - ln_nodes[i], grid[k[i] - 1], grid[k[i]], xtol=1e-15, rtol=1e-15)
+        Tg = math.exp(lnT)
+        phi = float(wb_trace_anomaly(Tg, h1_sign))
+        dphi_dT = float(np.imag(wb_trace_anomaly(Tg + 1j * h, h1_sign)) / h)    # complex-step derivative
+        pg = P(lnT) * Tg ** 4
+        eg = 3.0 * pg + phi * Tg ** 4
+        s_ = (eg + pg) / Tg
+        dI_dT = 4.0 * Tg ** 3 * phi + Tg ** 4 * dphi_dT
+        T[i] = Tg / HBARC
+        p[i] = pg / HBARC ** 4
+        cs2[i] = s_ / (3.0 * s_ + dI_dT)
+    return EOS(conformal=False, a_sb=A_SB_QCD, ln_e0=ln_e0, dln_e=dln, p=p, cs2=cs2, T=T)
+
+
 # --------------------------------------------------------------------------
 # Grids and primitive containers
 # --------------------------------------------------------------------------

@@ -182,6 +182,18 @@ def test_zero_steps_and_tiny_grids(kt):
             assert errs["q"] < 1e-12 and errs["e"] < 1e-12 and errs["u"] < 1e-12, (nx, ny, ne, errs)
 
 
+def test_tiny_periodic_grids(kt):
+    """Periodic axes shorter than the stencil, a wave's 16-cell rows or a
+    block's 4 rows: indices wrap several times around the grid."""
+    for (nx, ny, ne) in ((1, 1, 1), (3, 2, 1), (5, 3, 2), (17, 6, 3)):
+        g = I.Grid(nx, ny, ne, 0.2, 0.2, 0.2)
+        cfg = I.default_config(eta_s=0.2, zeta_coef=0.1, periodic=(True, True, True))
+        prims = I.random_smooth_fields(g, 1.0, seed=nx * 11 + ny, e_mean=4.0)
+        w = I.Workload("tiny_periodic", g, 1.0, 3, cfg, I.eos_c1_table(), prims)
+        errs, *_ = run_pair(kt, w, 3)
+        assert errs["q"] < 1e-12 and errs["e"] < 1e-12 and errs["u"] < 1e-12, (nx, ny, ne, errs)
+
+
 # ---------------------------------------------------------- full workloads --
 
 def test_gubser_viscous_32cube_100_steps(kt):
@@ -202,6 +214,17 @@ def test_hotspot_small_grid_100_steps(kt):
     errs, gpu, sim, f, r = run_pair(kt, w, 100, report="hotspot56")
     obs = gpu.observables()
     assert obs["n_floor"] > 0 and obs["n_nan"] == 0
+    assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9, errs
+
+
+def test_hotspot_lattice_eos_50_steps(kt):
+    """The hot-spot event with the lattice-QCD EOS table (Sec. 2) on the
+    56x52x24 grid: 50 Heun steps."""
+    w = I.workload_hotspot(nx=56, ny=52, neta=24, dx=0.4, deta=0.5, n_hot=60, seed=3,
+                           eos=I.eos_lattice_table())
+    errs, gpu, sim, f, r = run_pair(kt, w, 50, report="hotspot56_lattice")
+    obs = gpu.observables()
+    assert obs["n_nan"] == 0
     assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9, errs
 
 
