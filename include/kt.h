@@ -65,6 +65,7 @@ typedef enum {
 enum { KT_FP64 = 0, KT_MIXED = 1 };           /* kt_params.precision */
 enum { KT_MILNE = 0, KT_CARTESIAN = 1 };       /* Cartesian: metric diag(1,-1,-1,-1), no geometric sources (Sec. 5.1) */
 enum { KT_BC_OUTFLOW = 0, KT_BC_PERIODIC = 1 };
+enum { KT_ZETA_LINEAR = 0, KT_ZETA_PAPER = 1 }; /* kt_params.zeta_model */
 
 /* Equation of state (Sec. 2.3).  conformal != 0: p = e/3, c_s^2 = 1/3,
  * T = (e/a_sb)^{1/4}.  Otherwise a table on n >= 2 ln-uniform nodes
@@ -89,7 +90,9 @@ typedef struct {
     int32_t bc[3];                 /* per axis x, y, eta: KT_BC_OUTFLOW or KT_BC_PERIODIC */
     double theta;                  /* generalized minmod parameter in [1, 2] (Sec. 3.1) */
     double eta_over_s;             /* eta/s >= 0; 0 = ideal, pi not evolved */
-    double zeta_coef;              /* zeta/s = zeta_coef (1/3 - c_s^2) >= 0; 0 = Pi not evolved */
+    double zeta_coef;              /* >= 0; 0 = Pi not evolved.  KT_ZETA_LINEAR: zeta/s =
+                                    * zeta_coef (1/3 - c_s^2); KT_ZETA_PAPER: zeta_coef is the
+                                    * normalisation of the zeta/s(T) of Sec. 2.2 (Eq. zetas) */
     double taupipi;                /* tau_pipi / tau_pi (10/7 near the conformal limit, Sec. 2.2) */
     int32_t regulate;              /* apply the regulator of Sec. 3.2 */
     int32_t regulate_bulk;         /* the regulator factor also rescales Pi */
@@ -103,6 +106,11 @@ typedef struct {
                                     * FP64; pi, Pi, e, p, u and face speeds stored in FP32, flux
                                     * and source arithmetic in FP32, inversion and regulator in
                                     * FP64 */
+    int32_t zeta_model;            /* KT_ZETA_LINEAR or KT_ZETA_PAPER.  In both, zeta/tau_Pi =
+                                    * 15 (1/3 - c_s^2)^2 (e + P) (Sec. 2.2), so 1/tau_Pi =
+                                    * 15 (1/3 - c_s^2)^2 T / (zeta/s) */
+    double zeta_tc;                /* T_c of KT_ZETA_PAPER (> 0), in the EOS's temperature unit;
+                                    * ignored by KT_ZETA_LINEAR */
 } kt_params;
 
 /* Initial data on the device.  Either q[0..14] (conserved form; all 15

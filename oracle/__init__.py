@@ -41,7 +41,8 @@ class _Params(C.Structure):
                 ("taupipi", C.c_double), ("regulate", C.c_int32), ("xi0", C.c_double),
                 ("rho_max", C.c_double), ("e_floor", C.c_double), ("newton_tol", C.c_double),
                 ("newton_max", C.c_int32), ("regulate_bulk", C.c_int32),
-                ("m2_delta", C.c_double), ("floor_resets_q", C.c_int32)]
+                ("m2_delta", C.c_double), ("floor_resets_q", C.c_int32),
+                ("zeta_model", C.c_int32), ("zeta_tc", C.c_double)]
 
 
 class _EOS(C.Structure):
@@ -72,6 +73,8 @@ def lib():
         L.ora_recover.argtypes = [P, E, C.c_double, C.c_int64, dp, C.c_void_p, dp, dp, ip, ip]
         L.ora_regulate.argtypes = [P, E, C.c_double, C.c_int64, dp, dp, dp, dp]
         L.ora_eos_eval.argtypes = [E, C.c_int64, dp, dp, dp, dp]
+        L.ora_zeta_over_s_paper.argtypes = [C.c_double]
+        L.ora_zeta_over_s_paper.restype = C.c_double
         L.ora_init.argtypes = [P, E, C.c_double, dp, dp, dp, dp]
         L.ora_rhs.argtypes = [P, E, C.c_double, dp, dp, dp, dp, dp]
         L.ora_step.argtypes = [P, E, dp, dp, dp, dp, dp, C.c_int32, C.POINTER(_Stats)]
@@ -123,6 +126,8 @@ class Physics:
     regulate_bulk: bool = True
     m2_delta: float = 1e-3
     floor_resets_q: bool = True
+    zeta_model: int = 0
+    zeta_tc: float = 0.2 / 0.1973269804
 
     @classmethod
     def from_config(cls, grid, cfg: dict):
@@ -136,7 +141,8 @@ class Physics:
                        int(self.cartesian), (C.c_int32 * 3)(*[int(b) for b in self.periodic]),
                        self.theta, self.eta_s, self.zeta_coef, self.taupipi, int(self.regulate),
                        self.xi0, self.rho_max, self.e_floor, self.newton_tol, self.newton_max,
-                       int(self.regulate_bulk), self.m2_delta, int(self.floor_resets_q))
+                       int(self.regulate_bulk), self.m2_delta, int(self.floor_resets_q),
+                       int(self.zeta_model), self.zeta_tc)
 
     @property
     def ncells(self):
@@ -163,6 +169,11 @@ def eos_eval(eos, e):
     p, c2, T = np.empty_like(e), np.empty_like(e), np.empty_like(e)
     lib().ora_eos_eval(C.byref(ref.c), e.size, _dp(e), _dp(p), _dp(c2), _dp(T))
     return p, c2, T
+
+
+def zeta_over_s_paper(x):
+    """The oracle's zeta/s(T / T_c) of Sec. 2.2 (Eq. zetas), elementwise."""
+    return np.array([lib().ora_zeta_over_s_paper(float(v)) for v in np.ravel(x)]).reshape(np.shape(x))
 
 
 def aos_from_prims(prims):

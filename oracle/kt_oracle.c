@@ -78,7 +78,23 @@ typedef struct {
     int32_t regulate_bulk;    /* 1: the regulator factor also rescales Pi */
     double m2_delta;          /* M^2 clamp margin: M2max = (1 - m2_delta) W min(E - e_floor, W) */
     int32_t floor_resets_q;   /* 1: a floored cell's state q is reset to (e_floor,0,0,0; 0; 0) */
+    int32_t zeta_model;       /* 0: zeta/s = zeta_coef (1/3 - c_s^2); 1: zeta_coef times the
+                               * parametrization of Sec. 2.2 (Eq. zetas) at x = T / zeta_tc */
+    double zeta_tc;           /* T_c of zeta_model 1, in the EOS's temperature unit */
 } ora_params;
+
+/* zeta/s of Sec. 2.2 (Eq. zetas, T_c = 200 MeV there), x = T / T_c: a
+ * quadratic around T_c joined to exponential tails towards the QGP (above)
+ * and hadron-gas (below) values.  The printed range of the quadratic branch
+ * is garbled; it is read as 0.995 <= x <= 1.05, between the other two. */
+double ora_zeta_over_s_paper(double x)
+{
+    if (x > 1.05)
+        return 0.9 * exp(-(x - 1.0) / 0.025) + 0.25 * exp(-(x - 1.0) / 0.13) + 0.001;
+    if (x < 0.995)
+        return 0.9 * exp((x - 1.0) / 0.0025) + 0.22 * exp((x - 1.0) / 0.022) + 0.03;
+    return -13.45 + 27.55 * x - 13.77 * x * x;
+}
 
 typedef struct {
     int32_t conformal;        /* 1: p = e/3, T = (e/a)^{1/4} */
@@ -586,7 +602,11 @@ static void cell_sources(ctx_t *C, int i, int j, int k, double J[NQ])
             }
     }
     if (bulk) {
-        const double inv_tPi = 15.0 * d13 * T / P->zeta_coef;
+        /* zeta / tau_Pi = 15 (1/3 - c_s^2)^2 (e + P) in both models, so that
+         * 1/tau_Pi = 15 (1/3 - c_s^2)^2 T / (zeta/s) */
+        const double inv_tPi = P->zeta_model == 1
+            ? 15.0 * d13 * d13 * T / (P->zeta_coef * ora_zeta_over_s_paper(T / P->zeta_tc))
+            : 15.0 * d13 * T / P->zeta_coef;
         const double zeta_tPi = 15.0 * d13 * d13 * (e + p0);
         const double dPiPi = 2.0 / 3.0, lPipi = 8.0 / 5.0 * d13;
         double IPi = dPiPi * Pi * K.theta - lPipi * pis;

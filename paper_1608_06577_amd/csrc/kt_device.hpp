@@ -49,6 +49,8 @@ struct Phys {
     int periodic[3];
     double theta;
     double eta_s, zeta_coef, taupipi;
+    int zeta_model;      // 0: zeta/s = zeta_coef (1/3 - c_s^2); 1: zeta_coef zeta_over_s_paper(T / zeta_tc)
+    double zeta_tc;
     int shear, bulk;
     int regulate, regulate_bulk, floor_reset;
     double xi0, rho_max;
@@ -379,6 +381,18 @@ __device__ __forceinline__ R slope(R qm, R q0, R qp, R theta)
 }
 
 // ------------------------------------------------- relaxation sources ----
+// zeta/s(x), x = T / T_c, of Sec. 2.2 (Eq. zetas): near T_c a parabola, above
+// 1.05 T_c two decaying exponentials over the QGP value 0.001, below 0.995 T_c
+// two over the hadron-gas value 0.03 (the printed range of the parabola is
+// garbled; it lies between the two tails)
+__device__ __forceinline__ double zeta_over_s_paper(double x)
+{
+    const double y = x - 1.0;
+    if (x > 1.05) return 0.9 * exp(-y / 0.025) + 0.25 * exp(-y / 0.13) + 0.001;
+    if (x < 0.995) return 0.9 * exp(y / 0.0025) + 0.22 * exp(y / 0.022) + 0.03;
+    return (-13.77 * x + 27.55) * x - 13.45;
+}
+
 // Right-hand side J of the dissipative components (App. B):
 //   S_pi + G_pi = [2 (eta/tau_pi) sigma - pi/tau_pi - I_pi - G^{mu nu}] / u^tau + pi d_i v^i
 //   S_Pi        = [-(zeta/tau_Pi) theta - Pi/tau_Pi - I_Pi] / u^tau + Pi d_i v^i
@@ -491,7 +505,10 @@ __device__ __forceinline__ void relaxation_sources(const Phys &P, double tau_d, 
     }
     if (P.bulk) {
         const R d = R(1.0 / 3.0) - cs2;
-        const R inv_tPi = R(15) * d * T / R(P.zeta_coef);
+        // zeta / tau_Pi = 15 d^2 (e + P) in both models: 1/tau_Pi = 15 d^2 T / (zeta/s)
+        const R inv_tPi = P.zeta_model == 1
+            ? R(15) * d * d * T / R(P.zeta_coef * zeta_over_s_paper((double)T / P.zeta_tc))
+            : R(15) * d * T / R(P.zeta_coef);
         const R zeta_tPi = R(15) * d * d * (e + p0);
         const R IPi = R(2.0 / 3.0) * Pi * th - R(1.6) * d * pis;
         emit(BPI, Pi, (-zeta_tPi * th - Pi * inv_tPi - IPi) * inv_ut + Pi * divv);

@@ -1379,6 +1379,8 @@ static const char *check_args(const kt_params *p, const kt_eos *eos)
         if (p->bc[d] != KT_BC_OUTFLOW && p->bc[d] != KT_BC_PERIODIC) return "bc must be outflow or periodic";
     if (!(p->theta >= 1.0 && p->theta <= 2.0)) return "theta must lie in [1, 2]";
     if (!(p->eta_over_s >= 0) || !(p->zeta_coef >= 0) || !(p->taupipi >= 0)) return "transport parameters must be >= 0";
+    if (p->zeta_model != KT_ZETA_LINEAR && p->zeta_model != KT_ZETA_PAPER) return "zeta_model must be KT_ZETA_LINEAR or KT_ZETA_PAPER";
+    if (p->zeta_model == KT_ZETA_PAPER && !(p->zeta_tc > 0)) return "zeta_tc must be > 0 for KT_ZETA_PAPER";
     if (p->regulate && (!(p->xi0 > 0) || !(p->rho_max > 0))) return "regulator constants must be > 0";
     if (!(p->e_floor > 0)) return "e_floor must be > 0";
     if (!(p->m2_delta > 0 && p->m2_delta < 1)) return "m2_delta must lie in (0, 1)";
@@ -1404,6 +1406,7 @@ static void fill_phys(const kt_params *p, Phys &P)
     for (int d = 0; d < 3; ++d) P.periodic[d] = p->bc[d] == KT_BC_PERIODIC;
     P.theta = p->theta;
     P.eta_s = p->eta_over_s; P.zeta_coef = p->zeta_coef; P.taupipi = p->taupipi;
+    P.zeta_model = p->zeta_model == KT_ZETA_PAPER ? 1 : 0; P.zeta_tc = p->zeta_tc;
     P.shear = p->eta_over_s > 0; P.bulk = p->zeta_coef > 0;
     P.regulate = p->regulate != 0; P.regulate_bulk = p->regulate_bulk != 0;
     P.floor_reset = p->floor_resets_q != 0;

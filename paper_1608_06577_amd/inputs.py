@@ -563,7 +563,8 @@ def default_config(**kw) -> dict:
     cfg = dict(dtau=0.01, cartesian=False, periodic=(False, False, False), theta=1.0,
                eta_s=0.0, zeta_coef=0.0, taupipi=10.0 / 7.0, regulate=True, xi0=0.1,
                rho_max=1.0, e_floor=E_FLOOR_GEV / HBARC, newton_tol=1e-12, newton_max=50,
-               regulate_bulk=True, m2_delta=1e-3, floor_resets_q=True)
+               regulate_bulk=True, m2_delta=1e-3, floor_resets_q=True,
+               zeta_model=0, zeta_tc=0.2 / HBARC)
     cfg.update(kw)
     return cfg
 

@@ -38,7 +38,8 @@ class KtParams(C.Structure):
                 ("zeta_coef", C.c_double), ("taupipi", C.c_double), ("regulate", C.c_int32),
                 ("regulate_bulk", C.c_int32), ("xi0", C.c_double), ("rho_max", C.c_double),
                 ("e_floor", C.c_double), ("m2_delta", C.c_double), ("floor_resets_q", C.c_int32),
-                ("newton_tol", C.c_double), ("newton_max", C.c_int32), ("precision", C.c_int32)]
+                ("newton_tol", C.c_double), ("newton_max", C.c_int32), ("precision", C.c_int32),
+                ("zeta_model", C.c_int32), ("zeta_tc", C.c_double)]
 
 
 class KtInitState(C.Structure):
@@ -167,7 +168,8 @@ def make_params(grid, config: dict, tau0: float) -> KtParams:
         int(config.get("regulate_bulk", True)), config.get("xi0", 0.1),
         config.get("rho_max", 1.0), config["e_floor"], config.get("m2_delta", 1e-3),
         int(config.get("floor_resets_q", True)), config.get("newton_tol", 1e-12),
-        int(config.get("newton_max", 50)), KT_MIXED if config.get("mixed", False) else KT_FP64)
+        int(config.get("newton_max", 50)), KT_MIXED if config.get("mixed", False) else KT_FP64,
+        int(config.get("zeta_model", 0)), config.get("zeta_tc", 0.2 / 0.1973269804))
 
 
 class EosHost:

@@ -228,6 +228,23 @@ def test_hotspot_lattice_eos_50_steps(kt):
     assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9, errs
 
 
+def test_hotspot_lattice_eos_zeta_of_T_50_steps(kt):
+    """The paper's bulk viscosity zeta/s(T) (Sec. 2.2, Eq. zetas, normalisation
+    1, T_c = 200 MeV) with the lattice-QCD EOS, hot-spot event 56x52x24,
+    50 Heun steps."""
+    w = I.workload_hotspot(nx=56, ny=52, neta=24, dx=0.4, deta=0.5, n_hot=60, seed=3,
+                           eos=I.eos_lattice_table())
+    cfg = dict(w.config, zeta_model=1, zeta_coef=1.0)
+    w = I.Workload(w.name, w.grid, w.tau0, w.n_steps, cfg, w.eos, w.prims)
+    errs, gpu, sim, f, r = run_pair(kt, w, 50, report="hotspot56_lattice_zetaT")
+    obs = gpu.observables()
+    assert obs["n_nan"] == 0
+    assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9, errs
+    # the bulk pressure differs from the linear model's run
+    Pi = f["q"].reshape(15, -1)[14]
+    assert np.max(np.abs(Pi)) > 0
+
+
 def test_hotspot_128_against_oracle_samples(kt):
     """The full 128^3 event: GPU fields after 50/100/200 steps against oracle
     samples written by tests/golden/make_hotspot_golden.py.  The FP64 bar
