@@ -70,7 +70,7 @@ def sod_exact(x, t, eL: float, eR: float):
 # Bjorken flow ODEs (Secs. 5.4 and 5.5), pi = -tau^2 pi^{eta eta}
 # --------------------------------------------------------------------------
 
-def bjorken_rhs(tau, e, pi, Pi, eos_fn, eta_s, zeta_coef, taupipi):
+def bjorken_rhs(tau, e, pi, Pi, eos_fn, eta_s, zeta_coef, taupipi, zeta_fn=None):
     """Right-hand sides of the 0+1d equations of Secs. 5.4/5.5.
 
     de/dtau  = -(e + P0 + Pi - pi)/tau
@@ -78,8 +78,10 @@ def bjorken_rhs(tau, e, pi, Pi, eos_fn, eta_s, zeta_coef, taupipi):
     tau_pi dpi/dtau + pi = (4/3) eta/tau - (tau_pipi/3 + delta_pipi) pi/tau
                            + (2/3) lambda_piPi Pi/tau
     with the coefficients of Sec. 2.2 (eta = (eta/s) s, s = (e+P0)/T,
-    tau_pi = 5 (eta/s)/T, zeta/s = zeta_coef (1/3 - c_s^2)).  Returned as
-    (de, dpi, dPi); the relaxation equations are divided by their times.
+    tau_pi = 5 (eta/s)/T, zeta/s = zeta_coef (1/3 - c_s^2), or zeta_coef
+    zeta_fn(T) when zeta_fn is given; zeta/tau_Pi = 15 (1/3 - c_s^2)^2 (e+P0)).
+    Returned as (de, dpi, dPi); the relaxation equations are divided by their
+    times.
     """
     P0, cs2, T = eos_fn(e)
     de = -(e + P0 + Pi - pi) / tau
@@ -92,18 +94,21 @@ def bjorken_rhs(tau, e, pi, Pi, eos_fn, eta_s, zeta_coef, taupipi):
             + (2.0 / 3.0) * (6.0 / 5.0) * Pi / tau
     if zeta_coef > 0:
         d = 1.0 / 3.0 - cs2
-        inv_tPi = 15.0 * d * T / zeta_coef
         zeta_tPi = 15.0 * d * d * (e + P0)
+        if zeta_fn is None:
+            inv_tPi = 15.0 * d * T / zeta_coef
+        else:
+            inv_tPi = 15.0 * d * d * T / (zeta_coef * zeta_fn(T))
         dPi = -zeta_tPi / tau - Pi * inv_tPi - (2.0 / 3.0) * Pi / tau + (8.0 / 5.0) * d * pi / tau
     return de, dpi, dPi
 
 
 def bjorken_ode_solution(tau0, tau1, e0, pi0, Pi0, eos_fn, eta_s, zeta_coef, taupipi,
-                         t_eval=None):
+                         t_eval=None, zeta_fn=None):
     from scipy.integrate import solve_ivp
 
     def f(t, y):
-        return list(bjorken_rhs(t, y[0], y[1], y[2], eos_fn, eta_s, zeta_coef, taupipi))
+        return list(bjorken_rhs(t, y[0], y[1], y[2], eos_fn, eta_s, zeta_coef, taupipi, zeta_fn))
 
     sol = solve_ivp(f, (tau0, tau1), [e0, pi0, Pi0], method="DOP853", rtol=1e-12,
                     atol=1e-14, t_eval=t_eval, dense_output=False)

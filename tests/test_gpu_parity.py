@@ -245,6 +245,24 @@ def test_hotspot_lattice_eos_zeta_of_T_50_steps(kt):
     assert np.max(np.abs(Pi)) > 0
 
 
+def test_bjorken_lattice_eos_zeta_of_T_2plus1d(kt):
+    """The non-conformal Bjorken test of Sec. 5.5 (lattice-QCD EOS, zeta/s(T),
+    T0 = 0.6 GeV at tau0 = 0.25 fm) on a 2+1d grid (one eta cell), 200 steps."""
+    from tests.test_oracle_flows import e_of_T
+    eos = I.eos_lattice_table()
+    tau0, tc = 0.25, 0.2 / I.HBARC
+    e0 = e_of_T(eos, 0.6 / I.HBARC)
+    P0, _, T0 = (a[0] for a in oracle.eos_eval(eos, np.array([e0])))
+    g = I.Grid(20, 12, 1, 0.1, 0.1, 0.1)
+    cfg = I.default_config(dtau=0.01, periodic=(True, True, False), eta_s=0.2, zeta_coef=1.0,
+                           zeta_model=1, zeta_tc=tc)
+    prims = I.bjorken_fields(g, tau0, e0, T0, 0.2, P0)
+    w = I.Workload("bjorken_lattice", g, tau0, 200, cfg, eos, prims)
+    errs, gpu, sim, f, r = run_pair(kt, w, 200, report="bjorken_lattice_2+1d")
+    assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9, errs
+    assert abs(f["q"][14].reshape(-1)[0] - r["q"][14].reshape(-1)[0]) <= 1e-9 * abs(r["q"][14].reshape(-1)[0])
+
+
 def test_hotspot_128_against_oracle_samples(kt):
     """The full 128^3 event: GPU fields after 50/100/200 steps against oracle
     samples written by tests/golden/make_hotspot_golden.py.  The FP64 bar

@@ -130,6 +130,64 @@ def test_bjorken_bulk_nonconformal(oracle_lib):
     assert 3.0 < errs[0] / errs[1] < 5.0
 
 
+def e_of_T(eos, T_fm):
+    """e with T(e) = T_fm on the table (bisection in ln e)."""
+    lo, hi = eos.ln_e0, eos.ln_e0 + eos.dln_e * (eos.n - 1)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if oracle.eos_eval(eos, np.array([math.exp(mid)]))[2][0] < T_fm:
+            lo = mid
+        else:
+            hi = mid
+    return math.exp(0.5 * (lo + hi))
+
+
+def test_bjorken_lattice_eos_zeta_of_T_2plus1d(oracle_lib):
+    """The paper's non-conformal Bjorken test (Sec. 5.5): lattice-QCD EOS,
+    zeta/s(T) of Eq. zetas, eta/s = 0.2, T0 = 0.6 GeV at tau0 = 0.25 fm, pi at
+    its Navier-Stokes value, Pi0 = 0, on a grid with one eta cell (the 2+1d,
+    boost-invariant mode).  The grid converges to the 0+1d equations at
+    O(dtau^2).  Pi first turns positive through the bulk-shear coupling; with
+    these coefficients the Navier-Stokes term takes over near tau = 0.9 fm."""
+    eos = I.eos_lattice_table()
+    fn = table_eos_fn(eos)
+    tau0, eta_s, tc = 0.25, 0.2, 0.2 / I.HBARC
+    T0 = 0.6 / I.HBARC
+    e0 = e_of_T(eos, T0)
+    P0 = fn(e0)[0]
+    grid = I.Grid(2, 2, 1, 0.1, 0.1, 0.1)
+    zf = lambda T: float(oracle.zeta_over_s_paper(T / tc))
+    errs = []
+    for dtau, n in ((0.02, 100), (0.01, 200)):
+        cfg = I.default_config(dtau=dtau, periodic=(True, True, False), eta_s=eta_s, zeta_coef=1.0,
+                               zeta_model=1, zeta_tc=tc, regulate=False, e_floor=1e-12)
+        prims = I.bjorken_fields(grid, tau0, e0, fn(e0)[2], eta_s, P0)
+        sim = make_sim(grid, cfg, eos, prims)
+        pi0 = -tau0 ** 2 * prims.pi[9].flat[0]
+        sim.step(n)
+        f = sim.fields()
+        tau = tau0 + n * dtau
+        sol = A.bjorken_ode_solution(tau0, tau, e0, pi0, 0.0, fn, eta_s, 1.0, 10 / 7, t_eval=[tau],
+                                     zeta_fn=zf)
+        e_num, Pi_num = f["e"].flat[0], f["q"][14].flat[0]
+        pi_num = -tau ** 2 * f["q"][13].flat[0]
+        e_ode, pi_ode, Pi_ode = sol.y[0, -1], sol.y[1, -1], sol.y[2, -1]
+        assert np.allclose(f["e"], e_num, rtol=1e-13, atol=0)      # homogeneous
+        errs.append((abs(e_num / e_ode - 1), abs(pi_num / pi_ode - 1), abs(Pi_num - Pi_ode) / abs(Pi_ode)))
+        assert Pi_num < 0 and Pi_ode < 0
+    for k in range(3):
+        assert errs[1][k] < 2e-3 and 2.5 < errs[0][k] / errs[1][k] < 5.5, errs
+    # early times: Pi > 0, led by lambda_Pipi pi / tau
+    cfg = I.default_config(dtau=0.005, periodic=(True, True, False), eta_s=eta_s, zeta_coef=1.0,
+                           zeta_model=1, zeta_tc=tc, regulate=False, e_floor=1e-12)
+    sim = make_sim(grid, cfg, eos, I.bjorken_fields(grid, tau0, e0, fn(e0)[2], eta_s, P0))
+    sim.step(50)
+    sol = A.bjorken_ode_solution(tau0, sim.tau, e0, pi0, 0.0, fn, eta_s, 1.0, 10 / 7, t_eval=[sim.tau],
+                                 zeta_fn=zf)
+    Pi_num = sim.fields()["q"][14].flat[0]
+    assert Pi_num > 0 and abs(Pi_num / sol.y[2, -1] - 1) < 1e-2
+
+
 # ------------------------------------------------------------ conservation ---
 
 @pytest.mark.parametrize("viscous", [False, True])
