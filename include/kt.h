@@ -256,6 +256,24 @@ kt_status kt_mlp_adam(kt_ctx *c, const float *grad, float lr, float b1, float b2
  * of the current fields into the given device arrays.  Synchronises. */
 kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out);
 
+/* Validity of the effective theory (Sec. 7, Eq. inverseReynoldsNumbers) on
+ * the current state, per cell into caller-owned device arrays of nx*ny*neta
+ * doubles (x fastest, eta slowest; each nullable): the temperature T(e), the
+ * shear inverse Reynolds number sqrt(pi^{mu nu} pi_{mu nu}) / P(e) and the
+ * bulk one |Pi| / P(e), P the equilibrium pressure of the EOS.  Asynchronous
+ * on the context's stream; KT_E_HIP if the launch fails. */
+kt_status kt_validity(kt_ctx *c, double *T_out, double *rinv_pi, double *rinv_Pi);
+
+/* Runs Heun steps until the hottest cell is below T_f (the freeze-out
+ * temperature, 155 MeV in Sec. 7, in the EOS's temperature unit) or
+ * max_steps steps are done, checking kt_obs.T_max every check_every steps
+ * (and before the first).  *steps_done receives the steps taken (0 if the
+ * state is already below T_f).  KT_E_ARG for T_f <= 0, max_steps < 0,
+ * check_every < 1 or a null steps_done; errors of kt_step and
+ * kt_observables are passed on.  Synchronises at every check. */
+kt_status kt_run_to_freezeout(kt_ctx *c, double T_f, int32_t max_steps, int32_t check_every,
+                              int32_t *steps_done);
+
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * the launches of kt_step.  Kernel classes: 0 = KT flux divergence and
  * stage update, 1 = cell recovery and regulator, 2 = inversion of the

@@ -171,6 +171,24 @@ def eos_eval(eos, e):
     return p, c2, T
 
 
+def validity_maps(eos, tau, cartesian, e, pi, Pi):
+    """Sec. 7 (Eq. inverseReynoldsNumbers): T(e), sqrt(pi^{mu nu} pi_{mu nu})/P(e)
+    and |Pi|/P(e) per cell.  pi: the ten contravariant components in the order
+    tt, tx, ty, te, xx, xy, xe, yy, ye, ee (leading axis); both indices are
+    lowered with diag(1, -1, -1, -tau^2) (Milne) or diag(1, -1, -1, -1)."""
+    e = np.asarray(e, dtype=np.float64)
+    p, _, T = eos_eval(eos, e)
+    p, T = p.reshape(e.shape), T.reshape(e.shape)
+    g = np.array([1.0, -1.0, -1.0, -1.0 if cartesian else -tau * tau])
+    full = np.zeros((4, 4) + e.shape)
+    pairs = [(0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (1, 3), (2, 2), (2, 3), (3, 3)]
+    for k, (m, n) in enumerate(pairs):
+        full[m, n] = pi[k]
+        full[n, m] = pi[k]
+    pp = np.einsum("m,n,mn...,mn...->...", g, g, full, full)
+    return T, np.sqrt(np.maximum(pp, 0.0)) / p, np.abs(np.asarray(Pi)) / p
+
+
 def zeta_over_s_paper(x):
     """The oracle's zeta/s(T / T_c) of Sec. 2.2 (Eq. zetas), elementwise."""
     return np.array([lib().ora_zeta_over_s_paper(float(v)) for v in np.ravel(x)]).reshape(np.shape(x))

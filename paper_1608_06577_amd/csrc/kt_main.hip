@@ -1213,6 +1213,37 @@ constexpr int OBS_BLOCKS = 512;
 
 }  // namespace
 
+// Validity of the effective theory (Sec. 7, Eq. inverseReynoldsNumbers), per
+// cell: T(e), R^{-1}_pi = sqrt(pi^{mu nu} pi_{mu nu}) / P(e) and
+// R^{-1}_Pi = |Pi| / P(e), with the metric diag(1, -1, -1, -tau^2) (Milne) or
+// diag(1, -1, -1, -1) (Cartesian) lowering both indices.  Each output is
+// nullable.
+template <bool CART, typename S>
+__global__ __launch_bounds__(256) void validity_kernel(Phys P, Eos E, double tau, const S *qP, const S *e,
+                                                       double *T_out, double *rpi, double *rPi)
+{
+    const idx_t SS = (idx_t)P.stride;
+    const double w3 = CART ? -1.0 : -tau * tau;
+    const double w[4] = {1.0, -1.0, -1.0, w3};
+    for (idx_t i = (idx_t)blockIdx.x * blockDim.x + threadIdx.x; i < (idx_t)P.ncell;
+         i += (idx_t)gridDim.x * blockDim.x) {
+        double pe, cs2, T;
+        eos_full(E, (double)e[i], pe, cs2, T);
+        double pp = 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = m; n < 4; ++n) {
+                const double v = (double)qP[(idx_t)(pi_index(m, n) - PTT) * SS + i];
+                pp += (m == n ? 1.0 : 2.0) * w[m] * w[n] * v * v;
+            }
+        const double Pi = (double)qP[(idx_t)(BPI - PTT) * SS + i];
+        if (T_out) T_out[i] = T;
+        if (rpi) rpi[i] = sqrt(fmax(pp, 0.0)) / pe;
+        if (rPi) rPi[i] = fabs(Pi) / pe;
+    }
+}
+
 // ======================================================================
 // Host side
 // ======================================================================
@@ -1834,6 +1865,49 @@ kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out)
         host_out->n_fallback_faces = (int64_t)ctr[C_FALLBACK_FACES];
     }
     return KT_OK;
+}
+
+kt_status kt_validity(kt_ctx *c, double *T_out, double *rinv_pi, double *rinv_Pi)
+{
+    if (!c) return fail(nullptr, KT_E_ARG, "null context");
+    if (!T_out && !rinv_pi && !rinv_Pi) return KT_OK;
+    const bool cart = c->prm.coords == KT_CARTESIAN;
+    const long long n = c->P.ncell;
+    const dim3 g((unsigned)std::min<long long>((n + 255) / 256, 8192)), b(256);
+    hipError_t e;
+    if (c->mixed)
+        e = cart ? launch(validity_kernel<true, float>, g, b, c->stream, c->P, c->E, c->tau, (const float *)c->qP[0],
+                          (const float *)c->e, T_out, rinv_pi, rinv_Pi)
+                 : launch(validity_kernel<false, float>, g, b, c->stream, c->P, c->E, c->tau, (const float *)c->qP[0],
+                          (const float *)c->e, T_out, rinv_pi, rinv_Pi);
+    else
+        e = cart ? launch(validity_kernel<true, double>, g, b, c->stream, c->P, c->E, c->tau, (const double *)c->qP[0],
+                          (const double *)c->e, T_out, rinv_pi, rinv_Pi)
+                 : launch(validity_kernel<false, double>, g, b, c->stream, c->P, c->E, c->tau, (const double *)c->qP[0],
+                          (const double *)c->e, T_out, rinv_pi, rinv_Pi);
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "validity: %s", hipGetErrorString(e));
+    return KT_OK;
+}
+
+kt_status kt_run_to_freezeout(kt_ctx *c, double T_f, int32_t max_steps, int32_t check_every,
+                              int32_t *steps_done)
+{
+    if (!c) return fail(nullptr, KT_E_ARG, "null context");
+    if (!steps_done) return fail(c, KT_E_ARG, "steps_done is null");
+    *steps_done = 0;
+    if (!(T_f > 0) || max_steps < 0 || check_every < 1)
+        return fail(c, KT_E_ARG, "need T_f > 0, max_steps >= 0, check_every >= 1");
+    kt_obs o;
+    kt_status st = kt_observables(c, &o, nullptr);
+    while (st == KT_OK && o.T_max >= T_f && *steps_done < max_steps) {
+        const int32_t k = std::min(check_every, max_steps - *steps_done);
+        st = kt_step(c, k);
+        if (st == KT_OK) {
+            *steps_done += k;
+            st = kt_observables(c, &o, nullptr);
+        }
+    }
+    return st;
 }
 
 kt_status kt_set_inv_start(kt_ctx *c, int32_t start)

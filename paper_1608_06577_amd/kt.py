@@ -84,6 +84,7 @@ _lib = None
 
 #: every function the C ABI exports (the names declared in include/kt.h)
 EXPORTS = ("kt_workspace_bytes", "kt_init", "kt_step", "kt_recover", "kt_observables",
+           "kt_validity", "kt_run_to_freezeout",
            "kt_profile_enable", "kt_profile_read", "kt_destroy", "kt_last_error",
            "kt_status_string", "kt_set_inv_start", "kt_mlp_set", "kt_mlp_get", "kt_mlp_features",
            "kt_mlp_fwd", "kt_mlp_loss", "kt_mlp_bwd", "kt_mlp_adam", "kt_batch_workspace_bytes",
@@ -113,6 +114,9 @@ def lib():
         L.kt_recover.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p * 9, C.c_void_p,
                                  C.c_void_p * 4, C.c_void_p, C.c_void_p]
         L.kt_observables.argtypes = [C.c_void_p, C.POINTER(KtObs), C.POINTER(KtFields)]
+        L.kt_validity.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.kt_run_to_freezeout.argtypes = [C.c_void_p, C.c_double, C.c_int32, C.c_int32,
+                                          C.POINTER(C.c_int32)]
         L.kt_destroy.argtypes = [C.c_void_p]
         L.kt_destroy.restype = None
         L.kt_last_error.argtypes = [C.c_void_p]
@@ -142,6 +146,8 @@ def lib():
         L.kt_batch_last_error.argtypes = [vp]
         L.kt_batch_last_error.restype = C.c_char_p
         for f in ("kt_batch_init", "kt_batch_step", "kt_batch_tune", "kt_batch_observables"):
+            getattr(L, f).restype = C.c_int
+        for f in ("kt_validity", "kt_run_to_freezeout"):
             getattr(L, f).restype = C.c_int
         for f in ("kt_init", "kt_step", "kt_recover", "kt_observables", "kt_profile_enable",
                   "kt_profile_read", "kt_set_inv_start", "kt_mlp_set", "kt_mlp_get",
@@ -273,6 +279,24 @@ class Solver:
         o = KtObs()
         _check(lib().kt_observables(self.ctx, C.byref(o), None), self.ctx)
         return o.as_dict()
+
+    def validity(self) -> dict:
+        """T, R^{-1}_pi and R^{-1}_Pi per cell (Sec. 7), as (neta, ny, nx) tensors."""
+        torch = self.torch
+        with torch.cuda.device(self.device):
+            out = {k: torch.empty(self.grid.shape, dtype=torch.float64, device=self.device)
+                   for k in ("T", "rinv_pi", "rinv_Pi")}
+            _check(lib().kt_validity(self.ctx, out["T"].data_ptr(), out["rinv_pi"].data_ptr(),
+                                     out["rinv_Pi"].data_ptr()), self.ctx)
+            torch.cuda.synchronize(self.device)
+        return out
+
+    def run_to_freezeout(self, T_f: float, max_steps: int, check_every: int = 10) -> int:
+        """Steps until max T < T_f (checked every check_every steps); returns the steps taken."""
+        n = C.c_int32(0)
+        _check(lib().kt_run_to_freezeout(self.ctx, float(T_f), int(max_steps), int(check_every),
+                                         C.byref(n)), self.ctx)
+        return n.value
 
     def fields(self, which=("e", "u", "q", "u_prev")) -> dict:
         torch = self.torch

@@ -263,6 +263,47 @@ def test_bjorken_lattice_eos_zeta_of_T_2plus1d(kt):
     assert abs(f["q"][14].reshape(-1)[0] - r["q"][14].reshape(-1)[0]) <= 1e-9 * abs(r["q"][14].reshape(-1)[0])
 
 
+def test_validity_maps_match_oracle(kt):
+    """T, R^{-1}_pi and R^{-1}_Pi per cell (Sec. 7) after 20 steps of the
+    viscous hot-spot event (FP64), against the oracle's maps of its own state."""
+    w = I.workload_hotspot(nx=40, ny=36, neta=12, dx=0.4, deta=0.5, n_hot=40, seed=4)
+    errs, gpu, sim, f, r = run_pair(kt, w, 20)
+    assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9, errs
+    m = {k: v.cpu().numpy() for k, v in gpu.validity().items()}
+    T, rpi, rPi = oracle.validity_maps(w.eos, sim.tau, False, r["e"], r["q"][4:14], r["q"][14])
+    dense = r["e"] > 1e-3 * r["e"].max()
+    assert np.max(np.abs(m["T"] - T) / T) <= 1e-9
+    for got, ref in ((m["rinv_pi"], rpi), (m["rinv_Pi"], rPi)):
+        assert np.max(np.abs(got - ref)[dense]) <= 1e-9 * np.max(np.abs(ref[dense]))
+        assert np.all(np.isfinite(got))
+    assert np.max(rpi[dense]) > 0 and np.max(rPi[dense]) > 0
+
+
+def test_run_to_freezeout_matches_oracle_loop(kt):
+    """kt_run_to_freezeout stops after the same number of steps as the same
+    loop over the oracle (max T checked every 5 steps), with equal fields."""
+    w = I.workload_hotspot(nx=40, ny=36, neta=12, dx=0.4, deta=0.5, n_hot=40, seed=4)
+    phys = oracle.Physics.from_config(w.grid, w.config)
+    sim = oracle.Simulation.from_primitives(phys, w.eos, w.prims)
+
+    def tmax():
+        return oracle.eos_eval(w.eos, np.array([sim.fields()["e"].max()]))[2][0]
+
+    T_f = 0.93 * tmax()
+    n_ref = 0
+    while tmax() >= T_f and n_ref < 300:
+        sim.step(5)
+        n_ref += 5
+    gpu = kt.Solver(w.grid, w.config, w.eos, w.prims)
+    n = gpu.run_to_freezeout(T_f, 300, 5)
+    assert 0 < n == n_ref < 300
+    assert gpu.observables()["T_max"] < T_f
+    f = {k: v.cpu().numpy() for k, v in gpu.fields().items()}
+    r = sim.fields()
+    assert e_err(f["e"], r["e"]) <= 1e-9 and u_err(f["u"], r["u"], sim.tau) <= 1e-9
+    assert gpu.run_to_freezeout(T_f, 300, 5) == 0      # already below T_f
+
+
 def test_hotspot_128_against_oracle_samples(kt):
     """The full 128^3 event: GPU fields after 50/100/200 steps against oracle
     samples written by tests/golden/make_hotspot_golden.py.  The FP64 bar

@@ -51,3 +51,38 @@ def test_bulk_relaxation_rate_uses_the_model():
         rate = 15.0 * d * d * T[0] / zs
         dPi = np.asarray(J).reshape(-1, 15)[:, 14] if np.ndim(J) == 2 else np.asarray(J)[14::15]
         assert np.allclose(dPi, -Pi0 * rate, rtol=1e-12, atol=0), (model, norm, dPi[:3], -Pi0 * rate)
+
+
+def test_inverse_reynolds_numbers_closed_forms():
+    """Sec. 7: a Navier-Stokes Bjorken state has pi^{xx} = pi^{yy} = pi_s/2,
+    tau^2 pi^{eta eta} = -pi_s, so sqrt(pi:pi) = sqrt(3/2) pi_s; and pi:pi is
+    a Lorentz scalar (unchanged by a boost of the tensor)."""
+    eos = I.eos_c1_table(n=512)
+    tau, e, pis, Pi = 1.7, np.array([3.0, 11.0]), np.array([0.4, 1.3]), np.array([-0.05, 0.2])
+    pi = np.zeros((10, 2))
+    pi[4] = pi[7] = 0.5 * pis
+    pi[9] = -pis / tau ** 2
+    T, rpi, rPi = oracle.validity_maps(eos, tau, False, e, pi, Pi)
+    p, _, T_ref = oracle.eos_eval(eos, e)
+    assert np.allclose(rpi, np.sqrt(1.5) * pis / p, rtol=1e-14, atol=0)
+    assert np.allclose(rPi, np.abs(Pi) / p, rtol=1e-15, atol=0) and np.array_equal(T, T_ref)
+    # boost invariance (Cartesian metric)
+    rng = np.random.default_rng(3)
+    a = rng.normal(size=(3, 3))
+    full = np.zeros((4, 4))
+    full[1:, 1:] = a + a.T          # rest-frame tensor: pi:pi = sum of squares > 0
+    y = 0.7
+    L = np.eye(4)
+    L[0, 0] = L[1, 1] = np.cosh(y)
+    L[0, 1] = L[1, 0] = np.sinh(y)
+    boosted = L @ full @ L.T
+    pack = lambda M: np.array([M[m, n] for (m, n) in ((0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2),
+                                                      (1, 3), (2, 2), (2, 3), (3, 3))])[:, None]
+    g = np.diag([1.0, -1.0, -1.0, -1.0])
+    pp = np.trace(g @ full @ g @ full.T)
+    r0 = oracle.validity_maps(eos, 1.0, True, np.array([5.0]), pack(full), np.array([0.0]))[1]
+    r1 = oracle.validity_maps(eos, 1.0, True, np.array([5.0]), pack(boosted), np.array([0.0]))[1]
+    p5 = oracle.eos_eval(eos, np.array([5.0]))[0][0]
+    assert pp > 0 and abs(r0[0] - np.sqrt(pp) / p5) <= 1e-12 * r0[0]
+    assert not np.allclose(pack(boosted)[:4], 0.0)      # the boost mixes in tau components
+    assert abs(r0[0] - r1[0]) <= 1e-11 * r0[0]
