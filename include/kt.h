@@ -256,13 +256,17 @@ kt_status kt_mlp_adam(kt_ctx *c, const float *grad, float lr, float b1, float b2
  * of the current fields into the given device arrays.  Synchronises. */
 kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out);
 
-/* Validity of the effective theory (Sec. 7, Eq. inverseReynoldsNumbers) on
- * the current state, per cell into caller-owned device arrays of nx*ny*neta
- * doubles (x fastest, eta slowest; each nullable): the temperature T(e), the
- * shear inverse Reynolds number sqrt(pi^{mu nu} pi_{mu nu}) / P(e) and the
- * bulk one |Pi| / P(e), P the equilibrium pressure of the EOS.  Asynchronous
- * on the context's stream; KT_E_HIP if the launch fails. */
-kt_status kt_validity(kt_ctx *c, double *T_out, double *rinv_pi, double *rinv_Pi);
+/* Validity of the effective theory (Sec. 7) on the current state, per cell
+ * into caller-owned device arrays of nx*ny*neta doubles (x fastest, eta
+ * slowest; each nullable): the temperature T(e); the inverse Reynolds numbers
+ * of Eq. inverseReynoldsNumbers, sqrt(pi^{mu nu} pi_{mu nu}) / P(e) and
+ * |Pi| / P(e), P the equilibrium pressure of the EOS; the Knudsen numbers
+ * tau_pi theta and tau_Pi theta (signed; 0 where pi or Pi is not evolved),
+ * theta = d_mu u^mu + u^tau/tau (Milne) from a backward difference in tau
+ * against the previous step's u and central differences in x, y, eta.
+ * Asynchronous on the context's stream; KT_E_HIP if a launch fails. */
+kt_status kt_validity(kt_ctx *c, double *T_out, double *rinv_pi, double *rinv_Pi, double *kn_pi,
+                      double *kn_Pi);
 
 /* Runs Heun steps until the hottest cell is below T_f (the freeze-out
  * temperature, 155 MeV in Sec. 7, in the EOS's temperature unit) or

@@ -1244,6 +1244,48 @@ __global__ __launch_bounds__(256) void validity_kernel(Phys P, Eos E, double tau
     }
 }
 
+// Knudsen numbers of Sec. 7, per cell: Kn_pi = tau_pi theta and
+// Kn_Pi = tau_Pi theta, theta = d_mu u^mu + u^tau / tau (Milne) from the same
+// differences as the sources kernel (backward in tau from u_prev, central in
+// x, y, eta with the boundary conditions), tau_pi = 5 (eta/s) / T and
+// 1/tau_Pi as in relaxation_sources; 0 for a component that is not evolved.
+template <bool CART, typename S>
+__global__ __launch_bounds__(256) void knudsen_kernel(Phys P, Eos E, double tau, const double *u, const double *up,
+                                                      const S *e, double *knpi, double *knPi)
+{
+    const idx_t SS = (idx_t)P.stride;
+    const idx_t plane = (idx_t)P.nx * P.ny;
+    for (idx_t c = (idx_t)blockIdx.x * blockDim.x + threadIdx.x; c < (idx_t)P.ncell;
+         c += (idx_t)gridDim.x * blockDim.x) {
+        const int k = (int)(c / plane);
+        const idx_t rem = c - (idx_t)k * plane;
+        const int j = (int)(rem / P.nx), i = (int)(rem - (idx_t)j * P.nx);
+        const idx_t row = (idx_t)k * plane + (idx_t)j * P.nx, col = (idx_t)j * P.nx + i;
+        double th = (u[c] - up[c]) * P.inv_dtau;
+        th += (u[SS + row + wrap(i + 1, P.nx, P.periodic[0])] - u[SS + row + wrap(i - 1, P.nx, P.periodic[0])])
+              * (0.5 * P.inv_dx);
+        th += (u[2 * SS + (idx_t)k * plane + (idx_t)wrap(j + 1, P.ny, P.periodic[1]) * P.nx + i]
+               - u[2 * SS + (idx_t)k * plane + (idx_t)wrap(j - 1, P.ny, P.periodic[1]) * P.nx + i]) * (0.5 * P.inv_dy);
+        th += (u[3 * SS + (idx_t)wrap(k + 1, P.neta, P.periodic[2]) * plane + col]
+               - u[3 * SS + (idx_t)wrap(k - 1, P.neta, P.periodic[2]) * plane + col]) * (0.5 * P.inv_deta);
+        if (!CART) th += u[c] / tau;
+        double pe, cs2, T;
+        eos_full(E, (double)e[c], pe, cs2, T);
+        if (knpi) knpi[c] = P.shear ? 5.0 * P.eta_s / T * th : 0.0;
+        if (knPi) {
+            double v = 0.0;
+            if (P.bulk) {
+                const double d = 1.0 / 3.0 - cs2;
+                const double inv_tPi = P.zeta_model == 1
+                    ? 15.0 * d * d * T / (P.zeta_coef * zeta_over_s_paper(T / P.zeta_tc))
+                    : 15.0 * d * T / P.zeta_coef;
+                v = th / inv_tPi;
+            }
+            knPi[c] = v;
+        }
+    }
+}
+
 // ======================================================================
 // Host side
 // ======================================================================
@@ -1867,9 +1909,27 @@ kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out)
     return KT_OK;
 }
 
-kt_status kt_validity(kt_ctx *c, double *T_out, double *rinv_pi, double *rinv_Pi)
+kt_status kt_validity(kt_ctx *c, double *T_out, double *rinv_pi, double *rinv_Pi, double *kn_pi,
+                      double *kn_Pi)
 {
     if (!c) return fail(nullptr, KT_E_ARG, "null context");
+    if (kn_pi || kn_Pi) {
+        const dim3 g((unsigned)std::min<long long>((c->P.ncell + 255) / 256, 8192)), b(256);
+        const double *u = (const double *)c->u[c->ucur], *up = (const double *)c->u[c->uprev];
+        const bool cart = c->prm.coords == KT_CARTESIAN;
+        hipError_t e;
+        if (c->mixed)
+            e = cart ? launch(knudsen_kernel<true, float>, g, b, c->stream, c->P, c->E, c->tau, u, up,
+                              (const float *)c->e, kn_pi, kn_Pi)
+                     : launch(knudsen_kernel<false, float>, g, b, c->stream, c->P, c->E, c->tau, u, up,
+                              (const float *)c->e, kn_pi, kn_Pi);
+        else
+            e = cart ? launch(knudsen_kernel<true, double>, g, b, c->stream, c->P, c->E, c->tau, u, up,
+                              (const double *)c->e, kn_pi, kn_Pi)
+                     : launch(knudsen_kernel<false, double>, g, b, c->stream, c->P, c->E, c->tau, u, up,
+                              (const double *)c->e, kn_pi, kn_Pi);
+        if (e != hipSuccess) return fail(c, KT_E_HIP, "knudsen: %s", hipGetErrorString(e));
+    }
     if (!T_out && !rinv_pi && !rinv_Pi) return KT_OK;
     const bool cart = c->prm.coords == KT_CARTESIAN;
     const long long n = c->P.ncell;

@@ -114,7 +114,7 @@ def lib():
         L.kt_recover.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p * 9, C.c_void_p,
                                  C.c_void_p * 4, C.c_void_p, C.c_void_p]
         L.kt_observables.argtypes = [C.c_void_p, C.POINTER(KtObs), C.POINTER(KtFields)]
-        L.kt_validity.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.kt_validity.argtypes = [C.c_void_p] + [C.c_void_p] * 5
         L.kt_run_to_freezeout.argtypes = [C.c_void_p, C.c_double, C.c_int32, C.c_int32,
                                           C.POINTER(C.c_int32)]
         L.kt_destroy.argtypes = [C.c_void_p]
@@ -281,13 +281,12 @@ class Solver:
         return o.as_dict()
 
     def validity(self) -> dict:
-        """T, R^{-1}_pi and R^{-1}_Pi per cell (Sec. 7), as (neta, ny, nx) tensors."""
+        """T, R^{-1}_pi, R^{-1}_Pi, Kn_pi and Kn_Pi per cell (Sec. 7), as (neta, ny, nx) tensors."""
         torch = self.torch
+        names = ("T", "rinv_pi", "rinv_Pi", "kn_pi", "kn_Pi")
         with torch.cuda.device(self.device):
-            out = {k: torch.empty(self.grid.shape, dtype=torch.float64, device=self.device)
-                   for k in ("T", "rinv_pi", "rinv_Pi")}
-            _check(lib().kt_validity(self.ctx, out["T"].data_ptr(), out["rinv_pi"].data_ptr(),
-                                     out["rinv_Pi"].data_ptr()), self.ctx)
+            out = {k: torch.empty(self.grid.shape, dtype=torch.float64, device=self.device) for k in names}
+            _check(lib().kt_validity(self.ctx, *[out[k].data_ptr() for k in names]), self.ctx)
             torch.cuda.synchronize(self.device)
         return out
 

@@ -260,6 +260,10 @@ def test_bjorken_lattice_eos_zeta_of_T_2plus1d(kt):
     w = I.Workload("bjorken_lattice", g, tau0, 200, cfg, eos, prims)
     errs, gpu, sim, f, r = run_pair(kt, w, 200, report="bjorken_lattice_2+1d")
     assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9, errs
+    # Bjorken flow has theta = 1/tau: Kn_pi = tau_pi / tau = 5 (eta/s) / (T tau)
+    m = {k: v.cpu().numpy() for k, v in gpu.validity().items()}
+    T = oracle.eos_eval(eos, f["e"].reshape(-1))[2]
+    assert np.allclose(m["kn_pi"].reshape(-1), 5.0 * 0.2 / (T * sim.tau), rtol=1e-12, atol=0)
     assert abs(f["q"][14].reshape(-1)[0] - r["q"][14].reshape(-1)[0]) <= 1e-9 * abs(r["q"][14].reshape(-1)[0])
 
 
@@ -277,6 +281,31 @@ def test_validity_maps_match_oracle(kt):
         assert np.max(np.abs(got - ref)[dense]) <= 1e-9 * np.max(np.abs(ref[dense]))
         assert np.all(np.isfinite(got))
     assert np.max(rpi[dense]) > 0 and np.max(rPi[dense]) > 0
+    # Knudsen numbers: theta from the oracle's kinematics (App. A) on the same
+    # differences of the oracle's u (backward in tau, central in x, y, eta, clamped)
+    u, up, dt = r["u"], r["up"], w.config["dtau"]
+    g = w.grid
+    idx = np.argwhere(dense)
+    rng = np.random.default_rng(0)
+    idx = idx[rng.choice(len(idx), size=min(400, len(idx)), replace=False)]
+    cl = lambda v, n: min(max(v, 0), n - 1)
+    p_, cs2_, T_ = oracle.eos_eval(w.eos, r["e"][dense])
+    Tmap = np.zeros_like(r["e"]); cmap = np.zeros_like(r["e"])
+    Tmap[dense], cmap[dense] = T_, cs2_
+    worst = 0.0
+    for (k, j, i) in idx:
+        du = np.zeros((4, 4))
+        du[0] = (u[:, k, j, i] - up[:, k, j, i]) / dt
+        du[1] = (u[:, k, j, cl(i + 1, g.nx)] - u[:, k, j, cl(i - 1, g.nx)]) / (2 * g.dx)
+        du[2] = (u[:, k, cl(j + 1, g.ny), i] - u[:, k, cl(j - 1, g.ny), i]) / (2 * g.dy)
+        du[3] = (u[:, cl(k + 1, g.neta), j, i] - u[:, cl(k - 1, g.neta), j, i]) / (2 * g.deta)
+        th = oracle.kinematics(sim.tau, False, u[:, k, j, i], du)["theta"]
+        T, d = Tmap[k, j, i], 1.0 / 3.0 - cmap[k, j, i]
+        kn_pi = 5.0 * w.config["eta_s"] / T * th
+        kn_Pi = th / (15.0 * d * T / w.config["zeta_coef"])
+        worst = max(worst, abs(m["kn_pi"][k, j, i] - kn_pi) / (abs(kn_pi) + 1e-3),
+                    abs(m["kn_Pi"][k, j, i] - kn_Pi) / (abs(kn_Pi) + 1e-3))
+    assert worst <= 1e-8, worst
 
 
 def test_run_to_freezeout_matches_oracle_loop(kt):
