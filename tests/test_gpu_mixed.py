@@ -131,3 +131,29 @@ def test_mixed_hotspot_128_errors(kt):
         if s <= 100:
             assert de[hot].max() <= 1e-5 and du[hot].max() <= 1e-5
     assert gpu.observables()["n_nan"] == 0
+
+
+def test_mixed_lattice_eos_zeta_of_T_50_steps(kt):
+    """Mixed precision with the paper's physics (lattice-QCD EOS, zeta/s(T))
+    on the hot-spot event 56x52x24: 50 steps against the FP64 oracle.  Same
+    bars as the 128^3 event up to 100 steps: median 1e-6, dense cells 1e-5."""
+    w = I.workload_hotspot(nx=56, ny=52, neta=24, dx=0.4, deta=0.5, n_hot=60, seed=3,
+                           eos=I.eos_lattice_table())
+    cfg = dict(w.config, zeta_model=1, zeta_coef=1.0)
+    gpu = kt.Solver(w.grid, mixed(cfg), w.eos, w.prims)
+    gpu.step(50)
+    ref = oracle.Simulation.from_primitives(oracle.Physics.from_config(w.grid, cfg), w.eos, w.prims)
+    ref.step(50)
+    r = ref.fields()
+    f = {k: v.cpu().numpy() for k, v in gpu.fields(("e", "u")).items()}
+    er, emax = r["e"].reshape(-1), r["e"].max()
+    de = np.abs(f["e"].reshape(-1) - er) / np.maximum(er, 1e-6 * emax)
+    ur = r["u"].reshape(4, -1)
+    w_ = np.array([1, 1, 1, ref.tau])[:, None]
+    du = np.max(np.abs(f["u"].reshape(4, -1) - ur) * w_ / ur[0:1], axis=0)
+    hot = er > 1e-3 * emax
+    print("mixed lattice+zeta(T) 56x52x24, 50 steps: dense e %.2e u %.2e | median e %.1e u %.1e"
+          % (de[hot].max(), du[hot].max(), np.median(de), np.median(du)), flush=True)
+    assert np.median(de) <= 1e-6 and np.median(du) <= 1e-6
+    assert de[hot].max() <= 1e-5 and du[hot].max() <= 1e-5
+    assert gpu.observables()["n_nan"] == 0
