@@ -39,9 +39,9 @@ KERNEL_VALUES = {"flux": 45.0, "sources": 47.5, "recover": 32.0, "faces": 16.0}
 # WRITE_SIZE x 1.000 (scale factors of a 256 MiB device copy), profiles/kt_step_hotspot128_fp64.md;
 # valid for the kernel sources and compiler flags whose hash is TRAFFIC_SOURCES (else the traffic
 # is reported as null)
-TRAFFIC_SOURCES = "dcad5fdd5590f7ab"
-TRAFFIC_BYTES = {"faces": 6.542e8 + 1.185e8, "flux": 0.5 * (1.3827e9 + 1.3843e9) + 2.517e8,
-                 "sources": 0.5 * (7.471e8 + 1.1008e9) + 2.517e8, "recover": 2.706e8 + 3.201e8}
+TRAFFIC_SOURCES = "10a900de3a5d4b1a"
+TRAFFIC_BYTES = {"faces": 6.508e8 + 1.613e8, "flux": 0.5 * (1.3804e9 + 1.3838e9) + 2.517e8,
+                 "sources": 0.5 * (7.472e8 + 1.1081e9) + 2.517e8, "recover": 2.706e8 + 3.198e8}
 KERNEL_NAMES = {"flux": "flux_kernel (KT flux divergence + stage update)",
                 "sources": "sources_kernel (App. B sources + stage update)",
                 "recover": "recover_kernel (Newton inversion + regulator)",

@@ -213,8 +213,9 @@ __device__ __forceinline__ R face_H(R qm, R qp, R vm, R vp, R a)
 // Face speeds (Sec. 3.1, last paragraph): every face of the grid has two
 // reconstructed states, q^- = q_L + slope_L/2 from the cell on its left and
 // q^+ = q_R - slope_R/2 from the cell on its right; each is inverted like a
-// cell (warm start: the e of the cell it was extrapolated from) and the
-// velocity component normal to the face is stored.
+// cell, its Newton iteration started from the conformal closed-form root of
+// the state (fewer iterations than the e of the neighbouring cell, and no
+// load), and the velocity component normal to the face is stored.
 // One thread per face: it reads the four cells of the face's line that the
 // two slopes need and inverts q^- and then q^+.
 // The launch is cut into three segments of whole blocks, x, y and eta faces,
@@ -234,7 +235,7 @@ struct FaceLaunch {
 template <bool CART, typename S>
 __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, const FaceGeo G,
                                                  const FaceLaunch L, double tau, const double *qT,
-                                                 const S *qP, const S *e, S *vf,
+                                                 const S *qP, S *vf,
                                                  unsigned long long *slots, unsigned b, long long wave,
                                                  double (*qpark)[FACE_BLOCK])
 {
@@ -329,11 +330,11 @@ __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, co
             // (a compiler barrier: the parked values are not carried in registers)
             asm volatile("" ::: "memory");
             int it2 = 0;
-            st(vf + off, t, (S)speed(mm, (double)ld(e, cL), it));
+            st(vf + off, t, (S)speed(mm, 0.0, it));
             asm volatile("" ::: "memory");
 #pragma unroll
             for (int r = 0; r < 9; ++r) mp[r] = qpark[r][tx];
-            st(vf + off + nf, t, (S)speed(mp, (double)ld(e, cR), it2));
+            st(vf + off + nf, t, (S)speed(mp, 0.0, it2));
             it += it2;
         }
     }
@@ -345,11 +346,10 @@ __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, co
 template <bool CART, typename S>
 __global__ __launch_bounds__(FACE_BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void face_speeds_kernel(Phys P, Eos E, FaceGeo G, FaceLaunch L,
                                                           double tau, const double *qT, const S *qP,
-                                                          const S *e, S *vf,
-                                                          unsigned long long *slots)
+                                                          S *vf, unsigned long long *slots)
 {
     __shared__ double qpark[9][FACE_BLOCK];
-    face_speeds_body<CART, S>(P, E, G, L, tau, qT, qP, e, vf, slots, xcd_block(blockIdx.x, gridDim.x),
+    face_speeds_body<CART, S>(P, E, G, L, tau, qT, qP, vf, slots, xcd_block(blockIdx.x, gridDim.x),
                               (long long)blockIdx.x * (FACE_BLOCK / 64) + (threadIdx.x >> 6), qpark);
 }
 
@@ -895,7 +895,7 @@ struct BFace {              // one event of a face-speed launch
     FaceGeo G;
     FaceLaunch L;
     const double *qT;
-    const S *qP, *e;
+    const S *qP;
     S *vf;
     unsigned long long *slots;
 };
@@ -957,7 +957,7 @@ __global__ __launch_bounds__(FACE_BLOCK) __attribute__((amdgpu_waves_per_eu(8)))
     const unsigned lb = g - first[ev];
     const double tau = tau_dev[0] + A.P.dtau;
     __shared__ double qpark[9][FACE_BLOCK];
-    face_speeds_body<CART, S>(A.P, A.E, A.G, A.L, tau, A.qT, A.qP, A.e, A.vf, A.slots, lb,
+    face_speeds_body<CART, S>(A.P, A.E, A.G, A.L, tau, A.qT, A.qP, A.vf, A.slots, lb,
                               (long long)lb * (FACE_BLOCK / 64) + (threadIdx.x >> 6), qpark);
 }
 
@@ -1544,11 +1544,11 @@ static kt_status run_faces_t(kt_ctx *c, double tau, int which)
     const FaceLaunch L = face_launch(c->G, c->P.nx, c->P.ny);
     const dim3 g(L.nblocks), b(FACE_BLOCK);
     const double *qT = c->qT[which];
-    const S *qP = (const S *)c->qP[which], *ee = (const S *)c->e;
+    const S *qP = (const S *)c->qP[which];
     e = cart ? launch(face_speeds_kernel<true, S>, g, b, c->stream, c->P, c->E, c->G, L, tau, qT, qP,
-                      ee, (S *)c->vf, c->slots)
+                      (S *)c->vf, c->slots)
              : launch(face_speeds_kernel<false, S>, g, b, c->stream, c->P, c->E, c->G, L, tau, qT, qP,
-                      ee, (S *)c->vf, c->slots);
+                      (S *)c->vf, c->slots);
     if (e == hipSuccess) e = prof_mark(c, 2, false);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "face kernel: %s", hipGetErrorString(e));
     return KT_OK;
@@ -2266,7 +2266,6 @@ static kt_status batch_tables(kt_batch *b)
             F.L = face_launch(c->G, P.nx, P.ny);
             F.qT = c->qT[which];
             F.qP = (const S *)c->qP[which];
-            F.e = (const S *)c->e;
             F.vf = (S *)c->vf;
             F.slots = c->slots;
         }
