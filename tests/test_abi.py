@@ -48,11 +48,16 @@ def test_workspace_bytes_and_validation(L):
     n = L.kt_workspace_bytes(C.byref(p), C.byref(eos.c))
     assert n > 43 * 8 * g.ncells and n % 256 == 0
     bad = [("nx", 0), ("dx", 0.0), ("dtau", -1.0), ("theta", 2.5), ("theta", 0.9), ("tau0", 0.0),
-           ("e_floor", 0.0), ("m2_delta", 1.0), ("newton_max", 0), ("coords", 7)]
+           ("e_floor", 0.0), ("m2_delta", 1.0), ("newton_max", 0), ("coords", 7), ("zeta_model", 2)]
     for field, val in bad:
         q = kt.make_params(g, cfg, 0.5)
         setattr(q, field, val)
         assert L.kt_workspace_bytes(C.byref(q), C.byref(eos.c)) == 0, field
+    q = kt.make_params(g, cfg, 0.5)
+    q.zeta_model, q.zeta_tc = 1, 0.0            # the paper's zeta/s(T) needs T_c > 0
+    assert L.kt_workspace_bytes(C.byref(q), C.byref(eos.c)) == 0
+    q.zeta_tc = 0.2 / I.HBARC
+    assert L.kt_workspace_bytes(C.byref(q), C.byref(eos.c)) == n
     small = I.eos_c1_table(n=64)
     small.p = small.p[:1]
     small.cs2 = small.cs2[:1]
@@ -101,6 +106,9 @@ def test_init_rejects_bad_arguments_without_device_work(L):
     # calls on a null context
     assert L.kt_step(None, 1) == kt.KT_E_ARG
     assert L.kt_observables(None, None, None) == kt.KT_E_ARG
+    assert L.kt_validity(None, None, None, None, None, None) == kt.KT_E_ARG
+    n_done = C.c_int32(-1)
+    assert L.kt_run_to_freezeout(None, 0.7, 10, 1, C.byref(n_done)) == kt.KT_E_ARG
     L.kt_destroy(None)
     assert L.kt_status_string(kt.KT_E_ALLOC) == b"workspace too small"
 
