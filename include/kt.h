@@ -214,8 +214,8 @@ enum { KT_START_WARM = 0, KT_START_CONFORMAL = 1, KT_START_LEARNED = 2 };
  * e before the stage; the default), KT_START_CONFORMAL (closed form of the
  * conformal EOS) or KT_START_LEARNED (needs kt_mlp_set first: KT_E_STATE
  * otherwise).  kt_recover uses the network for KT_START_LEARNED and the
- * conformal closed form otherwise.  Face states always start from the e
- * of the cell they were extrapolated from. */
+ * conformal closed form otherwise.  Face states always start from the
+ * conformal closed form of their own state. */
 kt_status kt_set_inv_start(kt_ctx *c, int32_t start);
 
 /* Copy KT_MLP_NPARAMS parameters from d_params (device) into the context
