@@ -39,9 +39,9 @@ KERNEL_VALUES = {"flux": 45.0, "sources": 47.5, "recover": 32.0, "faces": 16.0}
 # WRITE_SIZE x 1.000 (scale factors of a 256 MiB device copy), profiles/kt_step_hotspot128_fp64.md;
 # valid for the kernel sources and compiler flags whose hash is TRAFFIC_SOURCES (else the traffic
 # is reported as null)
-TRAFFIC_SOURCES = "10a900de3a5d4b1a"
-TRAFFIC_BYTES = {"faces": 6.508e8 + 1.613e8, "flux": 0.5 * (1.3804e9 + 1.3838e9) + 2.517e8,
-                 "sources": 0.5 * (7.472e8 + 1.1081e9) + 2.517e8, "recover": 2.706e8 + 3.198e8}
+TRAFFIC_SOURCES = "c9ea6676b92e54a7"
+TRAFFIC_BYTES = {"faces": 6.519e8 + 1.613e8, "flux": 0.5 * (1.3829e9 + 1.3833e9) + 2.517e8,
+                 "sources": 0.5 * (7.486e8 + 1.1006e9) + 2.517e8, "recover": 2.552e8 + 3.215e8}
 KERNEL_NAMES = {"flux": "flux_kernel (KT flux divergence + stage update)",
                 "sources": "sources_kernel (App. B sources + stage update)",
                 "recover": "recover_kernel (Newton inversion + regulator)",
@@ -260,7 +260,7 @@ def main():
                    "dx_fm": w.grid.dx, "deta": w.grid.deta, "tau0": w.tau0,
                    "dtau": w.config["dtau"], "eta_over_s": w.config["eta_s"],
                    "zeta_over_s": "0.1 (1/3 - c_s^2)", "eos": "tabulated, 4096 nodes",
-                   "precision": "fp64", "inversion_start": "previous e of the cell (warm start)",
+                   "precision": "fp64", "inversion_start": "conformal closed-form root",
                    "step_hbm_frac": STEP_VALUES * 8.0 * value / (HBM_PEAK_GBS * 1e9),
                    "paper_context_ms_per_step": {"gtx980ti_fp32_128cube_table": 244.45,
                                                  "gtx980ti_program_summary": 38400.0}},

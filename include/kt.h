@@ -211,8 +211,8 @@ enum { KT_START_WARM = 0, KT_START_CONFORMAL = 1, KT_START_LEARNED = 2 };
 #define KT_MLP_NPARAMS 5188
 
 /* Newton start of the cell recoveries in kt_step: KT_START_WARM (the cell's
- * e before the stage; the default), KT_START_CONFORMAL (closed form of the
- * conformal EOS) or KT_START_LEARNED (needs kt_mlp_set first: KT_E_STATE
+ * e before the stage), KT_START_CONFORMAL (closed form of the conformal EOS;
+ * the default) or KT_START_LEARNED (needs kt_mlp_set first: KT_E_STATE
  * otherwise).  kt_recover uses the network for KT_START_LEARNED and the
  * conformal closed form otherwise.  Face states always start from the
  * conformal closed form of their own state. */

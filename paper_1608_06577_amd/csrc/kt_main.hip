@@ -941,7 +941,9 @@ __global__ __launch_bounds__(256) void recover_batch(const BRec<S> *__restrict__
     const int ev = map[g];
     const BRec<S> &A = tab[ev];
     const double tau = tau_dev[0] + A.P.dtau;
-    recover_body<CART, false, S>(A.P, A.E, tau, A.qT, A.qP, A.e, A.p, A.u, 1, 1, nullptr, A.slots,
+    // events of a batch keep the library's default Newton start (KT_START_CONFORMAL:
+    // warm = 0), as a single context does
+    recover_body<CART, false, S>(A.P, A.E, tau, A.qT, A.qP, A.e, A.p, A.u, 1, 0, nullptr, A.slots,
                                  (idx_t)(g - first[ev]) * 256 + threadIdx.x);
 }
 
@@ -1702,7 +1704,7 @@ kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0
     c->mlp_part = (float *)(base + L.mlp_part);
     c->loss_part = (double *)(base + L.loss_part);
     c->mlp_ready = false;
-    c->inv_start = KT_START_WARM;
+    c->inv_start = KT_START_CONFORMAL;   // the oracle's start, and the fastest measured
     c->tau = p->tau0;
     c->step = 0;
 

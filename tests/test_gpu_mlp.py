@@ -173,6 +173,7 @@ def test_learned_start_against_conformal_start(kt):
     gl = kt.Solver(w2.grid, w2.config, w2.eos, w2.prims)
     gl.mlp_set(gpu.mlp_get())
     gl.set_inv_start(kt.KT_START_LEARNED)
+    gw.set_inv_start(kt.KT_START_WARM)
     gw.step(20)
     gl.step(20)
     a, b = gw.fields(("e",))["e"], gl.fields(("e",))["e"]
