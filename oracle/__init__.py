@@ -85,6 +85,10 @@ def lib():
         L.ora_minmod3.argtypes = [C.c_double, C.c_double, C.c_double]
         L.ora_minmod3.restype = C.c_double
         L.ora_num_threads.restype = C.c_int
+        L.ora_set_num_threads.argtypes = [C.c_int32]
+        L.ora_observables.argtypes = [P, E, C.c_double, dp, dp, dp, dp]
+        L.ora_validity2.argtypes = [P, E, C.c_double, dp, dp, dp, dp, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]
         _lib = L
     return _lib
 
@@ -189,6 +193,38 @@ def validity_maps(eos, tau, cartesian, e, pi, Pi):
     return T, np.sqrt(np.maximum(pp, 0.0)) / p, np.abs(np.asarray(Pi)) / p
 
 
+OBS_KEYS = ("energy", "momentum_x", "momentum_y", "momentum_eta", "e_max", "T_max", "v_max",
+            "cfl", "norm_err", "pi_transverse", "pi_trace", "n_nan")
+
+
+def observables(phys: "Physics", eos, tau, q, e, u) -> dict:
+    """The state's observables (the definitions of the library's kt_obs): sums
+    of T^{tau mu} times the cell volume, maxima of e, T, |v|, the CFL number,
+    |u.u - 1| and the pi-constraint ratios of Sec. 2.4, non-finite cells."""
+    ref = EOSRef(eos)
+    out = np.empty(12)
+    P = phys.c()
+    lib().ora_observables(C.byref(P), C.byref(ref.c), float(tau), _dp(np.ascontiguousarray(q, float)),
+                          _dp(np.ascontiguousarray(e, float)), _dp(np.ascontiguousarray(u, float)),
+                          _dp(out))
+    return dict(zip(OBS_KEYS, out))
+
+
+def validity2(phys: "Physics", eos, tau, q, e, u, up):
+    """Per cell (AoS state as in Simulation): the second-order inverse Reynolds
+    numbers of Sec. 7 (Eq. inverseReynoldsNumbers2) and the regulation factor
+    tanh(rho)/rho of Sec. 3.2 evaluated on the state."""
+    ref = EOSRef(eos)
+    n = phys.ncells
+    r2pi, r2Pi, reg = np.empty(n), np.empty(n), np.empty(n)
+    P = phys.c()
+    lib().ora_validity2(C.byref(P), C.byref(ref.c), float(tau), _dp(np.ascontiguousarray(q, float)),
+                        _dp(np.ascontiguousarray(e, float)), _dp(np.ascontiguousarray(u, float)),
+                        _dp(np.ascontiguousarray(up, float)), r2pi.ctypes.data_as(C.c_void_p),
+                        r2Pi.ctypes.data_as(C.c_void_p), reg.ctypes.data_as(C.c_void_p))
+    return r2pi, r2Pi, reg
+
+
 def zeta_over_s_paper(x):
     """The oracle's zeta/s(T / T_c) of Sec. 2.2 (Eq. zetas), elementwise."""
     return np.array([lib().ora_zeta_over_s_paper(float(v)) for v in np.ravel(x)]).reshape(np.shape(x))
@@ -274,6 +310,11 @@ def minmod3(x, y, z):
 
 def num_threads() -> int:
     return int(lib().ora_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (results do not depend on it)."""
+    lib().ora_set_num_threads(int(n))
 
 
 class Simulation:

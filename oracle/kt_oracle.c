@@ -36,11 +36,12 @@
  *   - minmod uses sgn(0) = 0 (Sec. 3.1).
  *   - Stage 1 is evaluated at tau^n; the recovery of q*, stage 2 and the final
  *     recovery at tau^{n+1} (Sec. 4.3).
- *   - Regulator (Sec. 3.2): sqrt(e^2 + 3 P0^2) with the equilibrium pressure;
- *     the second and third ratios use absolute values; the third is the
- *     largest |pi^{lambda mu} u_mu| over lambda in an orthonormal frame
- *     (the eta component multiplied by tau); the factor is 1 when rho = 0.
- *     Only pi^{mu nu} is rescaled.
+ *   - Regulator (Sec. 3.2, Eq. rho): sqrt(e^2 + 3 P^2) with P = P0 + Pi, the
+ *     shorthand of Sec. 2.4 that Eq. rho prints; the second and third ratios
+ *     use absolute values; the third is the largest |pi^{lambda mu} u_mu|
+ *     over lambda in an orthonormal frame (the eta component multiplied by
+ *     tau); the factor is 1 when rho = 0.  pi^{mu nu} is rescaled, and Pi too
+ *     when regulate_bulk is set.
  *   - Recovery guards (Sec. 3.2 leaves them open), see recover() below.
  *   - Transport coefficients (Sec. 2.2) with eta/s fixed and
  *     zeta/s = zeta_coef (1/3 - c_s^2): 1/tau_pi = T / (5 eta/s),
@@ -210,7 +211,7 @@ static void tmunu_from_primitives(const ora_params *P, const ora_eos *eos, doubl
 /* Guards (the paper leaves them open; the HIP path applies the same):
  *  - E = T^tt - pi^tt not above e_floor (or not a number): e = e_floor, u = (1,0,0,0).
  *  - W = E + p(e_floor) + Pi not positive: the same floor state.
- *  - M^2 above M2max = (1 - 1e-8) W min(E - e_floor, W): M is rescaled to M2max.
+ *  - M^2 above M2max = (1 - m2_delta) W min(E - e_floor, W): M is rescaled to M2max.
  *    This keeps the root of f inside (e_floor, E] and e + P > 0.
  *  - Conformal EOS without bulk: closed form e = sqrt(4E^2 - 3M^2) - E.
  *  - Otherwise Newton on f(e) = e - E + M^2/(E + P(e)), f' = 1 - M^2 c_s^2/(E+P)^2,
@@ -304,7 +305,7 @@ static double regulate_cell(const ora_params *P, const ora_eos *eos, double tau,
     double pi[4][4];
     pi_tensor(q, pi);
     double Pi = P->zeta_coef > 0.0 ? q[14] : 0.0;
-    double p0 = eos_p(eos, e);
+    double Pcal = eos_p(eos, e) + Pi;   /* script P = P0 + Pi (Sec. 2.4) */
     double B[4][4];   /* Pi^{mu nu} = Pi Delta^{mu nu} + pi^{mu nu} */
     for (int m = 0; m < 4; ++m)
         for (int n = 0; n < 4; ++n)
@@ -313,7 +314,7 @@ static double regulate_cell(const ora_params *P, const ora_eos *eos, double tau,
     for (int m = 0; m < 4; ++m)
         for (int n = 0; n < 4; ++n) BB += B[m][n] * B[m][n] * glo[m] * glo[n];
     double nB = sqrt(fmax(BB, 0.0));
-    double rho = nB / (P->rho_max * sqrt(e * e + 3.0 * p0 * p0));
+    double rho = nB / (P->rho_max * sqrt(e * e + 3.0 * Pcal * Pcal));
     if (nB > 0.0) {
         double tr = 0.0;
         for (int m = 0; m < 4; ++m) tr += glo[m] * pi[m][m];
@@ -833,4 +834,173 @@ int ora_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ==================================================================== */
+/* Diagnostics.  Everything above this line defines the step (the       */
+/* golden samples of the test suite record its hash); what follows only */
+/* reads states.                                                        */
+/* ==================================================================== */
+
+/* OpenMP threads of the oracle's loops (the CPU baseline times 1 thread and
+ * all of them; results do not depend on the count: cells are independent) */
+void ora_set_num_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* Observables of a state, the definitions of the library's kt_obs written
+ * with this file's generic contractions (loops in cell order, one thread):
+ *   out[0]      sum of T^{tau tau} times the cell volume dx dy deta (times tau in Milne)
+ *   out[1..3]   the same for T^{tau x}, T^{tau y}, T^{tau eta}
+ *   out[4], [5] largest e and T(e)
+ *   out[6]      largest |v^i| = |u^i/u^tau| over cells and axes, in an orthonormal
+ *               frame (the eta component times tau)
+ *   out[7]      dtau times the largest |v^i| / d_i (coordinate components)
+ *   out[8]      largest |u^mu u_mu - 1|
+ *   out[9]      largest max_lambda |pi^{lambda mu} u_mu| / sqrt(|pi^{mu nu} pi_{mu nu}|)
+ *               (orthonormal frame), the orthogonality check of Sec. 2.4
+ *   out[10]     largest |g_{mu nu} pi^{mu nu}| / sqrt(|pi^{mu nu} pi_{mu nu}|), the
+ *               tracelessness check of Sec. 2.4 (both over cells with pi:pi != 0,
+ *               0 without shear viscosity)
+ *   out[11]     cells with a non-finite value in q, e or u (left out of the rest) */
+void ora_observables(const ora_params *P, const ora_eos *eos, double tau, const double *q,
+                     const double *e, const double *u, double *out)
+{
+    const int64_t n = (int64_t)P->nx * P->ny * P->neta;
+    double glo[4], ghi[4];
+    metric(tau, P->cartesian, glo, ghi);
+    const double h[3] = {P->dx, P->dy, P->deta};
+    double sum[4] = {0, 0, 0, 0}, emax = 0, Tmax = 0, vmax = 0, cfl = 0, nerr = 0, piu = 0, pitr = 0;
+    int64_t nnan = 0;
+    for (int64_t c = 0; c < n; ++c) {
+        const double *qc = q + NQ * c, *uc = u + 4 * c;
+        int finite = isfinite(e[c]);
+        for (int k = 0; k < NQ; ++k) finite = finite && isfinite(qc[k]);
+        for (int m = 0; m < 4; ++m) finite = finite && isfinite(uc[m]);
+        if (!finite) { ++nnan; continue; }
+        for (int m = 0; m < 4; ++m) sum[m] += qc[m];
+        double p, cs2, T;
+        eos_eval(eos, e[c], &p, &cs2, &T);
+        if (e[c] > emax) emax = e[c];
+        if (T > Tmax) Tmax = T;
+        double uu = 0.0;
+        for (int m = 0; m < 4; ++m) uu += glo[m] * uc[m] * uc[m];
+        if (fabs(uu - 1.0) > nerr) nerr = fabs(uu - 1.0);
+        for (int i = 1; i < 4; ++i) {
+            double v = fabs(uc[i] / uc[0]);
+            if (v * sqrt(fabs(glo[i])) > vmax) vmax = v * sqrt(fabs(glo[i]));
+            if (v / h[i - 1] * P->dtau > cfl) cfl = v / h[i - 1] * P->dtau;
+        }
+        if (P->eta_s > 0.0) {
+            double pi[4][4], pp = 0.0, tr = 0.0, w = 0.0;
+            pi_tensor(qc, pi);
+            for (int m = 0; m < 4; ++m) {
+                tr += glo[m] * pi[m][m];
+                double s = 0.0;
+                for (int k = 0; k < 4; ++k) {
+                    pp += glo[m] * glo[k] * pi[m][k] * pi[m][k];
+                    s += pi[m][k] * glo[k] * uc[k];
+                }
+                s = fabs(s) * sqrt(fabs(glo[m]));
+                if (s > w) w = s;
+            }
+            const double np = sqrt(fabs(pp));
+            if (np > 0.0) {
+                if (w / np > piu) piu = w / np;
+                if (fabs(tr) / np > pitr) pitr = fabs(tr) / np;
+            }
+        }
+    }
+    const double vol = P->dx * P->dy * P->deta * (P->cartesian ? 1.0 : tau);
+    for (int m = 0; m < 4; ++m) out[m] = sum[m] * vol;
+    out[4] = emax; out[5] = Tmax; out[6] = vmax; out[7] = cfl; out[8] = nerr;
+    out[9] = piu; out[10] = pitr; out[11] = (double)nnan;
+}
+
+/* Validity of the second-order truncation (Sec. 7, Eq. inverseReynoldsNumbers2)
+ * and the regulation factor (Sec. 3.2, Eqs. regPimunu, rho), per cell of the
+ * state (q, e, u) at tau with the previous step's flow up:
+ *   J^{mu nu} = 2 tau_pi pi_l^<mu omega^nu>l - delta_pipi pi^{mu nu} theta
+ *               - tau_pipi pi^{l<mu} sigma^{nu>}_l + lambda_piPi Pi sigma^{mu nu}
+ *   J         = -delta_PiPi Pi theta + lambda_Pipi pi^{mu nu} sigma_{mu nu}
+ * (Eq. 14_moment_terms without particle diffusion, coefficients of Sec. 2.2),
+ *   rinv2_pi = sqrt(J^{mu nu} J_{mu nu}) / (2 eta sqrt(sigma^{mu nu} sigma_{mu nu})),
+ *   rinv2_Pi = |J| / (zeta |theta|),
+ * with eta = tau_pi (e + P0)/5 and zeta = tau_Pi 15 (1/3 - c_s^2)^2 (e + P0), so
+ * the relaxation times cancel; 0 where the dissipative quantity is not evolved
+ * or the numerator vanishes, +inf where only the denominator vanishes.  The
+ * gradients are those of the sources: a backward difference in tau and central
+ * differences in space of the cell flow.  reg = tanh(rho)/rho of Eq. rho
+ * evaluated on the state (1 where it does not regulate).  Outputs nullable. */
+void ora_validity2(const ora_params *P, const ora_eos *eos, double tau, const double *q,
+                   const double *e, const double *u, const double *up, double *rinv2_pi,
+                   double *rinv2_Pi, double *reg)
+{
+    const int shear = P->eta_s > 0.0, bulk = P->zeta_coef > 0.0;
+    const double hs[3] = {P->dx, P->dy, P->deta};
+    double glo[4], ghi[4];
+    metric(tau, P->cartesian, glo, ghi);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < P->neta; ++k)
+        for (int j = 0; j < P->ny; ++j)
+            for (int i = 0; i < P->nx; ++i) {
+                const int64_t c = cell_index(P, i, j, k);
+                const double *qc = q + NQ * c, *uc = u + 4 * c, *upc = up + 4 * c;
+                double du[4][4];
+                for (int m = 0; m < 4; ++m) du[0][m] = (uc[m] - upc[m]) / P->dtau;
+                for (int d = 0; d < 3; ++d) {
+                    const double *ua = u + 4 * neighbour(P, i, j, k, d, +1);
+                    const double *ub = u + 4 * neighbour(P, i, j, k, d, -1);
+                    for (int m = 0; m < 4; ++m) du[d + 1][m] = (ua[m] - ub[m]) / (2.0 * hs[d]);
+                }
+                kin_t K;
+                kinematics(tau, P->cartesian, uc, du, &K);
+                double pi[4][4];
+                pi_tensor(qc, pi);
+                if (!shear)
+                    for (int m = 0; m < 4; ++m) for (int n = 0; n < 4; ++n) pi[m][n] = 0.0;
+                double I1[4][4], I2[4][4], I3[4][4], I4[4][4], pis;
+                second_order_terms(tau, P->cartesian, uc, pi, &K, I1, I2, I3, I4, &pis);
+                double p0, cs2, T;
+                eos_eval(eos, e[c], &p0, &cs2, &T);
+                const double Pi = bulk ? qc[14] : 0.0;
+                const double d13 = 1.0 / 3.0 - cs2;
+                if (rinv2_pi) {
+                    double v = 0.0;
+                    if (shear) {
+                        /* J^{mu nu} / tau_pi, with I3 = 2 pi_l^<mu omega^nu>l and
+                         * I4 = pi^{l<mu} sigma^{nu>}_l as in the relaxation equation */
+                        double XX = 0.0, SS = 0.0;
+                        for (int m = 0; m < 4; ++m)
+                            for (int n = 0; n < 4; ++n) {
+                                double X = I3[m][n] - 4.0 / 3.0 * I2[m][n] - P->taupipi * I4[m][n]
+                                         + 6.0 / 5.0 * Pi * K.sigma[m][n];
+                                XX += glo[m] * glo[n] * X * X;
+                                SS += glo[m] * glo[n] * K.sigma[m][n] * K.sigma[m][n];
+                            }
+                        const double num = sqrt(fabs(XX));
+                        v = num == 0.0 ? 0.0 : num / (2.0 * (e[c] + p0) / 5.0 * sqrt(fabs(SS)));
+                    }
+                    rinv2_pi[c] = v;
+                }
+                if (rinv2_Pi) {
+                    double v = 0.0;
+                    if (bulk) {
+                        /* J / tau_Pi over zeta / tau_Pi */
+                        const double num = fabs(-2.0 / 3.0 * Pi * K.theta + 8.0 / 5.0 * d13 * pis);
+                        v = num == 0.0 ? 0.0 : num / (15.0 * d13 * d13 * (e[c] + p0) * fabs(K.theta));
+                    }
+                    rinv2_Pi[c] = v;
+                }
+                if (reg) {
+                    double qq[NQ];
+                    for (int m = 0; m < NQ; ++m) qq[m] = qc[m];
+                    reg[c] = regulate_cell(P, eos, tau, qq, e[c], uc);
+                }
+            }
 }
