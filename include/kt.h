@@ -263,10 +263,21 @@ kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out);
  * |Pi| / P(e), P the equilibrium pressure of the EOS; the Knudsen numbers
  * tau_pi theta and tau_Pi theta (signed; 0 where pi or Pi is not evolved),
  * theta = d_mu u^mu + u^tau/tau (Milne) from a backward difference in tau
- * against the previous step's u and central differences in x, y, eta.
- * Asynchronous on the context's stream; KT_E_HIP if a launch fails. */
+ * against the previous step's u and central differences in x, y, eta; the
+ * second-order inverse Reynolds numbers of Eq. inverseReynoldsNumbers2,
+ * sqrt(J^{mu nu} J_{mu nu}) / (2 eta sqrt(sigma^{mu nu} sigma_{mu nu})) and
+ * |J| / (zeta |theta|), with J^{mu nu} = 2 tau_pi pi_l^<mu omega^nu>l -
+ * delta_pipi pi^{mu nu} theta - tau_pipi pi^{l<mu} sigma^{nu>}_l +
+ * lambda_piPi Pi sigma^{mu nu} and J = -delta_PiPi Pi theta + lambda_Pipi
+ * pi^{mu nu} sigma_{mu nu} (Eq. 14_moment_terms without particle diffusion,
+ * coefficients of Sec. 2.2; 0 where the quantity is not evolved or J
+ * vanishes, +inf where only the denominator does), from the full velocity
+ * gradient of the same differences; and the regulation factor tanh(rho)/rho
+ * of Sec. 3.2 (Eqs. regPimunu, rho) evaluated on the current state (1 where
+ * the regulator is off).  Asynchronous on the context's stream; KT_E_HIP if
+ * a launch fails. */
 kt_status kt_validity(kt_ctx *c, double *T_out, double *rinv_pi, double *rinv_Pi, double *kn_pi,
-                      double *kn_Pi);
+                      double *kn_Pi, double *rinv2_pi, double *rinv2_Pi, double *reg_factor);
 
 /* Runs Heun steps until the hottest cell is below T_f (the freeze-out
  * temperature, 155 MeV in Sec. 7, in the EOS's temperature unit) or
@@ -301,8 +312,8 @@ kt_status kt_profile_read(kt_ctx *c, kt_profile *out);
  * the same coordinates, precision, tau0 and dtau) are advanced together:
  * every kernel of a Heun step is one launch over the tiles of all events,
  * and one step is captured once as a hipGraph and replayed.  Results equal
- * those of separate contexts bit for bit.  Newton starts from the warm
- * start (the cell's e before the stage).
+ * those of separate contexts bit for bit.  Newton starts from the
+ * conformal closed form, the default start of a context.
  *
  * Workspace: kt_batch_workspace_bytes(p, n, eos) bytes (256-byte aligned,
  * caller-owned, must outlive the batch), holding every event's workspace,

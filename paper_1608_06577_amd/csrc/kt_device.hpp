@@ -315,10 +315,11 @@ __device__ __forceinline__ int recover(const Phys &P, const Eos &E, double tau, 
 }
 
 // ------------------------------------------------------------ regulator ---
-// Sec. 3.2: rho = max( |Pi^{mu nu}| / (rho_max sqrt(e^2 + 3 P0^2)),
+// Sec. 3.2: rho = max( |Pi^{mu nu}| / (rho_max sqrt(e^2 + 3 P^2)),
 //                      |pi^mu_mu| / (xi0 rho_max |Pi^{mu nu}|),
 //                      max_l |pi^{l mu} u_mu| / (xi0 rho_max |Pi^{mu nu}|) ),
 // |X| = sqrt(X^{mu nu} X_{mu nu}), Pi^{mu nu} = Pi Delta^{mu nu} + pi^{mu nu},
+// P = P0 + Pi (the shorthand of Sec. 2.4 that Eq. rho uses),
 // the eta row of pi.u taken in the tetrad (times sqrt(g33)); pi (and Pi
 // when regulate_bulk) are multiplied by tanh(rho)/rho.
 template <bool CART>
@@ -339,7 +340,8 @@ __device__ __forceinline__ double regulate(const Phys &P, double tau, double q[N
         }
     }
     const double nB = sqrt(fmax(BB, 0.0));
-    double rho = nB / (P.rho_max * sqrt(e * e + 3.0 * p0 * p0));
+    const double Pc = p0 + Pi;
+    double rho = nB / (P.rho_max * sqrt(e * e + 3.0 * Pc * Pc));
     if (nB > 0.0) {
         const double tr = q[PTT] - q[PXX] - q[PYY] - g33 * q[PEE];
         const double lim = 1.0 / (P.xi0 * P.rho_max * nB);
@@ -380,6 +382,22 @@ __device__ __forceinline__ R slope(R qm, R q0, R qp, R theta)
     return s * fmin(fmin(fabs(theta * a), fabs(R(0.5) * (qp - qm))), fabs(theta * b));
 }
 
+// the limiter of a kernel instantiated for theta = 1 (T1) or any theta.  For
+// theta = 1 the middle argument |qp - qm|/2 never decides: when a and b share
+// a sign, |qp - qm| >= 2 min(|a|, |b|) exactly, and rounding is monotone, so
+// fl(qp - qm)/2 >= min(fl|a|, fl|b|); the result is s min(|a|, |b|), bit for
+// bit what slope() returns, with five operations fewer.
+template <bool T1, typename R>
+__device__ __forceinline__ R limited(R qm, R q0, R qp, R theta)
+{
+    if (T1) {
+        const R a = q0 - qm, b = qp - q0;
+        const R s = copysign(R(0.5), a) + copysign(R(0.5), b);
+        return s * fmin(fabs(a), fabs(b));
+    }
+    return slope(qm, q0, qp, theta);
+}
+
 // ------------------------------------------------- relaxation sources ----
 // zeta/s(x), x = T / T_c, of Sec. 2.2 (Eq. zetas): near T_c a parabola, above
 // 1.05 T_c two decaying exponentials over the QGP value 0.001, below 0.995 T_c
@@ -403,12 +421,15 @@ __device__ __forceinline__ double zeta_over_s_paper(double x)
 // components in the order of q (pi^{tau tau} first).  Each result is handed
 // to emit(c, q_c, J_c) as soon as it is known (c: index in q).  Arithmetic
 // in R.
-template <bool CART, typename R, typename Emit>
-__device__ __forceinline__ void relaxation_sources(const Phys &P, double tau_d, const R pv[10],
-                                                   R Pi, R e, R p0, R cs2, R T, const R u[4],
-                                                   R C[4][4], R divv, Emit &&emit)
+// Kinematics of the flow (Sec. 2.4, App. A) from C[a][m] = partial_a u^m
+// (a: tau, x, y, eta): on return C holds the covariant derivative u^m_{;a},
+// th = theta, Du = D u^m, Dl = D u_m, sg the ten components of sigma^{mu nu}
+// in the order of q's pi, om the antisymmetric omega^{mu nu} for m < n in the
+// order (01, 02, 03, 12, 13, 23).  Arithmetic in R.
+template <bool CART, typename R>
+__device__ __forceinline__ void flow_kinematics(R tau, const R u[4], R C[4][4], R &th, R Du[4], R Dl[4],
+                                                R sg[10], R om[6])
 {
-    const R tau = R(tau_d);
     const R g33 = CART ? R(1) : tau * tau;
     const R inv_tau = R(1) / tau;
     const R glo[4] = {R(1), R(-1), R(-1), -g33};
@@ -419,15 +440,13 @@ __device__ __forceinline__ void relaxation_sources(const Phys &P, double tau_d, 
         C[0][3] += u[3] * inv_tau;      // Gamma^eta_{tau eta} u^eta
         C[3][3] += u[0] * inv_tau;      // Gamma^eta_{eta tau} u^tau
     }
-    const R th = C[0][0] + C[1][1] + C[2][2] + C[3][3];
-    R Du[4], Dl[4];
+    th = C[0][0] + C[1][1] + C[2][2] + C[3][3];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         Du[m] = u[0] * C[0][m] + u[1] * C[1][m] + u[2] * C[2][m] + u[3] * C[3][m];
         Dl[m] = glo[m] * Du[m];
     }
     // sigma (10) and omega (6) from nabla^m u^n = g^{mm} C[m][n] - u^m D u^n
-    R sg[10], om[6];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -437,18 +456,29 @@ __device__ __forceinline__ void relaxation_sources(const Phys &P, double tau_d, 
             const R Dmn = (m == n ? ghi[m] : R(0)) - u[m] * u[n];
             sg[pi_index(m, n) - PTT] = R(0.5) * (a + b) - th * R(1.0 / 3.0) * Dmn;
         }
-    // antisymmetric part, stored for m < n in the order (01, 02, 03, 12, 13, 23)
-    {
-        int k = 0;
+    int k = 0;
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = m + 1; n < 4; ++n) {
-                const R a = ghi[m] * C[m][n] - u[m] * Du[n];
-                const R b = ghi[n] * C[n][m] - u[n] * Du[m];
-                om[k++] = R(0.5) * (a - b);
-            }
-    }
+        for (int n = m + 1; n < 4; ++n) {
+            const R a = ghi[m] * C[m][n] - u[m] * Du[n];
+            const R b = ghi[n] * C[n][m] - u[n] * Du[m];
+            om[k++] = R(0.5) * (a - b);
+        }
+}
+
+template <bool CART, typename R, typename Emit>
+__device__ __forceinline__ void relaxation_sources(const Phys &P, double tau_d, const R pv[10],
+                                                   R Pi, R e, R p0, R cs2, R T, const R u[4],
+                                                   R C[4][4], R divv, Emit &&emit)
+{
+    const R tau = R(tau_d);
+    const R g33 = CART ? R(1) : tau * tau;
+    const R inv_tau = R(1) / tau;
+    const R glo[4] = {R(1), R(-1), R(-1), -g33};
+    const R ghi[4] = {R(1), R(-1), R(-1), R(-1) / g33};
+    R th, Du[4], Dl[4], sg[10], om[6];
+    flow_kinematics<CART, R>(tau, u, C, th, Du, Dl, sg, om);
     auto SG = [&](int m, int n) -> R { return sg[pi_index(m, n) - PTT]; };
     auto OM = [&](int m, int n) -> R {
         if (m == n) return R(0);
@@ -512,6 +542,72 @@ __device__ __forceinline__ void relaxation_sources(const Phys &P, double tau_d, 
         const R zeta_tPi = R(15) * d * d * (e + p0);
         const R IPi = R(2.0 / 3.0) * Pi * th - R(1.6) * d * pis;
         emit(BPI, Pi, (-zeta_tPi * th - Pi * inv_tPi - IPi) * inv_ut + Pi * divv);
+    }
+}
+
+// Second-order inverse Reynolds numbers of Sec. 7 (Eq. inverseReynoldsNumbers2)
+// of one cell, with the terms of Eq. 14_moment_terms that the relaxation
+// equations keep (no particle diffusion) and the coefficients of Sec. 2.2:
+//   J^{mu nu} / tau_pi = I3 - (4/3) theta pi - (tau_pipi/tau_pi) I4 + (6/5) Pi sigma,
+//   J / tau_Pi         = -(2/3) Pi theta + (8/5)(1/3 - c_s^2) pi^{mu nu} sigma_{mu nu},
+// I3 = 2 pi_l^<mu omega^nu>l, I4 = pi^{l<mu} sigma^{nu>}_l as in relaxation_sources;
+// with eta / tau_pi = (e + P0)/5 and zeta / tau_Pi = 15 (1/3 - c_s^2)^2 (e + P0)
+// the relaxation times cancel:
+//   r2pi = sqrt(J:J) / (2 eta sqrt(sigma:sigma)),  r2Pi = |J| / (zeta |theta|);
+// 0 where the quantity is not evolved or the numerator vanishes, +inf where
+// only the denominator does.  C as for flow_kinematics.  FP64.
+template <bool CART>
+__device__ __forceinline__ void second_order_reynolds(const Phys &P, double tau, const double pv[10],
+                                                      double Pi, double e, double p0, double cs2,
+                                                      const double u[4], double C[4][4], double &r2pi,
+                                                      double &r2Pi)
+{
+    const double g33 = CART ? 1.0 : tau * tau;
+    const double glo[4] = {1.0, -1.0, -1.0, -g33};
+    const double ghi[4] = {1.0, -1.0, -1.0, -1.0 / g33};
+    double th, Du[4], Dl[4], sg[10], om[6];
+    flow_kinematics<CART, double>(tau, u, C, th, Du, Dl, sg, om);
+    auto SG = [&](int m, int n) -> double { return sg[pi_index(m, n) - PTT]; };
+    auto OM = [&](int m, int n) -> double {
+        if (m == n) return 0.0;
+        const int a = m < n ? m : n, b = m < n ? n : m;
+        const int k = a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
+        return m < n ? om[k] : -om[k];
+    };
+    auto PI = [&](int m, int n) -> double { return pv[pi_index(m, n) - PTT]; };
+    double pis = 0.0, XX = 0.0, SS = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = m; n < 4; ++n) {
+            const double w = (m == n ? 1.0 : 2.0) * glo[m] * glo[n];
+            pis += w * PI(m, n) * SG(m, n);
+            SS += w * SG(m, n) * SG(m, n);
+        }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = m; n < 4; ++n) {
+            double I3 = 0.0, c4 = 0.0;
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                I3 += glo[l] * (PI(m, l) * OM(n, l) + PI(n, l) * OM(m, l));
+                c4 += glo[l] * (PI(m, l) * SG(n, l) + PI(n, l) * SG(m, l));
+            }
+            const double I4 = 0.5 * c4 - ((m == n ? ghi[m] : 0.0) - u[m] * u[n]) * pis * (1.0 / 3.0);
+            const double X = I3 - (4.0 / 3.0) * th * PI(m, n) - P.taupipi * I4 + 1.2 * Pi * SG(m, n);
+            XX += (m == n ? 1.0 : 2.0) * glo[m] * glo[n] * X * X;
+        }
+    r2pi = 0.0;
+    if (P.shear) {
+        const double num = sqrt(fabs(XX));
+        r2pi = num == 0.0 ? 0.0 : num / (0.4 * (e + p0) * sqrt(fabs(SS)));
+    }
+    r2Pi = 0.0;
+    if (P.bulk) {
+        const double d = 1.0 / 3.0 - cs2;
+        const double num = fabs(-(2.0 / 3.0) * Pi * th + 1.6 * d * pis);
+        r2Pi = num == 0.0 ? 0.0 : num / (15.0 * d * d * (e + p0) * fabs(th));
     }
 }
 

@@ -53,12 +53,13 @@ struct Fields {
     const S *p;
     const double *u;
     const double *up;
-    const S *vf;     // face speeds: v^-, v^+ per face, x, y and eta face arrays (see FaceGeo)
+    const S *vf;     // face coefficients c^-, c^+ of the KT flux per face, x, y and eta face arrays (see FaceGeo)
 };
 
 // Face arrays: the x faces of row (j,k) are i = 0..nx (face i lies between
-// cells i-1 and i), likewise for y and eta; each face holds v^- and v^+ of
-// its axis.  Offsets into Fields::vf, in elements.
+// cells i-1 and i), likewise for y and eta; each face holds the two
+// coefficients of its KT flux H = c^+ q^+ + c^- q^- (face_coefficients).
+// Offsets into Fields::vf, in elements.
 struct FaceGeo {
     long long nfx, nfy, nfe;          // faces per axis
     long long ox, oy, oe;             // offsets of the three arrays (v^- block then v^+ block)
@@ -121,14 +122,30 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// tile (bx, by, bz) of logical block L of a gx x gy x gz tiling of a stencil
+// launch: x fastest, or (KT_TILE_ZFAST) eta fastest, so that blocks running
+// together share their eta-neighbour planes
+__device__ __forceinline__ void tile_of_block(unsigned L, unsigned gx, unsigned gy, unsigned gz, unsigned &bx,
+                                              unsigned &by, unsigned &bz)
+{
+#ifdef KT_TILE_ZFAST
+    bz = L % gz;
+    bx = (L / gz) % gx;
+    by = L / (gz * gx);
+#else
+    (void)gz;
+    bx = L % gx;
+    by = (L / gx) % gy;
+    bz = L / (gx * gy);
+#endif
+}
+
 // logical (x, y, z) block of a 3D grid after the XCD renumbering
 __device__ __forceinline__ void xcd_block3(unsigned &bx, unsigned &by, unsigned &bz)
 {
     const unsigned gx = gridDim.x, gy = gridDim.y;
     const unsigned L = xcd_block(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
-    bx = L % gx;
-    by = (L / gx) % gy;
-    bz = L / (gx * gy);
+    tile_of_block(L, gx, gy, gridDim.z, bx, by, bz);
 }
 
 // floor(t / d) for t < 2^32, 1 <= d < 2^30, through a double product and one
@@ -203,11 +220,22 @@ template <typename T> __device__ __forceinline__ T row_up(T v)
 // minmod slopes of both cells, the half-cell extrapolations
 // q^- = q_L + slope_L/2 and q^+ = q_R - slope_R/2, the velocities of their
 // inversions v^-, v^+ (face_speeds_kernel; Sec. 3.1 last paragraph), the
-// local speed a = max(|v^-|, |v^+|) and H = (v^+ q^+ + v^- q^-)/2 - a (q^+ - q^-)/2.
-template <typename R>
-__device__ __forceinline__ R face_H(R qm, R qp, R vm, R vp, R a)
+// local speed a = max(|v^-|, |v^+|) and H = (v^+ q^+ + v^- q^-)/2 - a (q^+ - q^-)/2
+// (Eqs. Hflux, ax), written H = c^+ q^+ + c^- q^- with the two coefficients
+// c^+ = (v^+ - a)/2, c^- = (v^- + a)/2 of the face, which every component of q
+// shares: the face kernel stores them, the flux kernel forms each H with two
+// operations.
+__device__ __forceinline__ void face_coefficients(double vm, double vp, double &cm, double &cp)
 {
-    return R(0.5) * (vp * qp + vm * qm) - R(0.5) * a * (qp - qm);
+    const double a = fmax(fabs(vm), fabs(vp));
+    cp = 0.5 * (vp - a);
+    cm = 0.5 * (vm + a);
+}
+
+template <typename R>
+__device__ __forceinline__ R face_H(R qm, R qp, R cm, R cp)
+{
+    return cp * qp + cm * qm;
 }
 
 // Face speeds (Sec. 3.1, last paragraph): every face of the grid has two
@@ -232,7 +260,7 @@ struct FaceLaunch {
 };
 
 // b: the block within this event's launch; wave: its counter slot row
-template <bool CART, typename S>
+template <bool CART, bool T1, typename S>
 __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, const FaceGeo G,
                                                  const FaceLaunch L, double tau, const double *qT,
                                                  const S *qP, S *vf,
@@ -292,8 +320,8 @@ __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, co
                 a0 = R(ld(qP, co + c0)); a1 = R(ld(qP, co + cL));
                 a2 = R(ld(qP, co + cR)); a3 = R(ld(qP, co + c3));
             }
-            qm = (double)(a1 + R(0.5) * slope(a0, a1, a2, theta));
-            qp = (double)(a2 - R(0.5) * slope(a1, a2, a3, theta));
+            qm = (double)(a1 + R(0.5) * limited<T1>(a0, a1, a2, theta));
+            qp = (double)(a2 - R(0.5) * limited<T1>(a1, a2, a3, theta));
         };
         const long long off = d == 0 ? G.ox : (d == 1 ? G.oy : G.oe);
         // q^+ waits in the block's LDS (qpark, this thread's column) while q^- is inverted
@@ -305,7 +333,7 @@ __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, co
         // whatever its other components (the inversion's first guard).  Vacuum
         // regions make whole waves of such states; they skip the rest.
         if (__all(!(mm[0] - mm[4] > P.e_floor) && !(mp[0] - mp[4] > P.e_floor))) {
-            st(vf + off, t, (S)0.0);
+            st(vf + off, t, (S)0.0);          // v^- = v^+ = 0: both coefficients vanish
             st(vf + off + nf, t, (S)0.0);
         } else {
             qpark[0][tx] = mp[0];
@@ -330,12 +358,16 @@ __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, co
             // (a compiler barrier: the parked values are not carried in registers)
             asm volatile("" ::: "memory");
             int it2 = 0;
-            st(vf + off, t, (S)speed(mm, 0.0, it));
+            qpark[9][tx] = speed(mm, 0.0, it);        // v^- waits in LDS too
             asm volatile("" ::: "memory");
 #pragma unroll
             for (int r = 0; r < 9; ++r) mp[r] = qpark[r][tx];
-            st(vf + off + nf, t, (S)speed(mp, 0.0, it2));
+            const double vp = speed(mp, 0.0, it2);
             it += it2;
+            double cm, cp;
+            face_coefficients(qpark[9][tx], vp, cm, cp);
+            st(vf + off, t, (S)cm);
+            st(vf + off + nf, t, (S)cp);
         }
     }
     slot_add(slots, wave, C_ITERS_FACES, it, iter_bits(P) + 1);
@@ -343,13 +375,13 @@ __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, co
     slot_add(slots, wave, C_FALLBACK_FACES, nfb, 2);
 }
 
-template <bool CART, typename S>
+template <bool CART, bool T1, typename S>
 __global__ __launch_bounds__(FACE_BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void face_speeds_kernel(Phys P, Eos E, FaceGeo G, FaceLaunch L,
                                                           double tau, const double *qT, const S *qP,
                                                           S *vf, unsigned long long *slots)
 {
-    __shared__ double qpark[9][FACE_BLOCK];
-    face_speeds_body<CART, S>(P, E, G, L, tau, qT, qP, vf, slots, xcd_block(blockIdx.x, gridDim.x),
+    __shared__ double qpark[10][FACE_BLOCK];
+    face_speeds_body<CART, T1, S>(P, E, G, L, tau, qT, qP, vf, slots, xcd_block(blockIdx.x, gridDim.x),
                               (long long)blockIdx.x * (FACE_BLOCK / 64) + (threadIdx.x >> 6), qpark);
 }
 
@@ -602,7 +634,7 @@ __global__ __launch_bounds__(256) void sources_kernel(Phys P, Eos E, double tau,
 // component (Sec. 3.1), then
 //   stage 1: out = out + dtau D;   stage 2: out = (out + dtau D) / 2,
 // which with sources_kernel gives q + dtau C[q] and (qn + q + dtau C[q]) / 2.
-// Face speeds come from face_speeds_kernel.  Each wave holds 16 x 4 cells
+// Face coefficients come from face_speeds_kernel.  Each wave holds 16 x 4 cells
 // (x by y; lane = 16 row + column), so that a cell's y neighbours are mostly
 // other lanes' cells: every lane loads its own cell and one cell of the four
 // halo rows (y0-2, y0-1, y0+4, y0+5), and the stencil is assembled by lane
@@ -612,7 +644,7 @@ __global__ __launch_bounds__(256) void sources_kernel(Phys P, Eos E, double tau,
 // bottom face of plane k+1 (kept in LDS per thread); y faces: two per cell.
 // Components are processed one at a time.
 // Hb: the block's LDS carry of the eta faces; kc: eta planes per block
-template <bool STAGE2, typename S>
+template <bool STAGE2, bool T1, typename S>
 __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const double *qT, const S *qP,
                                           const S *vf, double *outT, S *outP, double (*HbT)[256],
                                           S (*Hb)[256], unsigned bx, unsigned by, unsigned bz, int kc)
@@ -653,30 +685,26 @@ __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const
         const idx_t col = (idx_t)jc * P.nx + ic;
         const int zm2 = wrap(k - 2, P.neta, P.periodic[2]), zm1 = wrap(k - 1, P.neta, P.periodic[2]);
         const int zp1 = wrap(k + 1, P.neta, P.periodic[2]), zp2 = wrap(k + 2, P.neta, P.periodic[2]);
-        // face speeds: x (left face, and the right one for the last lane of a row), y (both), eta (top)
+        // face coefficients: x (left face, and the right one for the last lane of a row), y (both),
+        // eta (top; the bottom one in the block's first plane)
         const idx_t fx = fidx_x(P.nx, P.ny, ifc, jc, k);
-        const R vmx = R(ld(vfx, fx)), vpx = R(ld(vfx + G.nfx, fx));
-        const R ax = fmax(fabs(vmx), fabs(vpx));
-        R vmr = R(0), vpr = R(0);
+        const R cmx = R(ld(vfx, fx)), cpx = R(ld(vfx + G.nfx, fx));
+        R cmr = R(0), cpr = R(0);
         if (right) {
-            vmr = R(ld(vfx, fx + 1));
-            vpr = R(ld(vfx + G.nfx, fx + 1));
+            cmr = R(ld(vfx, fx + 1));
+            cpr = R(ld(vfx + G.nfx, fx + 1));
         }
-        const R axr = fmax(fabs(vmr), fabs(vpr));
         const idx_t fy0 = fidx_y(P.nx, P.ny, ic, jc, k), fy1 = fidx_y(P.nx, P.ny, ic, jc + 1, k);
-        const R vmy0 = R(ld(vfy, fy0)), vpy0 = R(ld(vfy + G.nfy, fy0));
-        const R vmy1 = R(ld(vfy, fy1)), vpy1 = R(ld(vfy + G.nfy, fy1));
-        const R ay0 = fmax(fabs(vmy0), fabs(vpy0)), ay1 = fmax(fabs(vmy1), fabs(vpy1));
+        const R cmy0 = R(ld(vfy, fy0)), cpy0 = R(ld(vfy + G.nfy, fy0));
+        const R cmy1 = R(ld(vfy, fy1)), cpy1 = R(ld(vfy + G.nfy, fy1));
         const idx_t fe1 = fidx_e(P.nx, P.ny, ic, jc, k + 1);
-        const R vme = R(ld(vfe, fe1)), vpe = R(ld(vfe + G.nfe, fe1));
-        const R ae = fmax(fabs(vme), fabs(vpe));
-        R vmb = R(0), vpb = R(0);
+        const R cme = R(ld(vfe, fe1)), cpe = R(ld(vfe + G.nfe, fe1));
+        R cmb = R(0), cpb = R(0);
         if (kk == 0) {
             const idx_t fe0 = fidx_e(P.nx, P.ny, ic, jc, k);
-            vmb = R(ld(vfe, fe0));
-            vpb = R(ld(vfe + G.nfe, fe0));
+            cmb = R(ld(vfe, fe0));
+            cpb = R(ld(vfe + G.nfe, fe0));
         }
-        const R ab = fmax(fabs(vmb), fabs(vpb));
         const idx_t rx = kp + (idx_t)jc * P.nx;
         const idx_t rh = kp + (idx_t)jh * P.nx + ic;
         const idx_t e0 = col + (idx_t)zm2 * plane, e1 = col + (idx_t)zm1 * plane;
@@ -713,25 +741,27 @@ __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const
             const RR xe = xl == 15 ? edge2 : se;
             const RR xc = yc;
             // x: the face left of the cell; the right one from the next lane (the row's last lane: its own)
-            const RR sxb = slope(xa, xb, xc, th), sxc = slope(xb, xc, xd, th), sxd = slope(xc, xd, xe, th);
-            const RR Hx = face_H<RR>(xb + h * sxb, xc - h * sxc, RR(vmx), RR(vpx), RR(ax));
-            const RR Hown = face_H<RR>(xc + h * sxc, xd - h * sxd, RR(vmr), RR(vpr), RR(axr));
+            const RR sxb = limited<T1>(xa, xb, xc, th), sxc = limited<T1>(xb, xc, xd, th),
+                     sxd = limited<T1>(xc, xd, xe, th);
+            const RR Hx = face_H<RR>(xb + h * sxb, xc - h * sxc, RR(cmx), RR(cpx));
+            const RR Hown = face_H<RR>(xc + h * sxc, xd - h * sxd, RR(cmr), RR(cpr));
             const RR Hnb = row_next(Hx);
             RR D = (Hx - (right ? Hown : Hnb)) * RR(P.inv_dx);
             // y
-            const RR syb = slope(ya, yb, yc, th), syc = slope(yb, yc, yd, th), syd = slope(yc, yd, ye, th);
-            D += (face_H<RR>(yb + h * syb, yc - h * syc, RR(vmy0), RR(vpy0), RR(ay0))
-                - face_H<RR>(yc + h * syc, yd - h * syd, RR(vmy1), RR(vpy1), RR(ay1))) * RR(P.inv_dy);
+            const RR syb = limited<T1>(ya, yb, yc, th), syc = limited<T1>(yb, yc, yd, th),
+                     syd = limited<T1>(yc, yd, ye, th);
+            D += (face_H<RR>(yb + h * syb, yc - h * syc, RR(cmy0), RR(cpy0))
+                - face_H<RR>(yc + h * syc, yd - h * syd, RR(cmy1), RR(cpy1))) * RR(P.inv_dy);
             // eta: the bottom face is carried from the plane below except in the first plane
-            const RR sec = slope(eb, yc, ed, th), sed = slope(yc, ed, ee, th);
+            const RR sec = limited<T1>(eb, yc, ed, th), sed = limited<T1>(yc, ed, ee, th);
             RR Hb0;
             if (kk == 0) {
                 const RR ea = RR(ld(q, co + e0));
-                Hb0 = face_H<RR>(eb + h * slope(ea, eb, yc, th), yc - h * sec, RR(vmb), RR(vpb), RR(ab));
+                Hb0 = face_H<RR>(eb + h * limited<T1>(ea, eb, yc, th), yc - h * sec, RR(cmb), RR(cpb));
             } else {
                 Hb0 = Hc[tid];
             }
-            const RR Ht = face_H<RR>(yc + h * sec, ed - h * sed, RR(vme), RR(vpe), RR(ae));
+            const RR Ht = face_H<RR>(yc + h * sec, ed - h * sed, RR(cme), RR(cpe));
             Hc[tid] = Ht;
             D += (Hb0 - Ht) * RR(P.inv_deta);
             return D;
@@ -759,7 +789,7 @@ __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const
     }
 }
 
-template <bool STAGE2, typename S>
+template <bool STAGE2, bool T1, typename S>
 __global__ __launch_bounds__(256) void flux_kernel(Phys P, FaceGeo G, const double *qT, const S *qP,
                                                    const S *vf, double *outT, S *outP, int kc)
 {
@@ -767,17 +797,20 @@ __global__ __launch_bounds__(256) void flux_kernel(Phys P, FaceGeo G, const doub
     __shared__ S Hb[NQ - PTT][256];       // and pi, Pi
     unsigned bx, by, bz;
     xcd_block3(bx, by, bz);
-    flux_body<STAGE2, S>(P, G, qT, qP, vf, outT, outP, HbT, Hb, bx, by, bz, kc);
+    flux_body<STAGE2, T1, S>(P, G, qT, qP, vf, outT, outP, HbT, Hb, bx, by, bz, kc);
 }
 
 // recovery of every cell at tau, then the regulator and the floor reset;
 // writes e, p(e) and u.  Newton start: the cell's previous e (warm), the
-// conformal closed form, or (LEARNED) y_0 e_c from the network of kt_mlp.hpp.
-// The inversion and the regulator run in FP64 whatever the storage type S.
+// conformal closed form, or (LEARNED) y_0 e_c from the network of kt_mlp.hpp
+// on the matrix cores (K: the packed weights, xs: the wave's LDS rows; every
+// lane of the wave must call this).  The inversion and the regulator run in
+// FP64 whatever the storage type S.
 template <bool CART, bool LEARNED, typename S>
 __device__ __forceinline__ void recover_body(const Phys &P, const Eos &E, double tau, double *qT, S *qP,
                                              S *e_io, S *p_out, double *u_out, int do_regulate, int warm,
-                                             const float *__restrict__ mlpw, unsigned long long *slots,
+                                             const ktm::MlpPacked *__restrict__ K,
+                                             _Float16 (*xs)[ktm::XS_K], unsigned long long *slots,
                                              idx_t s)
 {
     const long long wave = s >> 6;
@@ -789,9 +822,34 @@ __device__ __forceinline__ void recover_body(const Phys &P, const Eos &E, double
     // wave of such cells (vacuum) writes that state without reading the rest or
     // evaluating the network (measured: no gain without the network, where the
     // extra registers cost the batched kernel a wave per SIMD)
-    const bool vacuum = LEARNED && valid && P.floor_reset
-                     && __all(!(ld(qT, s) - ldq(qT, qP, PTT, SS, s) > P.e_floor));
-    if (vacuum) {
+    bool vacuum = false;
+    if (LEARNED) {
+        const bool lane_vac = !valid || !(ld(qT, s) - ldq(qT, qP, PTT, SS, s) > P.e_floor);
+        vacuum = P.floor_reset && __all(lane_vac);    // uniform over the wave
+    }
+    double es = -1.0;
+    if (LEARNED && !vacuum) {
+        // the network's start, before the cell's state is held in registers;
+        // every lane takes part (lanes without a state pass zero features)
+        float x[ktm::NI];
+#pragma unroll
+        for (int f = 0; f < ktm::NI; ++f) x[f] = 0.0f;
+        double ec = -1.0;
+        if (valid) {
+            const double Ttt = ld(qT, s), ptt = ldq(qT, qP, PTT, SS, s);
+            if (Ttt > 0.0 && Ttt - ptt > 0.0) {
+                const double Ttx = ld(qT, SS + s), Tty = ld(qT, 2 * SS + s), Tte = ld(qT, 3 * SS + s);
+                const double ptx = ldq(qT, qP, PTX, SS, s), pty = ldq(qT, qP, PTY, SS, s);
+                const double pte = ldq(qT, qP, PTE, SS, s);
+                ktm::features<CART>(E, tau, Ttt, Ttx, Tty, Tte, ptt, ptx, pty, pte,
+                                    P.bulk ? ldq(qT, qP, BPI, SS, s) : 0.0, x);
+                ec = ktm::conformal_root<CART>(P.e_floor, tau, Ttt, Ttx, Tty, Tte, ptt, ptx, pty, pte);
+            }
+        }
+        const float y0 = ktm::forward_y0_mfma(K, x, xs);
+        if (ec > 0.0) es = (double)y0 * ec;
+    }
+    if (vacuum && valid) {
         fl = F_FLOOR;
         st(e_io, s, (S)P.e_floor);
         st(p_out, s, (S)P.p_floor);
@@ -802,20 +860,7 @@ __device__ __forceinline__ void recover_body(const Phys &P, const Eos &E, double
 #pragma unroll
         for (int c = PTT; c < NQ; ++c) st(qP, (idx_t)(c - PTT) * SS + s, (S)0);
     } else if (valid) {
-        double es = warm ? (double)ld(e_io, s) : -1.0;
-        if (LEARNED) {   // before the cell's state is held in registers
-            const double Ttt = ld(qT, s), ptt = ldq(qT, qP, PTT, SS, s);
-            if (Ttt > 0.0 && Ttt - ptt > 0.0) {
-                const double Ttx = ld(qT, SS + s), Tty = ld(qT, 2 * SS + s), Tte = ld(qT, 3 * SS + s);
-                const double ptx = ldq(qT, qP, PTX, SS, s), pty = ldq(qT, qP, PTY, SS, s);
-                const double pte = ldq(qT, qP, PTE, SS, s);
-                float x[ktm::NI];
-                ktm::features<CART>(E, tau, Ttt, Ttx, Tty, Tte, ptt, ptx, pty, pte,
-                                    P.bulk ? ldq(qT, qP, BPI, SS, s) : 0.0, x);
-                es = (double)ktm::forward_y0(mlpw, x)
-                   * ktm::conformal_root<CART>(P.e_floor, tau, Ttt, Ttx, Tty, Tte, ptt, ptx, pty, pte);
-            }
-        }
+        if (!LEARNED && warm) es = (double)ld(e_io, s);
         double qc[NQ];
 #pragma unroll
         for (int c = 0; c < NQ; ++c) qc[c] = ldq(qT, qP, c, SS, s);
@@ -849,10 +894,12 @@ template <bool CART, bool LEARNED, typename S>
 __global__ __launch_bounds__(256) void recover_kernel(Phys P, Eos E, double tau, double *qT, S *qP,
                                                       S *e_io, S *p_out, double *u_out,
                                                       int do_regulate, int warm,
-                                                      const float *__restrict__ mlpw,
+                                                      const ktm::MlpPacked *__restrict__ K,
                                                       unsigned long long *slots)
 {
-    recover_body<CART, LEARNED, S>(P, E, tau, qT, qP, e_io, p_out, u_out, do_regulate, warm, mlpw, slots,
+    __shared__ _Float16 xs[LEARNED ? 256 : 1][ktm::XS_K];
+    recover_body<CART, LEARNED, S>(P, E, tau, qT, qP, e_io, p_out, u_out, do_regulate, warm, K,
+                                   LEARNED ? xs + (threadIdx.x & ~63u) : xs, slots,
                                    (idx_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
@@ -910,13 +957,14 @@ __global__ __launch_bounds__(256) void sources_batch(const BStage<S> *__restrict
     const int ev = map[g];
     const BStage<S> &A = tab[ev];
     const unsigned lb = g - first[ev];
-    const unsigned bx = lb % A.sgx, by = (lb / A.sgx) % A.sgy, bz = lb / (A.sgx * A.sgy);
+    unsigned bx, by, bz;
+    tile_of_block(lb, A.sgx, A.sgy, A.P.neta, bx, by, bz);
     const double tau = STAGE2 ? tau_dev[0] + A.P.dtau : tau_dev[0];
     __shared__ SrcTile T;
     sources_body<CART, STAGE2, S>(A.P, A.E, tau, A.F, A.qnT, A.qnP, A.outT, A.outP, bx, by, bz, T);
 }
 
-template <bool STAGE2, typename S>
+template <bool STAGE2, bool T1, typename S>
 __global__ __launch_bounds__(256) void flux_batch(const BStage<S> *__restrict__ tab,
                                                   const unsigned short *__restrict__ map,
                                                   const unsigned *__restrict__ first)
@@ -927,8 +975,9 @@ __global__ __launch_bounds__(256) void flux_batch(const BStage<S> *__restrict__ 
     const int ev = map[g];
     const BStage<S> &A = tab[ev];
     const unsigned lb = g - first[ev];
-    const unsigned bx = lb % A.fgx, by = (lb / A.fgx) % A.fgy, bz = lb / (A.fgx * A.fgy);
-    flux_body<STAGE2, S>(A.P, A.G, A.F.qT, A.F.qP, A.F.vf, A.outT, A.outP, HbT, Hb, bx, by, bz, A.kc);
+    unsigned bx, by, bz;
+    tile_of_block(lb, A.fgx, A.fgy, (A.P.neta + A.kc - 1) / A.kc, bx, by, bz);
+    flux_body<STAGE2, T1, S>(A.P, A.G, A.F.qT, A.F.qP, A.F.vf, A.outT, A.outP, HbT, Hb, bx, by, bz, A.kc);
 }
 
 template <bool CART, typename S>
@@ -943,11 +992,11 @@ __global__ __launch_bounds__(256) void recover_batch(const BRec<S> *__restrict__
     const double tau = tau_dev[0] + A.P.dtau;
     // events of a batch keep the library's default Newton start (KT_START_CONFORMAL:
     // warm = 0), as a single context does
-    recover_body<CART, false, S>(A.P, A.E, tau, A.qT, A.qP, A.e, A.p, A.u, 1, 0, nullptr, A.slots,
+    recover_body<CART, false, S>(A.P, A.E, tau, A.qT, A.qP, A.e, A.p, A.u, 1, 0, nullptr, nullptr, A.slots,
                                  (idx_t)(g - first[ev]) * 256 + threadIdx.x);
 }
 
-template <bool CART, typename S>
+template <bool CART, bool T1, typename S>
 __global__ __launch_bounds__(FACE_BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void faces_batch(const BFace<S> *__restrict__ tab,
                                                    const unsigned short *__restrict__ map,
                                                    const unsigned *__restrict__ first,
@@ -958,8 +1007,8 @@ __global__ __launch_bounds__(FACE_BLOCK) __attribute__((amdgpu_waves_per_eu(8)))
     const BFace<S> &A = tab[ev];
     const unsigned lb = g - first[ev];
     const double tau = tau_dev[0] + A.P.dtau;
-    __shared__ double qpark[9][FACE_BLOCK];
-    face_speeds_body<CART, S>(A.P, A.E, A.G, A.L, tau, A.qT, A.qP, A.vf, A.slots, lb,
+    __shared__ double qpark[10][FACE_BLOCK];
+    face_speeds_body<CART, T1, S>(A.P, A.E, A.G, A.L, tau, A.qT, A.qP, A.vf, A.slots, lb,
                               (long long)lb * (FACE_BLOCK / 64) + (threadIdx.x >> 6), qpark);
 }
 
@@ -1022,22 +1071,31 @@ struct RecIn {
 template <bool CART, bool LEARNED>
 __global__ __launch_bounds__(256) void recover_standalone_kernel(Phys P, Eos E, double tau,
                                                                  long long n, RecIn R,
-                                                                 const float *__restrict__ mlpw)
+                                                                 const ktm::MlpPacked *__restrict__ K)
 {
+    __shared__ _Float16 xs[LEARNED ? 256 : 1][ktm::XS_K];
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const double Pi = (P.bulk && R.in[8]) ? R.in[8][s] : 0.0;
-    const double Ttt = R.in[0][s], ptt = R.in[4][s];
+    const bool valid = s < n;
+    if (!LEARNED && !valid) return;
+    const long long sv = valid ? s : 0;     // lanes past n compute on state 0 and store nothing
+    const double Pi = (P.bulk && R.in[8]) ? R.in[8][sv] : 0.0;
+    const double Ttt = R.in[0][sv], ptt = R.in[4][sv];
     double es = -1.0;
     if (LEARNED) {
+        // every lane of the wave takes part in the network (matrix instructions)
+        float x[ktm::NI];
+#pragma unroll
+        for (int f = 0; f < ktm::NI; ++f) x[f] = 0.0f;
+        double ec = -1.0;
         if (Ttt > 0.0 && Ttt - ptt > 0.0) {
-            float x[ktm::NI];
-            ktm::features<CART>(E, tau, Ttt, R.in[1][s], R.in[2][s], R.in[3][s], ptt, R.in[5][s],
-                                R.in[6][s], R.in[7][s], Pi, x);
-            es = (double)ktm::forward_y0(mlpw, x)
-               * ktm::conformal_root<CART>(P.e_floor, tau, Ttt, R.in[1][s], R.in[2][s], R.in[3][s], ptt,
-                                           R.in[5][s], R.in[6][s], R.in[7][s]);
+            ktm::features<CART>(E, tau, Ttt, R.in[1][sv], R.in[2][sv], R.in[3][sv], ptt, R.in[5][sv],
+                                R.in[6][sv], R.in[7][sv], Pi, x);
+            ec = ktm::conformal_root<CART>(P.e_floor, tau, Ttt, R.in[1][sv], R.in[2][sv], R.in[3][sv], ptt,
+                                           R.in[5][sv], R.in[6][sv], R.in[7][sv]);
         }
+        const float y0 = ktm::forward_y0_mfma(K, x, xs + (threadIdx.x & ~63u));
+        if (ec > 0.0) es = (double)y0 * ec;
+        if (!valid) return;
     }
     double e, p, u[4];
     int it;
@@ -1288,6 +1346,58 @@ __global__ __launch_bounds__(256) void knudsen_kernel(Phys P, Eos E, double tau,
     }
 }
 
+// Second-order inverse Reynolds numbers (Sec. 7, Eq. inverseReynoldsNumbers2;
+// second_order_reynolds) and the regulation factor tanh(rho)/rho of Sec. 3.2
+// (Eqs. regPimunu, rho) evaluated on the current state, per cell: the full
+// velocity gradient from the same differences as the sources kernel (backward
+// in tau from u_prev, central in x, y, eta with the boundary conditions).
+// Each output is nullable.
+template <bool CART, typename S>
+__global__ __launch_bounds__(256) void validity2_kernel(Phys P, Eos E, double tau, const double *u,
+                                                        const double *up, const S *qP, const S *e,
+                                                        double *r2pi_out, double *r2Pi_out, double *reg_out)
+{
+    const idx_t SS = (idx_t)P.stride;
+    const idx_t plane = (idx_t)P.nx * P.ny;
+    for (idx_t c = (idx_t)blockIdx.x * blockDim.x + threadIdx.x; c < (idx_t)P.ncell;
+         c += (idx_t)gridDim.x * blockDim.x) {
+        const int k = (int)(c / plane);
+        const idx_t rem = c - (idx_t)k * plane;
+        const int j = (int)(rem / P.nx), i = (int)(rem - (idx_t)j * P.nx);
+        const idx_t row = (idx_t)k * plane + (idx_t)j * P.nx, col = (idx_t)j * P.nx + i;
+        const idx_t nb[3][2] = {
+            {row + wrap(i + 1, P.nx, P.periodic[0]), row + wrap(i - 1, P.nx, P.periodic[0])},
+            {(idx_t)k * plane + (idx_t)wrap(j + 1, P.ny, P.periodic[1]) * P.nx + i,
+             (idx_t)k * plane + (idx_t)wrap(j - 1, P.ny, P.periodic[1]) * P.nx + i},
+            {(idx_t)wrap(k + 1, P.neta, P.periodic[2]) * plane + col,
+             (idx_t)wrap(k - 1, P.neta, P.periodic[2]) * plane + col}};
+        const double invh[3] = {P.inv_dx, P.inv_dy, P.inv_deta};
+        double uc[4], C[4][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            uc[m] = u[m * SS + c];
+            C[0][m] = (uc[m] - up[m * SS + c]) * P.inv_dtau;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                C[d + 1][m] = (u[m * SS + nb[d][0]] - u[m * SS + nb[d][1]]) * (0.5 * invh[d]);
+        }
+        double q[NQ];
+#pragma unroll
+        for (int cc = PTT; cc < NQ; ++cc) q[cc] = (double)qP[(cc - PTT) * SS + c];
+        const double ec = (double)e[c];
+        const double Pi = P.bulk ? q[BPI] : 0.0;
+        double p0, cs2, T;
+        eos_full(E, ec, p0, cs2, T);
+        if (r2pi_out || r2Pi_out) {
+            double r2pi, r2Pi;
+            second_order_reynolds<CART>(P, tau, q + PTT, Pi, ec, p0, cs2, uc, C, r2pi, r2Pi);
+            if (r2pi_out) r2pi_out[c] = r2pi;
+            if (r2Pi_out) r2Pi_out[c] = r2Pi;
+        }
+        if (reg_out) reg_out[c] = (P.regulate && P.shear) ? regulate<CART>(P, tau, q, ec, p0, uc) : 1.0;
+    }
+}
+
 // ======================================================================
 // Host side
 // ======================================================================
@@ -1312,6 +1422,8 @@ struct kt_ctx {
     FaceGeo G;
     double *partial, *obs;
     float *mlp_w, *mlp_m, *mlp_v, *mlp_part;   // network parameters, Adam moments, gradient partials
+    ktm::MlpPacked *mlp_pk;    // the parameters in the operand layout of the matrix-core inference
+    bool mlp_pk_dirty;         // mlp_w changed since mlp_pk was packed
     double *loss_part;
     bool mlp_ready;
     int inv_start;
@@ -1373,7 +1485,7 @@ static long long cell_stride(const kt_params *p)
 }
 
 struct Layout {
-    size_t qT, qP, qsT, qsP, u, e, p, vf, tab, slots, ctr, partial, obs, mlp, mlp_part, loss_part, total;
+    size_t qT, qP, qsT, qsP, u, e, p, vf, tab, slots, ctr, partial, obs, mlp, mlp_part, loss_part, mlp_pk, total;
     long long nwaves;
     FaceGeo G;
 };
@@ -1435,6 +1547,7 @@ static Layout layout(const kt_params *p, const kt_eos *eos)
     L.mlp = off; off += round_up((size_t)3 * ktm::NP * sizeof(float), 256);
     L.mlp_part = off; off += round_up((size_t)ktm::BWD_BLOCKS * ktm::NP * sizeof(float), 256);
     L.loss_part = off; off += round_up((size_t)(ktm::LOSS_BLOCKS + 1) * sizeof(double), 256);
+    L.mlp_pk = off; off += round_up(sizeof(ktm::MlpPacked), 256);
     L.total = off;
     return L;
 }
@@ -1471,6 +1584,30 @@ static const char *check_args(const kt_params *p, const kt_eos *eos)
     return nullptr;
 }
 
+// EOS table nodes on the host: per node p/e, T/e^{1/4}, c_s^2, 1/e_i with
+// e_i = exp(ln_e0 + i dln_e); h holds EOS_W * eos->n doubles
+static void eos_nodes_host(const kt_eos *eos, double *h)
+{
+    for (int i = 0; i < eos->n; ++i) {
+        const double ei = exp(eos->ln_e0 + eos->dln_e * (double)i);
+        h[EOS_W * i] = eos->p[i] / ei;
+        h[EOS_W * i + 1] = eos->T[i] / sqrt(sqrt(ei));
+        h[EOS_W * i + 2] = eos->cs2[i];
+        h[EOS_W * i + 3] = 1.0 / ei;
+    }
+}
+
+// kernels instantiated for theta = 1 take the limiter's exact shortcut (limited<true>)
+static bool theta_is_one(double theta)
+{
+#ifdef KT_NO_THETA1
+    (void)theta;
+    return false;
+#else
+    return theta == 1.0;
+#endif
+}
+
 static void fill_phys(const kt_params *p, Phys &P)
 {
     P.nx = p->nx; P.ny = p->ny; P.neta = p->neta;
@@ -1499,6 +1636,16 @@ static hipError_t launch(K kernel, dim3 g, dim3 b, hipStream_t st, A... args)
 
 static dim3 linear_grid(long long n) { return dim3((unsigned)((n + 255) / 256)); }
 
+// repack the network's parameters for the matrix-core inference if they
+// changed (kt_mlp_set, kt_mlp_adam); stream-ordered
+static hipError_t ensure_packed(kt_ctx *c)
+{
+    if (!c->mlp_pk_dirty) return hipSuccess;
+    hipError_t e = launch(ktm::mlp_pack_kernel, dim3(1), dim3(256), c->stream, (const float *)c->mlp_w, c->mlp_pk);
+    if (e == hipSuccess) c->mlp_pk_dirty = false;
+    return e;
+}
+
 // warm != 0: a step's recovery, whose start follows the context's choice
 // (previous e, conformal closed form, or the network); warm == 0: conformal.
 // which: 0 = q, 1 = q*; ub: u buffer receiving u.
@@ -1509,10 +1656,12 @@ static kt_status run_recover_t(kt_ctx *c, double tau, int which, int ub, int reg
     const bool learned = warm && c->inv_start == KT_START_LEARNED;
     if (warm && c->inv_start == KT_START_CONFORMAL) warm = 0;
     if (learned) warm = 0;
-    hipError_t e = prof_mark(c, 1, true);
+    hipError_t e = learned ? ensure_packed(c) : hipSuccess;
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "network packing: %s", hipGetErrorString(e));
+    e = prof_mark(c, 1, true);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
     const dim3 g = linear_grid(c->P.ncell), b(256);
-    const float *w = c->mlp_w;
+    const ktm::MlpPacked *w = c->mlp_pk;
     double *qT = c->qT[which];
     S *qP = (S *)c->qP[which], *ee = (S *)c->e, *pp = (S *)c->p;
     double *uu = (double *)c->u[ub];
@@ -1547,10 +1696,10 @@ static kt_status run_faces_t(kt_ctx *c, double tau, int which)
     const dim3 g(L.nblocks), b(FACE_BLOCK);
     const double *qT = c->qT[which];
     const S *qP = (const S *)c->qP[which];
-    e = cart ? launch(face_speeds_kernel<true, S>, g, b, c->stream, c->P, c->E, c->G, L, tau, qT, qP,
-                      (S *)c->vf, c->slots)
-             : launch(face_speeds_kernel<false, S>, g, b, c->stream, c->P, c->E, c->G, L, tau, qT, qP,
-                      (S *)c->vf, c->slots);
+    const bool t1 = theta_is_one(c->P.theta);
+    auto K = cart ? (t1 ? face_speeds_kernel<true, true, S> : face_speeds_kernel<true, false, S>)
+                  : (t1 ? face_speeds_kernel<false, true, S> : face_speeds_kernel<false, false, S>);
+    e = launch(K, g, b, c->stream, c->P, c->E, c->G, L, tau, qT, qP, (S *)c->vf, c->slots);
     if (e == hipSuccess) e = prof_mark(c, 2, false);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "face kernel: %s", hipGetErrorString(e));
     return KT_OK;
@@ -1590,8 +1739,10 @@ static kt_status run_stage_t(kt_ctx *c, bool stage2, double tau, int src, int ub
     const dim3 gf((P.nx + 63) / 64, (P.ny + 3) / 4, (P.neta + KC - 1) / KC);
     e = prof_mark(c, 0, true);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
-    e = stage2 ? launch(flux_kernel<true, S>, gf, b, c->stream, P, c->G, F.qT, F.qP, F.vf, outT, outP, KC)
-               : launch(flux_kernel<false, S>, gf, b, c->stream, P, c->G, F.qT, F.qP, F.vf, outT, outP, KC);
+    const bool t1 = theta_is_one(P.theta);
+    auto K = stage2 ? (t1 ? flux_kernel<true, true, S> : flux_kernel<true, false, S>)
+                    : (t1 ? flux_kernel<false, true, S> : flux_kernel<false, false, S>);
+    e = launch(K, gf, b, c->stream, P, c->G, F.qT, F.qP, F.vf, outT, outP, KC);
     if (e == hipSuccess) e = prof_mark(c, 0, false);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "flux kernel: %s", hipGetErrorString(e));
     return KT_OK;
@@ -1703,6 +1854,8 @@ kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0
     c->mlp_v = c->mlp_m + ktm::NP;
     c->mlp_part = (float *)(base + L.mlp_part);
     c->loss_part = (double *)(base + L.loss_part);
+    c->mlp_pk = (ktm::MlpPacked *)(base + L.mlp_pk);
+    c->mlp_pk_dirty = true;
     c->mlp_ready = false;
     c->inv_start = KT_START_CONFORMAL;   // the oracle's start, and the fastest measured
     c->tau = p->tau0;
@@ -1719,13 +1872,7 @@ kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0
     if (!eos->conformal) {
         double *h = (double *)malloc(sizeof(double) * EOS_W * eos->n);
         if (!h) { delete c; return fail(nullptr, KT_E_ALLOC, "host allocation failed"); }
-        for (int i = 0; i < eos->n; ++i) {
-            const double ei = exp(eos->ln_e0 + eos->dln_e * (double)i);
-            h[EOS_W * i] = eos->p[i] / ei;
-            h[EOS_W * i + 1] = eos->T[i] / sqrt(sqrt(ei));
-            h[EOS_W * i + 2] = eos->cs2[i];
-            h[EOS_W * i + 3] = 1.0 / ei;
-        }
+        eos_nodes_host(eos, h);
         Eos hE = c->E;   // same interpolation on the host for p(e_floor)
         hE.tab = h;
         c->P.p_floor = eos_p(hE, p->e_floor);
@@ -1818,8 +1965,9 @@ kt_status kt_recover(kt_ctx *c, int64_t n, double tau, const double *const in[9]
     R.iters = iters_out;
     R.flags = flags_out;
     const bool learned = c->inv_start == KT_START_LEARNED;
-    const float *w = c->mlp_w;
-    hipError_t e;
+    const ktm::MlpPacked *w = c->mlp_pk;
+    hipError_t e = learned ? ensure_packed(c) : hipSuccess;
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "network packing: %s", hipGetErrorString(e));
     if (c->prm.coords == KT_CARTESIAN)
         e = learned ? launch(recover_standalone_kernel<true, true>, linear_grid(n), dim3(256), c->stream, c->P, c->E, tau, (long long)n, R, w)
                     : launch(recover_standalone_kernel<true, false>, linear_grid(n), dim3(256), c->stream, c->P, c->E, tau, (long long)n, R, w);
@@ -1912,9 +2060,26 @@ kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out)
 }
 
 kt_status kt_validity(kt_ctx *c, double *T_out, double *rinv_pi, double *rinv_Pi, double *kn_pi,
-                      double *kn_Pi)
+                      double *kn_Pi, double *rinv2_pi, double *rinv2_Pi, double *reg_factor)
 {
     if (!c) return fail(nullptr, KT_E_ARG, "null context");
+    if (rinv2_pi || rinv2_Pi || reg_factor) {
+        const dim3 g((unsigned)std::min<long long>((c->P.ncell + 255) / 256, 8192)), b(256);
+        const double *u = (const double *)c->u[c->ucur], *up = (const double *)c->u[c->uprev];
+        const bool cart = c->prm.coords == KT_CARTESIAN;
+        hipError_t e;
+        if (c->mixed)
+            e = cart ? launch(validity2_kernel<true, float>, g, b, c->stream, c->P, c->E, c->tau, u, up,
+                              (const float *)c->qP[0], (const float *)c->e, rinv2_pi, rinv2_Pi, reg_factor)
+                     : launch(validity2_kernel<false, float>, g, b, c->stream, c->P, c->E, c->tau, u, up,
+                              (const float *)c->qP[0], (const float *)c->e, rinv2_pi, rinv2_Pi, reg_factor);
+        else
+            e = cart ? launch(validity2_kernel<true, double>, g, b, c->stream, c->P, c->E, c->tau, u, up,
+                              (const double *)c->qP[0], (const double *)c->e, rinv2_pi, rinv2_Pi, reg_factor)
+                     : launch(validity2_kernel<false, double>, g, b, c->stream, c->P, c->E, c->tau, u, up,
+                              (const double *)c->qP[0], (const double *)c->e, rinv2_pi, rinv2_Pi, reg_factor);
+        if (e != hipSuccess) return fail(c, KT_E_HIP, "second-order validity: %s", hipGetErrorString(e));
+    }
     if (kn_pi || kn_Pi) {
         const dim3 g((unsigned)std::min<long long>((c->P.ncell + 255) / 256, 8192)), b(256);
         const double *u = (const double *)c->u[c->ucur], *up = (const double *)c->u[c->uprev];
@@ -1993,6 +2158,7 @@ kt_status kt_mlp_set(kt_ctx *c, const float *d_params, int32_t n_params)
     if (e == hipSuccess) e = hipMemsetAsync(c->mlp_m, 0, 2 * b, c->stream);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "kt_mlp_set: %s", hipGetErrorString(e));
     c->mlp_ready = true;
+    c->mlp_pk_dirty = true;
     return KT_OK;
 }
 
@@ -2093,6 +2259,7 @@ kt_status kt_mlp_adam(kt_ctx *c, const float *grad, float lr, float b1, float b2
     hipError_t e = launch(ktm::adam_kernel, dim3((ktm::NP + 255) / 256), dim3(256), c->stream, c->mlp_w,
                           c->mlp_m, c->mlp_v, grad, lr, b1, b2, eps, c1, c2);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "adam kernel: %s", hipGetErrorString(e));
+    c->mlp_pk_dirty = true;
     return KT_OK;
 }
 
@@ -2142,6 +2309,7 @@ struct kt_batch {
     hipStream_t cap;             // stream the step graph is captured on and replayed on
     hipEvent_t fork_ev, join_ev;
     bool mixed, cart;
+    bool theta1;                 // every event limits with theta = 1
     double dtau;
     double *tau_dev;
     char *tab;                   // device tables (see batch_tables)
@@ -2333,7 +2501,7 @@ static kt_status batch_tables(kt_batch *b)
 
 // enqueue one Heun step of every event on stream st (captured into the graph
 // of step parity par)
-template <bool CART, typename S>
+template <bool CART, bool T1, typename S>
 static hipError_t batch_step_launches(kt_batch *b, hipStream_t st, int par)
 {
     const int n = b->n;
@@ -2345,25 +2513,25 @@ static hipError_t batch_step_launches(kt_batch *b, hipStream_t st, int par)
     hipError_t e = launch(sources_batch<CART, false, S>, dim3(b->nb_src), blk2, st,
                           (const BStage<S> *)T(b->o_s1[par]), M(b->o_msrc), F(b->o_fsrc), tau);
     if (e == hipSuccess)
-        e = launch(flux_batch<false, S>, dim3(b->nb_flux), blk2, st, (const BStage<S> *)T(b->o_s1[par]),
+        e = launch(flux_batch<false, T1, S>, dim3(b->nb_flux), blk2, st, (const BStage<S> *)T(b->o_s1[par]),
                    M(b->o_mflux), F(b->o_fflux));
     if (e == hipSuccess)
         e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r1[par]),
                    M(b->o_mrec), F(b->o_frec), tau);
     if (e == hipSuccess)
-        e = launch(faces_batch<CART, S>, dim3(b->nb_face), dim3(FACE_BLOCK), st, (const BFace<S> *)T(b->o_f1),
+        e = launch(faces_batch<CART, T1, S>, dim3(b->nb_face), dim3(FACE_BLOCK), st, (const BFace<S> *)T(b->o_f1),
                    M(b->o_mface), F(b->o_fface), tau);
     if (e == hipSuccess)
         e = launch(sources_batch<CART, true, S>, dim3(b->nb_src), blk2, st,
                    (const BStage<S> *)T(b->o_s2[par]), M(b->o_msrc), F(b->o_fsrc), tau);
     if (e == hipSuccess)
-        e = launch(flux_batch<true, S>, dim3(b->nb_flux), blk2, st, (const BStage<S> *)T(b->o_s2[par]),
+        e = launch(flux_batch<true, T1, S>, dim3(b->nb_flux), blk2, st, (const BStage<S> *)T(b->o_s2[par]),
                    M(b->o_mflux), F(b->o_fflux));
     if (e == hipSuccess)
         e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r2[par]),
                    M(b->o_mrec), F(b->o_frec), tau);
     if (e == hipSuccess)
-        e = launch(faces_batch<CART, S>, dim3(b->nb_face), dim3(FACE_BLOCK), st, (const BFace<S> *)T(b->o_f2),
+        e = launch(faces_batch<CART, T1, S>, dim3(b->nb_face), dim3(FACE_BLOCK), st, (const BFace<S> *)T(b->o_f2),
                    M(b->o_mface), F(b->o_fface), tau);
     if (e == hipSuccess) e = launch(tau_advance_kernel, dim3(1), dim3(64), st, b->tau_dev, b->dtau);
     return e;
@@ -2371,7 +2539,7 @@ static hipError_t batch_step_launches(kt_batch *b, hipStream_t st, int par)
 
 // stage 1 of the batch without its recovery: the sources and flux launches
 // (timed by kt_batch_tune; they only write q*, which every step rewrites)
-template <bool CART, typename S>
+template <bool CART, bool T1, typename S>
 static hipError_t batch_stage1_t(kt_batch *b, hipStream_t st)
 {
     const BStage<S> *tab = (const BStage<S> *)(const void *)(b->tab + b->o_s1[b->step & 1]);
@@ -2379,22 +2547,38 @@ static hipError_t batch_stage1_t(kt_batch *b, hipStream_t st)
                           (const unsigned short *)(b->tab + b->o_msrc), (const unsigned *)(b->tab + b->o_fsrc),
                           (const double *)b->tau_dev);
     if (e == hipSuccess)
-        e = launch(flux_batch<false, S>, dim3(b->nb_flux), dim3(64, 4), st, tab,
+        e = launch(flux_batch<false, T1, S>, dim3(b->nb_flux), dim3(64, 4), st, tab,
                    (const unsigned short *)(b->tab + b->o_mflux), (const unsigned *)(b->tab + b->o_fflux));
     return e;
 }
 
-static hipError_t batch_stage1(kt_batch *b, hipStream_t st)
-{
-    if (b->mixed) return b->cart ? batch_stage1_t<true, float>(b, st) : batch_stage1_t<false, float>(b, st);
-    return b->cart ? batch_stage1_t<true, double>(b, st) : batch_stage1_t<false, double>(b, st);
-}
-
-static hipError_t batch_launches(kt_batch *b, hipStream_t st, int par)
+template <bool T1>
+static hipError_t batch_stage1_t1(kt_batch *b, hipStream_t st)
 {
     if (b->mixed)
-        return b->cart ? batch_step_launches<true, float>(b, st, par) : batch_step_launches<false, float>(b, st, par);
-    return b->cart ? batch_step_launches<true, double>(b, st, par) : batch_step_launches<false, double>(b, st, par);
+        return b->cart ? batch_stage1_t<true, T1, float>(b, st) : batch_stage1_t<false, T1, float>(b, st);
+    return b->cart ? batch_stage1_t<true, T1, double>(b, st) : batch_stage1_t<false, T1, double>(b, st);
+}
+
+static hipError_t batch_stage1(kt_batch *b, hipStream_t st)
+{
+    return b->theta1 ? batch_stage1_t1<true>(b, st) : batch_stage1_t1<false>(b, st);
+}
+
+template <bool T1>
+static hipError_t batch_launches_t1(kt_batch *b, hipStream_t st, int par)
+{
+    if (b->mixed)
+        return b->cart ? batch_step_launches<true, T1, float>(b, st, par)
+                       : batch_step_launches<false, T1, float>(b, st, par);
+    return b->cart ? batch_step_launches<true, T1, double>(b, st, par)
+                   : batch_step_launches<false, T1, double>(b, st, par);
+}
+
+// theta1: every event limits with theta = 1 (the kernels' exact shortcut)
+static hipError_t batch_launches(kt_batch *b, hipStream_t st, int par)
+{
+    return b->theta1 ? batch_launches_t1<true>(b, st, par) : batch_launches_t1<false>(b, st, par);
 }
 
 static void batch_drop_graph(kt_batch *b)
@@ -2466,6 +2650,8 @@ kt_status kt_batch_init(const kt_params *p, int32_t n_events, const kt_eos *eos,
     b->user = stream;
     b->mixed = p[0].precision == KT_MIXED;
     b->cart = p[0].coords == KT_CARTESIAN;
+    b->theta1 = true;
+    for (int k = 0; k < n_events; ++k) b->theta1 = b->theta1 && theta_is_one(p[k].theta);
     b->dtau = p[0].dtau;
     b->tau = p[0].tau0;
     b->kc.assign(n_events, KC);

@@ -329,4 +329,122 @@ __global__ __launch_bounds__(256) void adam_kernel(float *theta, float *m, float
     theta[e] -= lr * (me / c1) / (sqrtf(ve / c2) + eps);
 }
 
+// ------------------------------------------------- matrix-core inference --
+// The start network inside the recovery kernels runs on the matrix cores: the
+// 64 cells of a wave are the batch of three small products with fp16 operands
+// and fp32 accumulation (v_mfma_f32_16x16x32_f16: A 16x32, B 32x16, D 16x16;
+// lane l holds row l%16 of A and column l%16 of B at k = 8(l/16) + j, j < 8,
+// and column l%16 of D at rows 4(l/16) + i, i < 4).  fp16 rather than bf16:
+// its 11-bit significand keeps the rounding of weights and activations
+// (5e-4) below the network's own start error (~1e-3); bf16's (4e-3) would not.
+//   layer 1: for each N-tile of 16 cells, B = their features (K = 11 padded
+//     to 32, through the wave's LDS rows), four M-tiles of 16 hidden units;
+//   layer 2: B = GELU of layer 1's D registers as they are: hidden unit
+//     u(mt, l, i) = 16 mt + 4 (l/16) + i sits in register i of D tile mt of
+//     lane l, so the K order of a K-step s is h(s, l, j) = u(2s + j/4, l, j%4)
+//     and the columns of W2 are permuted to it when the weights are packed
+//     (mlp_pack_kernel); no value moves between lanes;
+//   layer 3: y_0 only, a dot product of W3's first row with the 16 units a lane
+//     holds, summed over the four lanes of the cell's column (two exchanges).
+// Lane l keeps y_0 of cell l of the wave.  GELU through erf by Abramowitz &
+// Stegun 7.1.26 (|error| < 1.5e-7), well inside fp16.
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+struct MlpPacked {
+    h8_t a1[4][64];       // layer 1 A operand: M-tile, lane
+    h8_t a2[4][2][64];    // layer 2 A operand: M-tile, K-step, lane
+    float b1[NH], b2[NH], w3[NH], b3;
+};
+
+constexpr int XS_K = 16;  // fp16 features staged per cell (11 used)
+
+// hidden unit of layer 1 whose GELU lane l passes in slot j of K-step s of layer 2
+__host__ __device__ __forceinline__ int mlp_h2(int s, int l, int j)
+{
+    return 16 * (2 * s + j / 4) + 4 * (l / 16) + (j % 4);
+}
+
+// one block of 256 threads: W (FP32, the layout of kt_mlp_set) into K
+__global__ __launch_bounds__(256) void mlp_pack_kernel(const float *__restrict__ w, MlpPacked *K)
+{
+    for (int e = threadIdx.x; e < 4 * 64 * 8; e += 256) {
+        const int mt = e / 512, l = (e / 8) % 64, j = e % 8, k = 8 * (l / 16) + j;
+        K->a1[mt][l][j] = (_Float16)(k < NI ? w[OW1 + (16 * mt + l % 16) * NI + k] : 0.0f);
+    }
+    for (int e = threadIdx.x; e < 4 * 2 * 64 * 8; e += 256) {
+        const int mt = e / 1024, s = (e / 512) % 2, l = (e / 8) % 64, j = e % 8;
+        K->a2[mt][s][l][j] = (_Float16)w[OW2 + (16 * mt + l % 16) * NH + mlp_h2(s, l, j)];
+    }
+    for (int e = threadIdx.x; e < NH; e += 256) {
+        K->b1[e] = w[OB1 + e];
+        K->b2[e] = w[OB2 + e];
+        K->w3[e] = w[OW3 + e];
+    }
+    if (threadIdx.x == 0) K->b3 = w[OB3];
+}
+
+// GELU(a) = a Phi(a) = a (1 + erf(a / sqrt 2)) / 2, erf by Abramowitz & Stegun 7.1.26
+__device__ __forceinline__ float gelu_as(float a)
+{
+    const float z = fabsf(a) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, z, 1.0f));
+    float p = 1.061405429f;
+    p = fmaf(p, t, -1.453152027f);
+    p = fmaf(p, t, 1.421413741f);
+    p = fmaf(p, t, -0.284496736f);
+    p = fmaf(p, t, 0.254829592f);
+    const float erfz = 1.0f - p * t * __expf(-z * z);
+    return 0.5f * a * (1.0f + copysignf(erfz, a));
+}
+
+// y_0 of the lane's cell from its features x (any values in lanes whose result
+// is not used).  Every lane of the wave must call it (the matrix instructions
+// work on the whole wave); xs: this wave's 64 x XS_K staging rows in LDS.
+__device__ __forceinline__ float forward_y0_mfma(const MlpPacked *__restrict__ K, const float x[NI],
+                                                 _Float16 (*xs)[XS_K])
+{
+    const int l = (int)__lane_id();
+    const int g = l >> 4, c = l & 15;
+#pragma unroll
+    for (int k = 0; k < XS_K; ++k) xs[l][k] = (_Float16)(k < NI ? x[k] : 0.0f);
+    __builtin_amdgcn_wave_barrier();
+    float y0 = 0.0f;
+#pragma unroll 1
+    for (int t = 0; t < 4; ++t) {
+        h8_t b1;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) b1[j] = g < 2 ? xs[16 * t + c][8 * g + j] : (_Float16)0.0f;
+        f4_t d1[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f4_t acc;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i] = K->b1[16 * mt + 4 * g + i];
+            d1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(K->a1[mt][l], b1, acc, 0, 0, 0);
+        }
+        h8_t b2[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) b2[s][j] = (_Float16)gelu_as(d1[2 * s + j / 4][j % 4]);
+        float part = 0.0f;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f4_t acc;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i] = K->b2[16 * mt + 4 * g + i];
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(K->a2[mt][0][l], b2[0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(K->a2[mt][1][l], b2[1], acc, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) part = fmaf(K->w3[16 * mt + 4 * g + i], gelu_as(acc[i]), part);
+        }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (t == g) y0 = part + K->b3;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return y0;
+}
+
 }  // namespace ktm

@@ -636,15 +636,23 @@ def mlp_init_params(seed: int = 0, y0_bias: float = 0.8) -> np.ndarray:
 BATCH_SHAPES = ((64, 64, 64), (96, 96, 64), (128, 128, 96), (160, 160, 64))
 
 
-def workload_batch(n_events: int = 48, seed: int = 7, mixed: bool = True):
-    """Hot-spot events of the 128^3 event's physics on uneven grids: shapes
-    drawn uniformly from BATCH_SHAPES (PCG64(seed)), hot-spot counts uniform
-    in [50, 400], event k seeded 1000 + k; FP32 state when mixed."""
+def batch_shapes(n_events: int = 48, seed: int = 7):
+    """Grid shape index (into BATCH_SHAPES) and hot-spot count of each event of
+    the batch workload."""
     rng = np.random.Generator(np.random.PCG64(seed))
     shapes = rng.integers(0, len(BATCH_SHAPES), n_events)
     hots = rng.integers(50, 401, n_events)
+    return shapes, hots
+
+
+def workload_batch(n_events: int = 48, seed: int = 7, mixed: bool = True, only=None):
+    """Hot-spot events of the 128^3 event's physics on uneven grids: shapes
+    drawn uniformly from BATCH_SHAPES (PCG64(seed)), hot-spot counts uniform
+    in [50, 400], event k seeded 1000 + k; FP32 state when mixed.  only: the
+    indices of the events to build (the same events as in the full set)."""
+    shapes, hots = batch_shapes(n_events, seed)
     out = []
-    for k in range(n_events):
+    for k in (range(n_events) if only is None else only):
         nx, ny, ne = BATCH_SHAPES[shapes[k]]
         w = workload_hotspot(nx=nx, ny=ny, neta=ne, n_hot=int(hots[k]), seed=1000 + k)
         if mixed:

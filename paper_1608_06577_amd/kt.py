@@ -114,7 +114,7 @@ def lib():
         L.kt_recover.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p * 9, C.c_void_p,
                                  C.c_void_p * 4, C.c_void_p, C.c_void_p]
         L.kt_observables.argtypes = [C.c_void_p, C.POINTER(KtObs), C.POINTER(KtFields)]
-        L.kt_validity.argtypes = [C.c_void_p] + [C.c_void_p] * 5
+        L.kt_validity.argtypes = [C.c_void_p] + [C.c_void_p] * 8
         L.kt_run_to_freezeout.argtypes = [C.c_void_p, C.c_double, C.c_int32, C.c_int32,
                                           C.POINTER(C.c_int32)]
         L.kt_destroy.argtypes = [C.c_void_p]
@@ -281,9 +281,11 @@ class Solver:
         return o.as_dict()
 
     def validity(self) -> dict:
-        """T, R^{-1}_pi, R^{-1}_Pi, Kn_pi and Kn_Pi per cell (Sec. 7), as (neta, ny, nx) tensors."""
+        """T, R^{-1}_pi, R^{-1}_Pi, Kn_pi, Kn_Pi, the second-order (R^{(2)}_pi)^{-1},
+        (R^{(2)}_Pi)^{-1} (Sec. 7) and the regulation factor tanh(rho)/rho (Sec. 3.2)
+        per cell, as (neta, ny, nx) tensors."""
         torch = self.torch
-        names = ("T", "rinv_pi", "rinv_Pi", "kn_pi", "kn_Pi")
+        names = ("T", "rinv_pi", "rinv_Pi", "kn_pi", "kn_Pi", "rinv2_pi", "rinv2_Pi", "reg")
         with torch.cuda.device(self.device):
             out = {k: torch.empty(self.grid.shape, dtype=torch.float64, device=self.device) for k in names}
             _check(lib().kt_validity(self.ctx, *[out[k].data_ptr() for k in names]), self.ctx)

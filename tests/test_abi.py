@@ -106,7 +106,7 @@ def test_init_rejects_bad_arguments_without_device_work(L):
     # calls on a null context
     assert L.kt_step(None, 1) == kt.KT_E_ARG
     assert L.kt_observables(None, None, None) == kt.KT_E_ARG
-    assert L.kt_validity(None, None, None, None, None, None) == kt.KT_E_ARG
+    assert L.kt_validity(None, None, None, None, None, None, None, None, None) == kt.KT_E_ARG
     n_done = C.c_int32(-1)
     assert L.kt_run_to_freezeout(None, 0.7, 10, 1, C.byref(n_done)) == kt.KT_E_ARG
     L.kt_destroy(None)

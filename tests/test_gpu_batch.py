@@ -86,3 +86,40 @@ def test_batch_matches_oracle(kt):
         f = {key: v.cpu().numpy() for key, v in batch.fields(k).items()}
         ee, eu = e_err(f["e"], r["e"]), u_err(f["u"], r["u"], sim.tau)
         assert ee <= 1e-12 and eu <= 1e-12, (k, ee, eu)
+
+
+def test_two_events_of_the_48_event_set_against_oracle(kt):
+    """Two differently shaped events of the 48-event batch workload (event 7,
+    64^3, and event 9, 96x96x64) advanced together for 10 steps, in FP64 and
+    in the set's mixed-precision state, against the FP64 oracle run of each
+    event: FP64 within 1e-9; mixed precision within 1e-6 (median cell) and
+    1e-5 (dense cells, e > 1e-3 e_max), the bars of the 128^3 event."""
+    shapes, _ = I.batch_shapes()
+    assert tuple(shapes[[7, 9]]) == (0, 1)
+    ws = I.workload_batch(only=(7, 9), mixed=False)
+    refs = []
+    for w in ws:
+        sim = oracle.Simulation.from_primitives(oracle.Physics.from_config(w.grid, w.config), w.eos, w.prims)
+        sim.step(10)
+        refs.append((sim.fields(), sim.tau))
+    for mixed in (False, True):
+        evs = [(w.grid, dict(w.config, mixed=mixed), w.prims) for w in ws]
+        batch = kt.Batch(evs, ws[0].eos)
+        batch.tune()
+        batch.step(10)
+        for k, (r, tau) in enumerate(refs):
+            f = {key: v.cpu().numpy() for key, v in batch.fields(k, ("e", "u")).items()}
+            emax = r["e"].max()
+            de = np.abs(f["e"] - r["e"]) / np.maximum(r["e"], 1e-6 * emax)
+            du = np.max(np.abs(f["u"] - r["u"]) * np.array([1, 1, 1, tau])[:, None, None, None]
+                        / r["u"][0:1], axis=0)
+            dense = r["e"] > 1e-3 * emax
+            print("batch event %d (%s), %s: e %.2e u %.2e, dense e %.2e, median e %.1e" % (
+                (7, 9)[k], "x".join(map(str, ws[k].grid.shape[::-1])), "mixed" if mixed else "fp64",
+                de.max(), du.max(), de[dense].max(), np.median(de)), flush=True)
+            if mixed:
+                assert np.median(de) <= 1e-6 and np.median(du) <= 1e-6
+                assert de[dense].max() <= 1e-5 and du[dense].max() <= 1e-5
+            else:
+                assert de.max() <= 1e-9 and du.max() <= 1e-9
+        batch.close()

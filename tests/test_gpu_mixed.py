@@ -61,18 +61,20 @@ def run_mixed(kt, w, nsteps, band=0):
 
 
 def test_mixed_gubser_200_steps(kt):
-    """Viscous Gubser flow, 32^3 cells of 0.1 fm.  The 3.2 fm box is small: its
-    outflow corners (r ~ 1.7-2 fm) amplify any perturbation (there the FP32
-    differences grow from 1e-6 at step 50 to 1e-4 at step 200), so the bar
-    holds on the cells six or more cells from the x and y boundaries, the band
-    the analytic Gubser comparisons leave out as well."""
+    """Viscous Gubser flow, 32^3 cells of 0.1 fm, 200 steps: e and u within
+    1e-4 of the FP64 oracle on the whole box.  The 3.2 fm box is small: its
+    outflow corners (r ~ 1.7-2 fm) amplify any perturbation most, and pi there
+    reaches 1e-4 of e + P; pi is held to 1e-4 on the cells six or more cells
+    from the x and y boundaries (the band the analytic Gubser comparisons leave
+    out as well) and to 2e-4 on the whole box."""
     w = I.workload_gubser_viscous(n=32)
     full, _ = run_mixed(kt, w, 200)
     errs, gpu = run_mixed(kt, w, 200, band=6)
     print("mixed gubser32 200 steps: whole box", {k: "%.2e" % v for k, v in full.items()},
           "| without the 6-cell edge band", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    assert full["e"] <= 1e-4 and full["u"] <= 1e-4, full
     assert errs["e"] <= 1e-4 and errs["u"] <= 1e-4 and errs["pi"] <= 1e-4, errs
-    assert full["e"] <= 1e-3 and full["u"] <= 1e-3 and full["pi"] <= 1e-3, full
+    assert full["pi"] <= 2e-4, full
     assert gpu.observables()["n_nan"] == 0
 
 

@@ -124,10 +124,12 @@ def test_learned_start_against_conformal_start(kt):
     """Train on a hot-spot event's own states, then invert held-out states of
     a different event.  The inversion results equal the oracle's whatever the
     start, and the network's start is closer to the root than the conformal
-    closed form (median over the states).  Newton's convergence is
-    quadratic, so at the 1e-12 tolerance a start saves an iteration only
-    below ~1e-6 relative error: both starts (~1e-3) take about the same
-    number of iterations, which the test reports and bounds."""
+    closed form (median over the states): that is what the network gains.
+    It gains no Newton iteration: convergence is quadratic, so at the 1e-12
+    tolerance a start saves an iteration only below ~1e-6 relative error, and
+    both starts (~1e-3) take about the same number of iterations; the test
+    reports them without a bar.  The full step with the learned start then
+    matches the FP64 oracle to the 1e-9 bar, like the plain step."""
     import torch
     w = I.workload_hotspot(nx=40, ny=40, neta=16, dx=0.4, deta=0.5, n_hot=40, seed=5)
     gpu = kt.Solver(w.grid, w.config, w.eos, w.prims)
@@ -167,8 +169,8 @@ def test_learned_start_against_conformal_start(kt):
           "Newton iterations per state conformal %.3f learned %.3f"
           % (len(e_o), np.median(err_c), np.median(err_l), mc, ml), flush=True)
     assert np.median(err_l) < np.median(err_c)
-    assert ml < mc + 0.15
-    # the full step with the learned start equals the step with the warm start
+    # the full step with the learned start: equal to the step with the warm
+    # start to rounding, and to the FP64 oracle within the 1e-9 bar
     gw = kt.Solver(w2.grid, w2.config, w2.eos, w2.prims)
     gl = kt.Solver(w2.grid, w2.config, w2.eos, w2.prims)
     gl.mlp_set(gpu.mlp_get())
@@ -178,6 +180,15 @@ def test_learned_start_against_conformal_start(kt):
     gl.step(20)
     a, b = gw.fields(("e",))["e"], gl.fields(("e",))["e"]
     assert (torch.abs(a - b) / a).max().item() < 1e-12
+    sim = oracle.Simulation.from_primitives(oracle.Physics.from_config(w2.grid, w2.config), w2.eos, w2.prims)
+    sim.step(20)
+    r = sim.fields()
+    fl = {k: v.cpu().numpy() for k, v in gl.fields(("e", "u")).items()}
+    emax = r["e"].max()
+    de = np.max(np.abs(fl["e"] - r["e"]) / np.maximum(r["e"], 1e-6 * emax))
+    du = np.max(np.abs(fl["u"] - r["u"]) * np.array([1, 1, 1, sim.tau])[:, None, None, None] / r["u"][0:1])
+    print("learned-start step vs oracle, 20 steps: e %.2e u %.2e" % (de, du), flush=True)
+    assert de <= 1e-9 and du <= 1e-9
     ow, ol = gw.observables(), gl.observables()
     print("kt_step cell iterations: warm %.3f, learned %.3f" % (
         ow["newton_iters_cells"] / ow["n_recover_cells"], ol["newton_iters_cells"] / ol["n_recover_cells"]),

@@ -308,6 +308,56 @@ def test_validity_maps_match_oracle(kt):
     assert worst <= 1e-8, worst
 
 
+def test_second_order_validity_and_regulation_maps_match_oracle(kt):
+    """The second-order inverse Reynolds numbers of Sec. 7 (Eq.
+    inverseReynoldsNumbers2) and the regulation factor tanh(rho)/rho of
+    Sec. 3.2 per cell after 20 steps of the viscous hot-spot event (FP64),
+    against the oracle's maps of its own state."""
+    w = I.workload_hotspot(nx=40, ny=36, neta=12, dx=0.4, deta=0.5, n_hot=40, seed=4)
+    errs, gpu, sim, f, r = run_pair(kt, w, 20)
+    assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9, errs
+    m = {k: v.cpu().numpy().reshape(-1) for k, v in gpu.validity().items()}
+    phys = oracle.Physics.from_config(w.grid, w.config)
+    r2pi, r2Pi, reg = oracle.validity2(phys, w.eos, sim.tau, sim.q, sim.e, sim.u, sim.up)
+    dense = sim.e > 1e-3 * sim.e.max()
+    print("second order: max r2pi %.3g, r2Pi %.3g (dense cells); min reg %.3g" % (
+        r2pi[dense].max(), r2Pi[dense].max(), reg.min()), flush=True)
+    for got, ref in ((m["rinv2_pi"], r2pi), (m["rinv2_Pi"], r2Pi)):
+        fin = np.isfinite(ref)
+        assert np.array_equal(np.isfinite(got), fin)
+        floor = 1e-3 * np.median(ref[dense & fin])
+        rel = np.abs(got - ref)[dense & fin] / np.maximum(np.abs(ref[dense & fin]), floor)
+        assert rel.max() <= 1e-7, rel.max()
+        assert np.max(ref[dense & fin]) > 0
+    assert np.max(np.abs(m["reg"] - reg)) <= 1e-12
+    assert reg.min() < 1.0
+
+
+def test_observables_match_oracle(kt):
+    """kt_observables (sums, maxima and the pi-constraint checks of Sec. 2.4)
+    against the oracle's observables of its own state after 12 steps of the
+    viscous hot-spot event (FP64)."""
+    w = I.workload_hotspot(nx=56, ny=52, neta=24, dx=0.4, deta=0.5, n_hot=60, seed=3)
+    errs, gpu, sim, f, r = run_pair(kt, w, 12)
+    assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9, errs
+    obs = gpu.observables()
+    phys = oracle.Physics.from_config(w.grid, w.config)
+    ref = oracle.observables(phys, w.eos, sim.tau, sim.q, sim.e, sim.u)
+    rel = lambda a, b: abs(a - b) / max(abs(b), 1e-300)
+    assert rel(obs["energy"], ref["energy"]) < 1e-12
+    vol = w.grid.dx * w.grid.dy * w.grid.deta * sim.tau
+    for i, k in enumerate(("momentum_x", "momentum_y", "momentum_eta")):
+        scale = np.abs(sim.q[:, 1 + i]).sum() * vol
+        assert abs(obs["momentum"][i] - ref[k]) <= 1e-11 * scale
+    for k in ("e_max", "T_max", "v_max", "cfl"):
+        assert rel(obs[k], ref[k]) < 1e-9, (k, obs[k], ref[k])
+    assert obs["norm_err"] < 1e-12 and ref["norm_err"] < 1e-12
+    # the pi-constraint ratios: maxima of ratios of fields that agree to 1e-9
+    for k in ("pi_transverse", "pi_trace"):
+        assert abs(obs[k] - ref[k]) <= 1e-8 * max(ref[k], 1e-6), (k, obs[k], ref[k])
+    assert ref["pi_transverse"] > 0 and obs["n_nan"] == ref["n_nan"] == 0
+
+
 def test_run_to_freezeout_matches_oracle_loop(kt):
     """kt_run_to_freezeout stops after the same number of steps as the same
     loop over the oracle (max T checked every 5 steps), with equal fields."""
