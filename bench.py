@@ -1,11 +1,14 @@
 """Benchmark: Heun steps of the 128^3 non-conformal viscous hot-spot event (FP64).
 
 One step is one full Heun step of the KT scheme (two stages, two recoveries)
-over the whole 128^3 grid.  Prints one JSON line:
+over the whole 128^3 grid, replayed from a captured hipGraph.  Prints one
+JSON line:
   value        cell-updates/s (128^3 cells x steps / seconds), inputs resident in HBM
-  roofline     the KT stage kernel: algorithmic bytes per launch / mean launch time
-               (HIP events on the library's stream, recorded in the timed region)
-  cpu_baseline the FP64 CPU oracle on a bounded sample of the same event
+  roofline     the whole step against HBM: 103 algorithmic values (824 B in FP64) per
+               cell and step x cells / the mean step time (HIP events over the timed
+               region); traffic: rocprofv3 counter bytes of one step
+  cpu_baseline the FP64 CPU oracle on a bounded sample of the same event, on all
+               host threads and on one
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--copy-probe]
 """
@@ -25,23 +28,28 @@ METRIC = "cell-updates/s per Heun step (128^3 viscous), % HBM peak; learned vs N
 # algorithmic values moved per cell (8 bytes each in FP64):
 #   stage 1 reads q^n (15), u^n (4), u^{n-1} (4), e^n (1) and writes q* (15)            = 39
 #   stage 2 reads q* (15), u* (4), e* (1), u^n (4), q^n (15) and writes q^{n+1} (15)     = 54
-#   one Heun step moves 103 values when recovery is fused with the stages
-STAGE_VALUES = (39, 54)
+#   the two recoveries write u and e (10)                                              = 10
+#   one Heun step moves 103 values (p is recomputed, not stored)
 STEP_VALUES = 103
-# algorithmic values per cell and launch of each kernel class, averaged over the two stages:
+# mixed-precision state: T^{tau mu} (4 of the 15 q components) and u (4) stay 8 bytes,
+# the other 11 q components and e are 4 bytes: 492 B per cell and step
+STEP_BYTES_MIXED = 492.0
+# algorithmic values per cell and launch of each kernel class, averaged over the two stages
+# (diagnostics: the per-kernel fractions):
 #   flux     reads q (15) and the stage accumulator (15), writes it (15)           = 45
 #   sources  reads q (15), u (4), u_prev (4), e, p and, in stage 2, q^n (15);
 #            writes 15                                                             = 40 / 55
 #   recover  reads q (15), e; writes e, p, u (4) and the 10 regulated pi           = 32
 #   faces    reads 9 components of q and e; writes v^-, v^+ of 3 faces (6)         = 16
 KERNEL_VALUES = {"flux": 45.0, "sources": 47.5, "recover": 32.0, "faces": 16.0}
-# HBM bytes per launch of the FP64 kernels on this event, from rocprofv3 FETCH_SIZE x 2.000 and
-# WRITE_SIZE x 1.000 (scale factors of a 256 MiB device copy), profiles/kt_step_hotspot128_fp64.md;
-# valid for the kernel sources and compiler flags whose hash is TRAFFIC_SOURCES (else the traffic
-# is reported as null)
-TRAFFIC_SOURCES = "c9ea6676b92e54a7"
-TRAFFIC_BYTES = {"faces": 6.519e8 + 1.613e8, "flux": 0.5 * (1.3829e9 + 1.3833e9) + 2.517e8,
-                 "sources": 0.5 * (7.486e8 + 1.1006e9) + 2.517e8, "recover": 2.552e8 + 3.215e8}
+# launches of each class per Heun step
+LAUNCHES_PER_STEP = {"flux": 2, "sources": 2, "recover": 2, "faces": 2}
+# HBM bytes per launch of the FP64 batched kernels of one step on this event, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE scaled by what the counters read for a plain device copy
+# (profiles/); valid for the kernel sources and compiler flags whose hash is TRAFFIC_SOURCES
+# (else the traffic is reported as null)
+TRAFFIC_SOURCES = "none"
+TRAFFIC_BYTES = {}
 KERNEL_NAMES = {"flux": "flux_kernel (KT flux divergence + stage update)",
                 "sources": "sources_kernel (App. B sources + stage update)",
                 "recover": "recover_kernel (Newton inversion + regulator)",
@@ -89,23 +97,76 @@ def copy_probe():
                       "launches": 3}), flush=True)
 
 
+def copy_gbs(torch) -> float:
+    """Bandwidth of a plain 1 GiB device-to-device copy (bytes read + written / time)."""
+    n = (1 << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(5):
+        y.copy_(x)
+    stop.record()
+    torch.cuda.synchronize()
+    gbs = 5 * 2 * n * 8 / (start.elapsed_time(stop) * 1e-3) / 1e9
+    del x, y
+    return gbs
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, budget_s):
+    """The FP64 oracle on the host's cores: the mean over up to 3 Heun steps of
+    the 128^3 event on all threads, then one step on one thread (the paper's
+    serial CPU timings, Tables 980ti_compare and k20M_compare, are one core)."""
     import oracle
     phys = oracle.Physics.from_config(w.grid, w.config)
+    n_all = oracle.num_threads()
     t0 = time.perf_counter()
     sim = oracle.Simulation.from_primitives(phys, w.eos, w.prims)
     t_init = time.perf_counter() - t0
     steps = 0
     t1 = time.perf_counter()
-    while steps < 1 or (time.perf_counter() - t1 < budget_s and steps < 5):
+    while steps < 1 or (time.perf_counter() - t1 < budget_s and steps < 3):
         sim.step(1)
         steps += 1
     dt = time.perf_counter() - t1
+    oracle.set_num_threads(1)
+    t2 = time.perf_counter()
+    sim.step(1)
+    dt1 = time.perf_counter() - t2
+    oracle.set_num_threads(n_all)
     return {"value": w.grid.ncells * steps / dt, "unit": "cell-updates/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%d Heun step(s) of the same %dx%dx%d event from its initial state "
-                      "(%.1f s, plus %.1f s initial recovery)" % (steps, w.grid.nx, w.grid.ny,
-                                                                  w.grid.neta, dt, t_init)}
+            "cores": n_all, "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": "%d Heun step(s) of the same %dx%dx%d event from its initial state on %d "
+                      "threads (%.1f s, plus %.1f s initial recovery)" % (
+                          steps, w.grid.nx, w.grid.ny, w.grid.neta, n_all, dt, t_init),
+            "single_thread": {"value": w.grid.ncells / dt1, "unit": "cell-updates/s", "cores": 1,
+                              "sample": "the next Heun step of the same event on 1 thread "
+                                        "(%.1f s)" % dt1}}
+
+
+def time_graph_steps(torch, batch, warmup, steps):
+    """Mean time of one replayed step graph (HIP events on the caller's stream,
+    which the replays are ordered between)."""
+    batch.step(warmup)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    batch.step(steps)
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
 
 
 def learned_leg(args, kt, I, torch):
@@ -169,33 +230,48 @@ def learned_leg(args, kt, I, torch):
     return out
 
 
-def lattice_leg(args, rec, w, ncell, start, stop):
+def lattice_leg(args, rec, w, ncell, torch, kt, I):
     """The headline event and step count in FP64 with the paper's own physics
     of Sec. 2: the lattice-QCD EOS table and the bulk viscosity zeta/s(T)
     (Eq. zetas, normalisation 1, T_c = 200 MeV) instead of the synthetic EOS
-    and zeta/s = 0.1 (1/3 - c_s^2)."""
-    import torch
-    from paper_1608_06577_amd import inputs as I
-    from paper_1608_06577_amd import kt
-
+    and zeta/s = 0.1 (1/3 - c_s^2).  Replayed from the step graph."""
     eos_l = I.eos_lattice_table()
     cfg = dict(w.config, zeta_model=1, zeta_coef=1.0, zeta_tc=0.2 / I.HBARC)
-    sl = kt.Solver(w.grid, cfg, eos_l, w.prims, device="cuda:0")
-    sl.step(args.warmup)
-    torch.cuda.synchronize()
-    start.record()
-    sl.step(args.steps)
-    stop.record()
-    torch.cuda.synchronize()
-    ms_l = start.elapsed_time(stop) / args.steps
-    obs_l = sl.observables()
+    bl = kt.Batch([(w.grid, cfg, w.prims)], eos_l, device="cuda:0")
+    bl.tune()
+    ms_l = time_graph_steps(torch, bl, args.warmup, args.steps)
+    obs_l = bl.observables(0)
     rec["variants"]["lattice_eos"] = {
         "ms_per_step": ms_l, "value": ncell / (ms_l * 1e-3), "state": "FP64",
         "eos": "lattice-QCD trace-anomaly fit, 4096 nodes", "zeta_over_s": "zeta/s(T), T_c = 200 MeV",
+        "step_hbm_frac": STEP_VALUES * 8.0 * ncell / (ms_l * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "newton_iters_per_cell": obs_l["newton_iters_cells"] / max(1, obs_l["n_recover_cells"]),
         "n_nan": obs_l["n_nan"]}
-    sl.close()
+    bl.close()
     print("bench: lattice-QCD EOS and zeta/s(T) %.3f ms/step" % ms_l, file=sys.stderr, flush=True)
+
+
+def eager_kernel_times(kt, torch, w, cfg, n_steps):
+    """Per-launch times of the four kernel classes of the eager step (HIP events
+    around each launch on the library's stream; outside the timed region), and
+    the eager step time."""
+    s = kt.Solver(w.grid, cfg, w.eos, w.prims, device="cuda:0")
+    s.step(2)
+    s.profile(True)
+    s.step(n_steps)
+    prof = s.profile_read()
+    s.profile(False)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    s.step(n_steps)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / n_steps
+    obs = s.observables()
+    s.close()
+    per = {k: prof[k + "_ms"] / max(1, prof[k + "_launches"]) for k in kt.PROFILE_CLASSES}
+    return per, ms, obs
 
 
 def main():
@@ -213,44 +289,35 @@ def main():
 
     w = I.workload_hotspot(nx=args.n, ny=args.n, neta=args.n)
     ncell = w.grid.ncells
-    solver = kt.Solver(w.grid, w.config, w.eos, w.prims, device="cuda:0")
-    print("bench: %s, warmup %d steps" % (w.name, args.warmup), file=sys.stderr, flush=True)
-    # every kernel class is timed during the warm-up; the dominant class (largest
-    # total time) is then timed alone over the timed region, so that only its
-    # launches carry event records
-    solver.profile(True)
-    solver.step(args.warmup)
-    warm = solver.profile_read()
-    per = {k: warm[k + "_ms"] / max(1, warm[k + "_launches"]) for k in kt.PROFILE_CLASSES}
-    dom = max(kt.PROFILE_CLASSES, key=lambda k: warm[k + "_ms"])
-    solver.profile(True, classes=(dom,) if args.warmup > 0 else None)
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    solver.step(args.steps)
-    stop.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / args.steps
-    prof = solver.profile_read()
-    solver.profile(False)
-    obs = solver.observables()
-    if args.warmup == 0:
-        per = {k: prof[k + "_ms"] / max(1, prof[k + "_launches"]) for k in kt.PROFILE_CLASSES}
-        dom = max(kt.PROFILE_CLASSES, key=lambda k: prof[k + "_ms"])
-    per[dom] = prof[dom + "_ms"] / max(1, prof[dom + "_launches"])
-    print("bench: timed %d steps, %.3f ms/step; per launch (%s in the timed region, the others "
-          "in the warm-up): %s" % (args.steps, ms, dom, ", ".join("%s %.3f ms" % kv for kv in per.items())),
-          file=sys.stderr, flush=True)
+    # the headline: the FP64 step replayed from its captured graph (a batch of
+    # one event: the same kernels per cell, tau kept on the device)
+    print("bench: %s, FP64, step graph, warmup %d steps" % (w.name, args.warmup), file=sys.stderr, flush=True)
+    b = kt.Batch([(w.grid, w.config, w.prims)], w.eos, device="cuda:0")
+    kc = b.tune()
+    ms = time_graph_steps(torch, b, args.warmup, args.steps)
+    obs = b.observables(0)
+    b.close()
     value = ncell / (ms * 1e-3)
-    dom_avg_s = per[dom] * 1e-3
-    dom_bytes = 8.0 * ncell * KERNEL_VALUES[dom]
-    achieved = dom_bytes / dom_avg_s / 1e9
-    traffic = TRAFFIC_BYTES[dom] if kernel_sources_hash() == TRAFFIC_SOURCES else None
+    step_bytes = STEP_VALUES * 8.0 * ncell
+    achieved = step_bytes / (ms * 1e-3) / 1e9
+    print("bench: timed %d graph steps, %.3f ms/step, %.3g cell-updates/s, %.3f of the HBM roofline"
+          % (args.steps, ms, value, achieved / HBM_PEAK_GBS), file=sys.stderr, flush=True)
+    # diagnostics outside the timed region: per-kernel times of the eager step
+    per, ms_eager, _ = eager_kernel_times(kt, torch, w, w.config, min(args.steps, 10))
+    print("bench: eager step %.3f ms; per launch: %s" % (
+        ms_eager, ", ".join("%s %.3f ms" % kv for kv in per.items())), file=sys.stderr, flush=True)
+    cgbs = copy_gbs(torch)
+    traffic = None
+    if kernel_sources_hash() == TRAFFIC_SOURCES and TRAFFIC_BYTES:
+        traffic = sum(TRAFFIC_BYTES[k] * LAUNCHES_PER_STEP[k] for k in TRAFFIC_BYTES)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": KERNEL_NAMES[dom], "bytes_per_launch": dom_bytes,
-            "mean_launch_ms": per[dom],
-            "per_launch_ms": per}
+            "kernel": "one Heun step (the captured graph of its launches)",
+            "bytes_per_launch": step_bytes, "mean_launch_ms": ms,
+            "copy_kernel_gbs": cgbs,
+            "per_kernel": {k: {"launch_ms": per[k], "launches_per_step": LAUNCHES_PER_STEP[k],
+                               "frac": 8.0 * ncell * KERNEL_VALUES[k] / (per[k] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                           for k in kt.PROFILE_CLASSES}}
     rec = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -261,53 +328,46 @@ def main():
                    "dtau": w.config["dtau"], "eta_over_s": w.config["eta_s"],
                    "zeta_over_s": "0.1 (1/3 - c_s^2)", "eos": "tabulated, 4096 nodes",
                    "precision": "fp64", "inversion_start": "conformal closed-form root",
-                   "step_hbm_frac": STEP_VALUES * 8.0 * value / (HBM_PEAK_GBS * 1e9),
+                   "flux_eta_planes": kc[0],
                    "paper_context_ms_per_step": {"gtx980ti_fp32_128cube_table": 244.45,
                                                  "gtx980ti_program_summary": 38400.0}},
         "roofline": roof,
         "diagnostics": dict({k: obs[k] for k in ("tau", "n_nan", "n_floor", "n_clamp", "n_fallback",
                                                  "n_fallback_faces", "e_max", "cfl")},
+                            eager_ms_per_step=ms_eager,
                             newton_iters_per_cell=obs["newton_iters_cells"] / max(1, obs["n_recover_cells"]),
                             newton_iters_per_face_state=obs["newton_iters_faces"] / max(1, obs["n_recover_faces"])),
     }
-    solver.close()
     # the mixed-precision state on the same event and step count (reported beside the FP64 line)
     cfg_m = dict(w.config)
     cfg_m["mixed"] = True
-    sm = kt.Solver(w.grid, cfg_m, w.eos, w.prims, device="cuda:0")
-    sm.step(args.warmup)
-    torch.cuda.synchronize()
-    start.record()
-    sm.step(args.steps)
-    stop.record()
-    torch.cuda.synchronize()
-    ms_m = start.elapsed_time(stop) / args.steps
+    bm = kt.Batch([(w.grid, cfg_m, w.prims)], w.eos, device="cuda:0")
+    bm.tune()
+    ms_m = time_graph_steps(torch, bm, args.warmup, args.steps)
+    bm.close()
+    per_m, ms_m_eager, _ = eager_kernel_times(kt, torch, w, cfg_m, min(args.steps, 10))
     rec["variants"] = {"mixed_precision": {
         "ms_per_step": ms_m, "value": ncell / (ms_m * 1e-3),
-        "state": "T^{tau mu} FP64; pi, Pi, e, p, u, face speeds FP32; inversion FP64"}}
-    sm.close()
-    print("bench: mixed precision %.3f ms/step" % ms_m, file=sys.stderr, flush=True)
+        "step_hbm_frac": STEP_BYTES_MIXED * ncell / (ms_m * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "eager_ms_per_step": ms_m_eager, "per_kernel_launch_ms": per_m,
+        "state": "T^{tau mu} and u FP64; pi, Pi, e, p, face speeds FP32; inversion FP64"}}
+    print("bench: mixed precision %.3f ms/step (eager %.3f)" % (ms_m, ms_m_eager), file=sys.stderr, flush=True)
     # the same event and step count, FP64, with the lattice-QCD EOS table (Sec. 2)
     if not args.no_lattice:
-        lattice_leg(args, rec, w, ncell, start, stop)
+        lattice_leg(args, rec, w, ncell, torch, kt, I)
     if not args.no_batch:
         # 48 hot-spot events on uneven grids, FP32 state, one launch per kernel for all
-        # events, one step replayed as a hipGraph, flux tiling autotuned per grid shape
+        # events, one step replayed as a hipGraph, tiling autotuned
         evs = I.workload_batch()
         ncb = sum(e.grid.ncells for e in evs)
         batch = kt.Batch([(e.grid, e.config, e.prims) for e in evs], evs[0].eos, device="cuda:0")
         del evs
-        kc = batch.tune()
-        batch.step(args.warmup)
-        torch.cuda.synchronize()
-        start.record()
-        batch.step(args.steps)
-        stop.record()
-        torch.cuda.synchronize()
-        ms_b = start.elapsed_time(stop) / args.steps
+        kcb = batch.tune()
+        ms_b = time_graph_steps(torch, batch, args.warmup, args.steps)
         rec["variants"]["batch_48_events"] = {
             "ms_per_step": ms_b, "value": ncb / (ms_b * 1e-3), "cells": ncb,
-            "shapes": [list(s) for s in I.BATCH_SHAPES], "flux_eta_planes": sorted(set(kc)),
+            "step_hbm_frac": STEP_BYTES_MIXED * ncb / (ms_b * 1e-3) / (HBM_PEAK_GBS * 1e9),
+            "shapes": [list(s) for s in I.BATCH_SHAPES], "flux_eta_planes": sorted(set(kcb)),
             "state": "mixed precision; all events per launch; step replayed as a hipGraph"}
         batch.close()
         print("bench: batch of 48 events %.3f ms/step (%.3g cell-updates/s)" % (ms_b, ncb / (ms_b * 1e-3)),
