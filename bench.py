@@ -293,7 +293,7 @@ def main():
     # one event: the same kernels per cell, tau kept on the device)
     print("bench: %s, FP64, step graph, warmup %d steps" % (w.name, args.warmup), file=sys.stderr, flush=True)
     b = kt.Batch([(w.grid, w.config, w.prims)], w.eos, device="cuda:0")
-    kc = b.tune()
+    blocks = b.tune()
     ms = time_graph_steps(torch, b, args.warmup, args.steps)
     obs = b.observables(0)
     b.close()
@@ -328,7 +328,8 @@ def main():
                    "dtau": w.config["dtau"], "eta_over_s": w.config["eta_s"],
                    "zeta_over_s": "0.1 (1/3 - c_s^2)", "eos": "tabulated, 4096 nodes",
                    "precision": "fp64", "inversion_start": "conformal closed-form root",
-                   "flux_eta_planes": kc[0],
+                   "flux_block": {"eta_planes": blocks[0][0], "cells_x": blocks[0][1],
+                                  "cells_y": 256 // blocks[0][1]},
                    "paper_context_ms_per_step": {"gtx980ti_fp32_128cube_table": 244.45,
                                                  "gtx980ti_program_summary": 38400.0}},
         "roofline": roof,
@@ -361,13 +362,17 @@ def main():
         evs = I.workload_batch()
         ncb = sum(e.grid.ncells for e in evs)
         batch = kt.Batch([(e.grid, e.config, e.prims) for e in evs], evs[0].eos, device="cuda:0")
+        shapes_b = [tuple(e.grid.shape[::-1]) for e in evs]
         del evs
-        kcb = batch.tune()
+        blocks_b = batch.tune()
         ms_b = time_graph_steps(torch, batch, args.warmup, args.steps)
         rec["variants"]["batch_48_events"] = {
             "ms_per_step": ms_b, "value": ncb / (ms_b * 1e-3), "cells": ncb,
             "step_hbm_frac": STEP_BYTES_MIXED * ncb / (ms_b * 1e-3) / (HBM_PEAK_GBS * 1e9),
-            "shapes": [list(s) for s in I.BATCH_SHAPES], "flux_eta_planes": sorted(set(kcb)),
+            "shapes": [list(s) for s in I.BATCH_SHAPES],
+            "flux_block_per_shape": {"x".join(map(str, sh)): {"eta_planes": bl[0], "cells_x": bl[1],
+                                                              "cells_y": 256 // bl[1]}
+                                     for sh, bl in zip(shapes_b, blocks_b)},
             "state": "mixed precision; all events per launch; step replayed as a hipGraph"}
         batch.close()
         print("bench: batch of 48 events %.3f ms/step (%.3g cell-updates/s)" % (ms_b, ncb / (ms_b * 1e-3)),

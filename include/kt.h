@@ -169,6 +169,7 @@ size_t kt_workspace_bytes(const kt_params *p, const kt_eos *eos);
 kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0,
                   void *d_ws, size_t ws_bytes, hipStream_t stream, kt_ctx **out);
 
+
 /* Enqueue n_steps >= 0 full Heun steps (Sec. 3.1, Eqs. step1-finalStep with
  * s = 2; order of Sec. 4.3): stage 1 at tau^n, recovery and regulation of q*
  * and stage 2 at tau^{n+1}, Heun average, recovery and regulation of
@@ -321,10 +322,15 @@ kt_status kt_profile_read(kt_ctx *c, kt_profile *out);
  * n_events entries; kt_batch_init synchronises the stream.
  * kt_batch_step enqueues n_steps steps (asynchronous; the graph runs on a
  * stream of the batch ordered after and before the caller's stream).
- * kt_batch_tune times the batched flux launch, all events together, with 1,
- * 2, 4 and 8 eta planes per block on the live state (which it does not
- * change), keeps the fastest for every event (kc_out[n_events], nullable)
- * and synchronises.
+ * kt_batch_tune chooses the flux kernel's block: per distinct grid shape its
+ * cells in (x, y), 64 x 4, 32 x 8 or 16 x 16, then for the whole launch its
+ * eta planes, 2 or 4.  It times the batched stage 1 (sources and flux
+ * launches, all events together) on the live state, which it does not change:
+ * every width of one shape with the other shapes held at their current choice
+ * (shapes with the most cells first), then both plane counts; it keeps the
+ * fastest, writes the choices per event (kc_out: eta planes, tile_out: the
+ * block's width in x, 64, 32 or 16; each an array of n_events, nullable),
+ * rebuilds the step and synchronises.  Results do not depend on the choice.
  * kt_batch_observables is kt_observables of one event.
  * --------------------------------------------------------------------- */
 typedef struct kt_batch kt_batch;
@@ -334,7 +340,13 @@ kt_status kt_batch_init(const kt_params *p, int32_t n_events, const kt_eos *eos,
                         const kt_init_state *s0, void *d_ws, size_t ws_bytes, hipStream_t stream,
                         kt_batch **out);
 kt_status kt_batch_step(kt_batch *b, int32_t n_steps);
-kt_status kt_batch_tune(kt_batch *b, int32_t *kc_out);
+kt_status kt_batch_tune(kt_batch *b, int32_t *kc_out, int32_t *tile_out);
+/* Set the flux kernel's block per event without timing (for instance to reuse
+ * an earlier kt_batch_tune result): kc[e] eta planes, 2 or 4 and the same for
+ * every event; tile_x[e] in {64, 32, 16} cells in x (then 4, 8 or 16 cells in
+ * y); arrays of n_events.  Rebuilds the step and synchronises; KT_E_ARG for
+ * values outside these sets.  Results do not depend on the choice. */
+kt_status kt_batch_set_flux_blocks(kt_batch *b, const int32_t *kc, const int32_t *tile_x);
 kt_status kt_batch_observables(kt_batch *b, int32_t event, kt_obs *host_out, const kt_fields *dev_out);
 void kt_batch_destroy(kt_batch *b);
 const char *kt_batch_last_error(const kt_batch *b);

@@ -89,6 +89,13 @@ def lib():
         L.ora_observables.argtypes = [P, E, C.c_double, dp, dp, dp, dp]
         L.ora_validity2.argtypes = [P, E, C.c_double, dp, dp, dp, dp, C.c_void_p, C.c_void_p,
                                     C.c_void_p]
+        L.ora_expand.argtypes = [P, C.c_double, C.c_int64, dp, dp, dp, dp]
+        L.ora_pi_dependent.argtypes = [C.c_double, C.c_int32, C.c_int64, dp, dp]
+        L.ora_recover_reduced.argtypes = [P, E, C.c_double, C.c_int64, dp, dp, dp, ip, ip, ip]
+        L.ora_init_reduced.argtypes = [P, E, C.c_double, dp, dp, dp, dp]
+        L.ora_step_reduced.argtypes = [P, E, dp, dp, dp, dp, dp, C.c_int32, C.POINTER(_Stats),
+                                       C.POINTER(C.c_int64)]
+        L.ora_step_reduced.restype = C.c_int
         _lib = L
     return _lib
 
@@ -367,3 +374,93 @@ class Simulation:
                     u=self.u.T.reshape((4,) + s).copy(),
                     up=self.up.T.reshape((4,) + s).copy(),
                     q=self.q.T.reshape((NQ,) + s).copy())
+
+
+# ------------------------------------------------------------ reduced storage --
+#: positions in the 15-component q of the reduced evolved vector
+#: (T^{tau mu}, pi^{xx}, pi^{xy}, pi^{x eta}, pi^{yy}, pi^{y eta}, Pi)
+RED_IDX = (0, 1, 2, 3, 8, 9, 10, 11, 12, 14)
+NR = len(RED_IDX)
+
+
+def pi_dependent(tau, cartesian, u, q):
+    """q (n, 15) with pi^{tau mu} and pi^{eta eta} replaced by the values that
+    Eqs. pi_tautau .. pi_etaeta (Sec. 2.4) give from the five independent
+    components and u (n, 4)."""
+    q = np.array(q, dtype=np.float64, order="C")
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    lib().ora_pi_dependent(float(tau), int(cartesian), q.shape[0], _dp(u), _dp(q))
+    return q
+
+
+def recover_reduced(phys: Physics, eos, tau, r):
+    """Recovery of n reduced states r (n, 10): e, u (n, 4), Newton iterations,
+    fixed-point passes (negative where the fixed point did not converge), flags."""
+    ref = EOSRef(eos)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    n = r.shape[0]
+    e, u = np.empty(n), np.empty((n, 4))
+    it, ps, fl = (np.empty(n, np.int32) for _ in range(3))
+    P = phys.c()
+    lib().ora_recover_reduced(C.byref(P), C.byref(ref.c), float(tau), n, _dp(r), _dp(e), _dp(u),
+                              _ip(it), _ip(ps), _ip(fl))
+    return e, u, it, ps, fl
+
+
+class ReducedSimulation:
+    """Oracle state with reduced storage (Sec. 2.4: five pi components and three
+    u components; the rest rebuilt algebraically): r (n, 10), e, u3 (n, 3),
+    up3 and tau; steps in place.  fields() expands to all components."""
+
+    def __init__(self, phys: Physics, eos, tau0: float, q: np.ndarray):
+        self.phys = phys
+        self.eos_ref = EOSRef(eos)
+        self.tau = float(tau0)
+        n = phys.ncells
+        q = np.asarray(q, dtype=np.float64).reshape(n, NQ)
+        self.r = np.ascontiguousarray(q[:, list(RED_IDX)])
+        self.e = np.empty(n)
+        self.u3 = np.empty((n, 3))
+        self.up3 = np.empty((n, 3))
+        self.step_count = 0
+        self.stats = _Stats()
+        self.fp = np.zeros(2, np.int64)       # fixed-point passes, cells not converged
+        self._P = phys.c()
+        lib().ora_init_reduced(C.byref(self._P), C.byref(self.eos_ref.c), self.tau, _dp(self.r),
+                               _dp(self.e), _dp(self.u3), _dp(self.up3))
+
+    @classmethod
+    def from_primitives(cls, phys: Physics, eos, prims):
+        e, u, pi, Pi = aos_from_prims(prims)
+        q = tmunu(phys, eos, prims.tau0, e, u, pi, Pi)
+        return cls(phys, eos, prims.tau0, q)
+
+    def step(self, n: int = 1):
+        tau = C.c_double(self.tau)
+        rc = lib().ora_step_reduced(C.byref(self._P), C.byref(self.eos_ref.c), C.byref(tau),
+                                    _dp(self.r), _dp(self.e), _dp(self.u3), _dp(self.up3), int(n),
+                                    C.byref(self.stats), self.fp.ctypes.data_as(C.POINTER(C.c_int64)))
+        if rc != 0:
+            raise MemoryError("oracle step could not allocate its work arrays")
+        self.tau = tau.value
+        self.step_count += n
+        return self
+
+    def expanded(self, tau=None, u3=None):
+        """Full q (n, 15) and u (n, 4) of the state (u3 at tau, default the current)."""
+        n = self.phys.ncells
+        q, u = np.empty((n, NQ)), np.empty((n, 4))
+        u3 = self.u3 if u3 is None else np.ascontiguousarray(u3)
+        lib().ora_expand(C.byref(self._P), float(self.tau if tau is None else tau), n, _dp(self.r),
+                         _dp(u3), _dp(q), _dp(u))
+        return q, u
+
+    def shape(self):
+        return (self.phys.neta, self.phys.ny, self.phys.nx)
+
+    def fields(self):
+        s = self.shape()
+        q, u = self.expanded()
+        _, up = self.expanded(self.tau - self.phys.dtau, self.up3)
+        return dict(e=self.e.reshape(s).copy(), u=u.T.reshape((4,) + s).copy(),
+                    up=up.T.reshape((4,) + s).copy(), q=q.T.reshape((NQ,) + s).copy())

@@ -1004,3 +1004,256 @@ void ora_validity2(const ora_params *P, const ora_eos *eos, double tau, const do
                 }
             }
 }
+
+/* ==================================================================== */
+/* Reduced storage (Sec. 2.4, the paragraph with Eqs. pi_tautau ..       */
+/* pi_etaeta; Sec. 4.2, last paragraph on memory).  Only the five        */
+/* components pi^{xx}, pi^{xy}, pi^{x eta}, pi^{yy}, pi^{y eta} of the    */
+/* shear stress and the three u^x, u^y, u^eta of the flow are kept; the   */
+/* other five of pi follow from u_mu pi^{mu nu} = 0 and g_{mu nu}         */
+/* pi^{mu nu} = 0, and u^tau from u^mu u_mu = 1 (Sec. 2.4).  The step is   */
+/* the one above, applied to the state expanded to all components:       */
+/*   - the evolved vector is (T^{tau mu}, the five pi, Pi); the other five */
+/*     pi components are not evolved but rebuilt from the five and the    */
+/*     cell's velocity wherever a cell's full state is needed (sources,   */
+/*     and the cells whose reconstruction gives the face states);         */
+/*   - the recovery solves for (e, u) and the dependent pi together: with */
+/*     pi^{tau mu} of the current velocity iterate, Newton's recovery     */
+/*     gives the next velocity, until it stops changing;                  */
+/*   - the regulator acts on the full tensor and rescales the five (and   */
+/*     Pi as in the full step).                                           */
+/* Reading taken: the paper states only that the remaining components are */
+/* determined algebraically; the face states use the reconstructed cell    */
+/* values of all components, the cells' dependent ones included.          */
+/* ==================================================================== */
+
+#define NR 10   /* reduced evolved vector: T^{tau mu} (4), five pi, Pi */
+static const int RED_IDX[NR] = {0, 1, 2, 3, 8, 9, 10, 11, 12, 14};   /* positions in q[NQ] */
+
+/* pi^{eta eta}, pi^{tau eta}, pi^{tau y}, pi^{tau x}, pi^{tau tau} of q from its
+ * five independent components and the contravariant 3-velocity v^i = u^i / u^tau:
+ * Eq. pi_etaeta, then the four orthogonality relations Eq. pi_tautau and the
+ * three printed after it, each written as the paper writes it (tau^2 -> 1 in
+ * Cartesian coordinates). */
+static void pi_dependent(double tau, int cart, const double u[4], double q[NQ])
+{
+    const double t2 = cart ? 1.0 : tau * tau;
+    const double vx = u[1] / u[0], vy = u[2] / u[0], ve = u[3] / u[0];
+    const double pxx = q[8], pxy = q[9], pxe = q[10], pyy = q[11], pye = q[12];
+    const double pee = (pxx * (vx * vx - 1.0) + pyy * (vy * vy - 1.0) + 2.0 * pxy * vx * vy
+                        + 2.0 * t2 * (pxe * vx * ve + pye * vy * ve))
+                       / (t2 * (1.0 - t2 * ve * ve));
+    const double pte = pxe * vx + pye * vy + t2 * pee * ve;
+    const double pty = pxy * vx + pyy * vy + t2 * pye * ve;
+    const double ptx = pxx * vx + pxy * vy + t2 * pxe * ve;
+    const double ptt = ptx * vx + pty * vy + t2 * pte * ve;
+    q[4] = ptt; q[5] = ptx; q[6] = pty; q[7] = pte; q[13] = pee;
+}
+
+/* u^tau from u^mu u_mu = 1 at tau (Sec. 2.4) */
+static void u_full(double tau, int cart, const double *u3, double u[4])
+{
+    const double t2 = cart ? 1.0 : tau * tau;
+    u[1] = u3[0]; u[2] = u3[1]; u[3] = u3[2];
+    u[0] = sqrt(1.0 + u[1] * u[1] + u[2] * u[2] + t2 * u[3] * u[3]);
+}
+
+/* full state of a cell from its reduced state r[NR] and flow u3 at tau */
+static void expand_cell(const ora_params *P, double tau, const double *r, const double *u3,
+                        double q[NQ], double u[4])
+{
+    for (int c = 0; c < NQ; ++c) q[c] = 0.0;
+    for (int k = 0; k < NR; ++k) q[RED_IDX[k]] = r[k];
+    u_full(tau, P->cartesian, u3, u);
+    if (P->eta_s > 0.0) pi_dependent(tau, P->cartesian, u, q);
+}
+
+/* Recovery of (e, u) from the reduced state at tau: fixed point of
+ *   u_{k+1} = recover(T^{tau mu}, pi^{tau mu}(five, v(u_k)), Pi)
+ * from u_0 = u_start (the cell's flow before the stage, normalised at tau; null:
+ * (1, 0, 0, 0), i.e. pi^{tau mu} = 0), stopped when no component of u moves by
+ * more than FP_TOL u^tau (the eta component times tau), or after FP_MAX passes
+ * (counted as not converged).  The state's dependent components are those of the
+ * final u.  Returns the flags of the last recovery. */
+static const double FP_TOL = 1e-14;
+static const int FP_MAX = 100;
+
+static int recover_reduced(const ora_params *P, const ora_eos *eos, double tau, const double *r,
+                           const double *u_start, double *e_out, double u_out[4], int *iters,
+                           int *passes, int *conv)
+{
+    const double t2 = P->cartesian ? 1.0 : tau * tau;
+    double q[NQ], u[4] = {1.0, 0.0, 0.0, 0.0};
+    if (u_start) u_full(tau, P->cartesian, u_start, u);
+    int flags = 0, it_sum = 0, k = 0;
+    *conv = 0;
+    for (k = 0; k < FP_MAX; ++k) {
+        for (int c = 0; c < NQ; ++c) q[c] = 0.0;
+        for (int m = 0; m < NR; ++m) q[RED_IDX[m]] = r[m];
+        if (P->eta_s > 0.0) pi_dependent(tau, P->cartesian, u, q);
+        double un[4], e;
+        int it;
+        flags = recover(P, eos, tau, q, &e, un, &it);
+        it_sum += it;
+        *e_out = e;
+        double dmax = 0.0;
+        for (int m = 0; m < 4; ++m) {
+            double d = fabs(un[m] - u[m]) * (m == 3 ? sqrt(t2) : 1.0) / un[0];
+            if (d > dmax) dmax = d;
+        }
+        for (int m = 0; m < 4; ++m) u[m] = un[m];
+        if ((flags & FL_FLOOR) || !(P->eta_s > 0.0) || dmax <= FP_TOL) { *conv = 1; ++k; break; }
+    }
+    for (int m = 0; m < 4; ++m) u_out[m] = u[m];
+    *iters = it_sum;
+    *passes = k;
+    return flags;
+}
+
+typedef struct {
+    int64_t passes, not_converged;
+} ora_fp_stats;
+
+/* recover every cell of the reduced state, reset floor cells, regulate (the
+ * full tensor; the five and Pi are rescaled) */
+static void recover_all_reduced(const ora_params *P, const ora_eos *eos, double tau, double *r,
+                                const double *u_start, double *e, double *u3, ora_stats *st,
+                                ora_fp_stats *fs, int do_regulate)
+{
+    const int64_t n = (int64_t)P->nx * P->ny * P->neta;
+    int64_t it_sum = 0, nfl = 0, ncl = 0, nfb = 0, np = 0, nnc = 0;
+#pragma omp parallel for schedule(static) reduction(+ : it_sum, nfl, ncl, nfb, np, nnc)
+    for (int64_t c = 0; c < n; ++c) {
+        double *rc = r + NR * c;
+        double u[4];
+        int it, passes, conv;
+        int f = recover_reduced(P, eos, tau, rc, u_start ? u_start + 3 * c : NULL, e + c, u, &it,
+                                &passes, &conv);
+        if ((f & FL_FLOOR) && P->floor_resets_q) {
+            for (int m = 0; m < NR; ++m) rc[m] = 0.0;
+            rc[0] = P->e_floor;
+        }
+        if (do_regulate) {
+            double q[NQ];
+            for (int m = 0; m < NQ; ++m) q[m] = 0.0;
+            for (int m = 0; m < NR; ++m) q[RED_IDX[m]] = rc[m];
+            if (P->eta_s > 0.0) pi_dependent(tau, P->cartesian, u, q);
+            regulate_cell(P, eos, tau, q, e[c], u);
+            for (int m = 4; m < NR; ++m) rc[m] = q[RED_IDX[m]];
+        }
+        for (int m = 0; m < 3; ++m) u3[3 * c + m] = u[m + 1];
+        it_sum += it;
+        nfl += (f & FL_FLOOR) != 0;
+        ncl += (f & FL_CLAMP) != 0;
+        nfb += (f & FL_FALLBACK) != 0;
+        np += passes;
+        nnc += !conv;
+    }
+    if (st) {
+        st->newton_iters += it_sum;
+        st->n_floor += nfl;
+        st->n_clamp += ncl;
+        st->n_fallback += nfb;
+        st->n_recover += n;
+    }
+    if (fs) {
+        fs->passes += np;
+        fs->not_converged += nnc;
+    }
+}
+
+/* full arrays (q: n x 15, u: n x 4) of a reduced state (r: n x 10, u3: n x 3) at tau */
+void ora_expand(const ora_params *P, double tau, int64_t n, const double *r, const double *u3,
+                double *q, double *u)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c) expand_cell(P, tau, r + NR * c, u3 + 3 * c, q + NQ * c, u + 4 * c);
+}
+
+/* the dependent components of n cells (q: n x 15 in and out, u: n x 4) */
+void ora_pi_dependent(double tau, int32_t cartesian, int64_t n, const double *u, double *q)
+{
+    for (int64_t c = 0; c < n; ++c) pi_dependent(tau, cartesian, u + 4 * c, q + NQ * c);
+}
+
+/* standalone reduced recovery of n cells (no regulation, no floor reset) */
+void ora_recover_reduced(const ora_params *P, const ora_eos *eos, double tau, int64_t n,
+                         const double *r, double *e, double *u, int32_t *iters, int32_t *passes,
+                         int32_t *flags)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c) {
+        int it, ps, conv;
+        int f = recover_reduced(P, eos, tau, r + NR * c, NULL, e + c, u + 4 * c, &it, &ps, &conv);
+        if (iters) iters[c] = it;
+        if (passes) passes[c] = conv ? ps : -ps;
+        if (flags) flags[c] = f;
+    }
+}
+
+/* initial recovery of a reduced state at tau0 (no regulation, as ora_init); u_prev = u */
+void ora_init_reduced(const ora_params *P, const ora_eos *eos, double tau0, double *r,
+                      double *e, double *u3, double *up3)
+{
+    const int64_t n = (int64_t)P->nx * P->ny * P->neta;
+    recover_all_reduced(P, eos, tau0, r, NULL, e, u3, NULL, NULL, 0);
+    memcpy(up3, u3, sizeof(double) * 3 * n);
+}
+
+/* n_steps Heun steps of the reduced state in place, the step of ora_step on the
+ * expanded state (the previous flow u_prev is normalised at tau - dtau, the time
+ * of its level; the first step's u_prev is u^0).  The recovery of q* starts its
+ * fixed point from u^n, that of q^{n+1} from u*.  fp_stats (nullable): passes
+ * of the recovery's fixed point and cells where it did not converge. */
+int ora_step_reduced(const ora_params *P, const ora_eos *eos, double *tau_io, double *r,
+                     double *e, double *u3, double *up3, int32_t n_steps, ora_stats *st,
+                     int64_t *fp_stats)
+{
+    const int64_t n = (int64_t)P->nx * P->ny * P->neta;
+    double *qf = malloc(sizeof(double) * NQ * n);
+    double *rhs = malloc(sizeof(double) * NQ * n);
+    double *uf = malloc(sizeof(double) * 4 * n);
+    double *upf = malloc(sizeof(double) * 4 * n);
+    double *rs = malloc(sizeof(double) * NR * n);
+    double *us3 = malloc(sizeof(double) * 3 * n);
+    double *es = malloc(sizeof(double) * n);
+    if (!qf || !rhs || !uf || !upf || !rs || !us3 || !es) {
+        free(qf); free(rhs); free(uf); free(upf); free(rs); free(us3); free(es);
+        return 1;
+    }
+    ora_fp_stats fs = {0, 0};
+    double tau = *tau_io;
+    for (int s = 0; s < n_steps; ++s) {
+        const double tau1 = tau + P->dtau;
+        /* stage 1 at tau on (q^n, e^n, u^n, u^{n-1}) */
+        ora_expand(P, tau, n, r, u3, qf, uf);
+#pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < n; ++c) u_full(tau - P->dtau, P->cartesian, up3 + 3 * c, upf + 4 * c);
+        ctx_t C1 = {P, eos, tau, qf, e, uf, upf, st};
+        rhs_all(&C1, rhs);
+        for (int64_t c = 0; c < n; ++c)
+            for (int k = 0; k < NR; ++k) rs[NR * c + k] = r[NR * c + k] + P->dtau * rhs[NQ * c + RED_IDX[k]];
+        recover_all_reduced(P, eos, tau1, rs, u3, es, us3, st, &fs, 1);
+        /* stage 2 at tau^{n+1} on (q*, e*, u*, u^n) */
+        ora_expand(P, tau1, n, rs, us3, qf, uf);
+#pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < n; ++c) u_full(tau1 - P->dtau, P->cartesian, u3 + 3 * c, upf + 4 * c);
+        ctx_t C2 = {P, eos, tau1, qf, es, uf, upf, st};
+        rhs_all(&C2, rhs);
+        for (int64_t c = 0; c < n; ++c)
+            for (int k = 0; k < NR; ++k) {
+                double rss = rs[NR * c + k] + P->dtau * rhs[NQ * c + RED_IDX[k]];
+                r[NR * c + k] = (r[NR * c + k] + rss) / 2.0;
+            }
+        memcpy(up3, u3, sizeof(double) * 3 * n);
+        recover_all_reduced(P, eos, tau1, r, us3, e, u3, st, &fs, 1);
+        tau = tau1;
+    }
+    *tau_io = tau;
+    if (fp_stats) {
+        fp_stats[0] += fs.passes;
+        fp_stats[1] += fs.not_converged;
+    }
+    free(qf); free(rhs); free(uf); free(upf); free(rs); free(us3); free(es);
+    return 0;
+}

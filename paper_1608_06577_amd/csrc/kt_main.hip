@@ -35,7 +35,7 @@ using namespace ktd;
 
 namespace {
 
-constexpr int KC = 4;      // consecutive eta planes per thread in flux_kernel (eta faces carried)
+constexpr int KC = 2;      // eta planes per flux block of a single event (2 or 4, the instantiated ones)
 
 // ------------------------------------------------------------------ grid --
 
@@ -629,110 +629,140 @@ __global__ __launch_bounds__(256) void sources_kernel(Phys P, Eos E, double tau,
     sources_body<CART, STAGE2, S>(P, E, tau, F, qnT, qnP, outT, outP, bx, by, bz, T);
 }
 
-// Flux part of one Euler stage: for a 64 x 4 x KC block of cells, the KT
-// flux divergence D = -sum_d (H_{+1/2} - H_{-1/2}) / d_d of every
-// component (Sec. 3.1), then
+// Flux part of one Euler stage: for a block of 4 waves of 16 x 4 cells (tw
+// waves along x and 4 / tw along y: 64 x 4, 32 x 8 or 16 x 16 cells) and KCC
+// eta planes, the KT flux divergence D = -sum_d (H_{+1/2} - H_{-1/2}) / d_d of
+// every component (Sec. 3.1), then
 //   stage 1: out = out + dtau D;   stage 2: out = (out + dtau D) / 2,
 // which with sources_kernel gives q + dtau C[q] and (qn + q + dtau C[q]) / 2.
-// Face coefficients come from face_speeds_kernel.  Each wave holds 16 x 4 cells
-// (x by y; lane = 16 row + column), so that a cell's y neighbours are mostly
-// other lanes' cells: every lane loads its own cell and one cell of the four
-// halo rows (y0-2, y0-1, y0+4, y0+5), and the stencil is assembled by lane
-// exchanges.  x faces: lane l computes the face on the left of its cell and
-// takes the right one from the next lane of its row (the last lane of a row
-// computes its right face itself); eta faces: the top face of plane k is the
-// bottom face of plane k+1 (kept in LDS per thread); y faces: two per cell.
-// Components are processed one at a time.
-// Hb: the block's LDS carry of the eta faces; kc: eta planes per block
-template <bool STAGE2, bool T1, typename S>
+// The block first stages the KT coefficients of all its faces (from
+// face_speeds_kernel) in LDS, then takes one component at a time through its
+// planes.  A component's eta stencil (planes k0-2 .. k0+KCC+1 of the lane's
+// column) is loaded once into registers and the eta face is carried from
+// plane to plane in a register, so the values a plane re-reads from its
+// neighbours were read moments before by the same block for the same
+// component and are still cached (taking all 15 components of a plane before
+// the next plane re-reads a plane only after the whole state of the previous
+// one has passed through L2).  Each wave holds 16 x 4 cells (x by y; lane =
+// 16 row + column), so that a cell's y neighbours are mostly other lanes'
+// cells: every lane loads its own cell and one cell of the four halo rows
+// (y0-2, y0-1, y0+4, y0+5), and the stencil is assembled by lane exchanges.
+// A lane computes the x face on each side of its cell and the y face on each
+// side (the coefficients of the far side from the neighbouring lane's LDS
+// slot, or from the block's edge slots).
+template <typename S, int KCC>
+struct FluxLds {
+    S x[KCC][2][256];       // c^-, c^+ of the x face left of each cell
+    S xr[KCC][2][16];       // ... of the x face right of the last column of each wave row (4 wave + row)
+    S y[KCC][2][256];       // ... of the y face below each cell
+    S yt[KCC][2][64];       // ... of the y face above the last row of each wave (16 wave + column)
+    S e[KCC + 1][2][256];   // ... of the eta face below each cell of planes k0 .. k0 + KCC
+};
+
+template <bool STAGE2, bool T1, typename S, int KCC>
 __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const double *qT, const S *qP,
-                                          const S *vf, double *outT, S *outP, double (*HbT)[256],
-                                          S (*Hb)[256], unsigned bx, unsigned by, unsigned bz, int kc)
+                                             const S *vf, double *outT, S *outP, FluxLds<S, KCC> &Lc,
+                                             unsigned bx, unsigned by, unsigned bz, int tw)
 {
     typedef S R;   // flux arithmetic of pi and Pi; T^{tau mu} is done in FP64
     const int lane = threadIdx.x;
-    const int tid = threadIdx.y * 64 + lane;
-    const int xl = lane & 15, r = lane >> 4;     // column and row of the lane in its wave
-    const int i = bx * 64 + threadIdx.y * 16 + xl;
-    const int j0 = by * 4;
+    const int w = threadIdx.y;
+    const int tid = w * 64 + lane;
+    const int xl = lane & 15, r = lane >> 4;
+    const int wx = w % tw, wy = w / tw;
+    const int i = bx * (16 * tw) + wx * 16 + xl;
+    const int j0 = by * (16 / tw) + wy * 4;
     const int j = j0 + r;
-    const int k0 = bz * kc;
+    const int k0 = bz * KCC;
+    const int m = min(KCC, P.neta - k0);        // planes of this block (>= 1)
     const idx_t plane = (idx_t)P.nx * P.ny;
     const idx_t SS = (idx_t)P.stride;
-    // lanes outside the grid compute on the cell their index wraps to (the last
-    // cell of a non-periodic direction); their results are not stored.  Cells
-    // that are in the grid then find their wrapped neighbours in the lanes
-    // next to them.
     const int ic = wrap(i, P.nx, P.periodic[0]);
     const int jc = wrap(j, P.ny, P.periodic[1]);
-    const int jh = wrap(j0 + (r < 2 ? r - 2 : r + 2), P.ny, P.periodic[1]);   // this lane's halo row
-    const int ifc = i <= P.nx ? i : P.nx;     // x face index of this lane
+    const int jh = wrap(j0 + (r < 2 ? r - 2 : r + 2), P.ny, P.periodic[1]);
+    const int ifc = i <= P.nx ? i : P.nx;
+    const int jfc = j <= P.ny ? (j < P.ny ? jc : P.ny) : jc;
     const bool out_ok = i < P.nx && j < P.ny;
-    const bool right = xl == 15 && out_ok;   // this lane also computes its right x face
     const int xm2 = wrap(i - 2, P.nx, P.periodic[0]), xm1 = wrap(i - 1, P.nx, P.periodic[0]);
     const int xp1 = wrap(i + 1, P.nx, P.periodic[0]), xp2 = wrap(i + 2, P.nx, P.periodic[0]);
     const S *vfx = vf + G.ox, *vfy = vf + G.oy, *vfe = vf + G.oe;
     const double f = P.dtau;
-    // evolved dissipative components: pi (if shear) and Pi (if bulk)
     const int c0 = P.shear ? PTT : BPI, c1 = P.bulk ? NQ : BPI;
-#pragma unroll 1
-    for (int kk = 0; kk < kc; ++kk) {
-        const int k = k0 + kk;
-        if (k >= P.neta) break;    // uniform over the block
-        const idx_t kp = (idx_t)k * plane;
-        const idx_t rowc = kp + (idx_t)jc * P.nx;
-        const idx_t s = rowc + ic;
-        const idx_t col = (idx_t)jc * P.nx + ic;
-        const int zm2 = wrap(k - 2, P.neta, P.periodic[2]), zm1 = wrap(k - 1, P.neta, P.periodic[2]);
-        const int zp1 = wrap(k + 1, P.neta, P.periodic[2]), zp2 = wrap(k + 2, P.neta, P.periodic[2]);
-        // face coefficients: x (left face, and the right one for the last lane of a row), y (both),
-        // eta (top; the bottom one in the block's first plane)
-        const idx_t fx = fidx_x(P.nx, P.ny, ifc, jc, k);
-        const R cmx = R(ld(vfx, fx)), cpx = R(ld(vfx + G.nfx, fx));
-        R cmr = R(0), cpr = R(0);
-        if (right) {
-            cmr = R(ld(vfx, fx + 1));
-            cpr = R(ld(vfx + G.nfx, fx + 1));
-        }
-        const idx_t fy0 = fidx_y(P.nx, P.ny, ic, jc, k), fy1 = fidx_y(P.nx, P.ny, ic, jc + 1, k);
-        const R cmy0 = R(ld(vfy, fy0)), cpy0 = R(ld(vfy + G.nfy, fy0));
-        const R cmy1 = R(ld(vfy, fy1)), cpy1 = R(ld(vfy + G.nfy, fy1));
-        const idx_t fe1 = fidx_e(P.nx, P.ny, ic, jc, k + 1);
-        const R cme = R(ld(vfe, fe1)), cpe = R(ld(vfe + G.nfe, fe1));
-        R cmb = R(0), cpb = R(0);
-        if (kk == 0) {
-            const idx_t fe0 = fidx_e(P.nx, P.ny, ic, jc, k);
-            cmb = R(ld(vfe, fe0));
-            cpb = R(ld(vfe + G.nfe, fe0));
-        }
-        const idx_t rx = kp + (idx_t)jc * P.nx;
-        const idx_t rh = kp + (idx_t)jh * P.nx + ic;
-        const idx_t e0 = col + (idx_t)zm2 * plane, e1 = col + (idx_t)zm1 * plane;
-        const idx_t e3 = col + (idx_t)zp1 * plane, e4 = col + (idx_t)zp2 * plane;
-        // divergence D of one component (array q, component offset co) in the
-        // arithmetic type RR, with the eta carry Hc.  The loads are issued
-        // together (no load waits on a branch), and each cell's slope along a
-        // direction is computed once.
-        auto divergence = [&](auto rtag, const auto *q, idx_t co, auto *Hc) {
-            typedef decltype(rtag) RR;
-            const RR th = RR(P.theta), h = RR(0.5);
-            const RR yc = RR(ld(q, co + s)), yh = RR(ld(q, co + rh));
-            const RR eb = RR(ld(q, co + e1)), ed = RR(ld(q, co + e3)), ee = RR(ld(q, co + e4));
-            // the first and last lane of a row read the two cells beyond its ends
-            RR edge1 = RR(0), edge2 = RR(0);
-            if (xl == 0 || xl == 15) {
-                edge1 = RR(ld(q, co + rx + (xl == 0 ? xm1 : xp1)));
-                edge2 = RR(ld(q, co + rx + (xl == 0 ? xm2 : xp2)));
+    // the block's face coefficients
+#pragma unroll
+    for (int kk = 0; kk < KCC; ++kk) {
+        if (kk < m) {
+            const int k = k0 + kk;
+            const idx_t fx = fidx_x(P.nx, P.ny, ifc, jc, k);
+            Lc.x[kk][0][tid] = ld(vfx, fx);
+            Lc.x[kk][1][tid] = ld(vfx + G.nfx, fx);
+            if (xl == 15) {
+                // (lanes outside the grid read a face that exists; their value is not used)
+                const idx_t fr = fidx_x(P.nx, P.ny, min(i + 1, P.nx), jc, k);
+                Lc.xr[kk][0][w * 4 + r] = ld(vfx, fr);
+                Lc.xr[kk][1][w * 4 + r] = ld(vfx + G.nfx, fr);
             }
-            // y neighbours j-2, j-1, j+1, j+2: rows r-2 .. r+2 of the wave where
-            // they exist, else halo rows (every exchange is taken by all lanes
-            // before any select)
-            const RR o32 = half_swap(yc), h32 = half_swap(yh);
-            const RR ya = r < 2 ? yh : o32;
-            const RR ye = r < 2 ? o32 : yh;
+            // (jfc: the face below the lane's row, the grid's top face for the row above
+            // the grid, whose lane is the upper neighbour of the grid's last row)
+            const idx_t fy0 = fidx_y(P.nx, P.ny, ic, jfc, k);
+            Lc.y[kk][0][tid] = ld(vfy, fy0);
+            Lc.y[kk][1][tid] = ld(vfy + G.nfy, fy0);
+            if (r == 3) {
+                const idx_t fy1 = fidx_y(P.nx, P.ny, ic, jc + 1, k);
+                Lc.yt[kk][0][w * 16 + xl] = ld(vfy, fy1);
+                Lc.yt[kk][1][w * 16 + xl] = ld(vfy + G.nfy, fy1);
+            }
+        }
+    }
+#pragma unroll
+    for (int kk = 0; kk <= KCC; ++kk) {
+        if (kk <= m) {
+            const idx_t fe = fidx_e(P.nx, P.ny, ic, jc, k0 + kk);
+            Lc.e[kk][0][tid] = ld(vfe, fe);
+            Lc.e[kk][1][tid] = ld(vfe + G.nfe, fe);
+        }
+    }
+    __syncthreads();
+    const idx_t col = (idx_t)jc * P.nx + ic;
+    idx_t zi[KCC + 4];     // the lane's column at planes k0-2 .. k0+KCC+1
+#pragma unroll
+    for (int t = 0; t < KCC + 4; ++t) zi[t] = col + (idx_t)wrap(k0 - 2 + t, P.neta, P.periodic[2]) * plane;
+    // (a lane's x face of the next lane in its row, or its own right face in the last column)
+    const int nb = tid + 1;
+    const int yup = r < 3 ? tid + 16 : -1;
+    auto component = [&](auto rtag, const auto *q, idx_t co, auto *out) {
+        typedef decltype(rtag) RR;
+        const RR th = RR(P.theta), h = RR(0.5);
+        RR z[KCC + 4], yh[KCC], e1[KCC], e2[KCC];
+        decltype(rtag) prev[KCC];
+#pragma unroll
+        for (int t = 0; t < KCC + 4; ++t) z[t] = RR(ld(q, co + zi[t]));
+#pragma unroll
+        for (int kk = 0; kk < KCC; ++kk) {
+            const idx_t kp = (idx_t)wrap(k0 + kk, P.neta, P.periodic[2]) * plane;
+            yh[kk] = RR(ld(q, co + kp + (idx_t)jh * P.nx + ic));
+            prev[kk] = RR(ld(out, co + kp + (idx_t)jc * P.nx + ic));
+            e1[kk] = RR(0);
+            e2[kk] = RR(0);
+            if (xl == 0 || xl == 15) {
+                const idx_t rx = kp + (idx_t)jc * P.nx;
+                e1[kk] = RR(ld(q, co + rx + (xl == 0 ? xm1 : xp1)));
+                e2[kk] = RR(ld(q, co + rx + (xl == 0 ? xm2 : xp2)));
+            }
+        }
+        RR Hb0 = face_H<RR>(z[1] + h * limited<T1>(z[0], z[1], z[2], th),
+                            z[2] - h * limited<T1>(z[1], z[2], z[3], th), RR(Lc.e[0][0][tid]),
+                            RR(Lc.e[0][1][tid]));
+#pragma unroll
+        for (int kk = 0; kk < KCC; ++kk) {
+            if (kk >= m) break;     // uniform over the block
+            const RR yc = z[kk + 2], eb = z[kk + 1], ed = z[kk + 3], ee = z[kk + 4];
+            const RR yhh = yh[kk], edge1 = e1[kk], edge2 = e2[kk];
+            const RR o32 = half_swap(yc), h32 = half_swap(yhh);
+            const RR ya = r < 2 ? yhh : o32;
+            const RR ye = r < 2 ? o32 : yhh;
             const RR mb = r == 3 ? h32 : yc, md = r == 0 ? h32 : yc;
             const RR yb = row_down(mb), yd = row_up(md);
-            // x neighbours from the lanes of the row
             const RR sb = row_prev(yc), sd = row_next(yc);
             const RR xb = xl == 0 ? edge1 : sb;
             const RR xd = xl == 15 ? edge1 : sd;
@@ -740,64 +770,47 @@ __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const
             const RR xa = xl == 0 ? edge2 : sa;
             const RR xe = xl == 15 ? edge2 : se;
             const RR xc = yc;
-            // x: the face left of the cell; the right one from the next lane (the row's last lane: its own)
+            const RR cmx = RR(Lc.x[kk][0][tid]), cpx = RR(Lc.x[kk][1][tid]);
+            const RR cmr = RR(xl == 15 ? Lc.xr[kk][0][w * 4 + r] : Lc.x[kk][0][nb & 255]);
+            const RR cpr = RR(xl == 15 ? Lc.xr[kk][1][w * 4 + r] : Lc.x[kk][1][nb & 255]);
+            const RR cmy0 = RR(Lc.y[kk][0][tid]), cpy0 = RR(Lc.y[kk][1][tid]);
+            const RR cmy1 = RR(yup >= 0 ? Lc.y[kk][0][yup] : Lc.yt[kk][0][w * 16 + xl]);
+            const RR cpy1 = RR(yup >= 0 ? Lc.y[kk][1][yup] : Lc.yt[kk][1][w * 16 + xl]);
+            const RR cme = RR(Lc.e[kk + 1][0][tid]), cpe = RR(Lc.e[kk + 1][1][tid]);
             const RR sxb = limited<T1>(xa, xb, xc, th), sxc = limited<T1>(xb, xc, xd, th),
                      sxd = limited<T1>(xc, xd, xe, th);
-            const RR Hx = face_H<RR>(xb + h * sxb, xc - h * sxc, RR(cmx), RR(cpx));
-            const RR Hown = face_H<RR>(xc + h * sxc, xd - h * sxd, RR(cmr), RR(cpr));
-            const RR Hnb = row_next(Hx);
-            RR D = (Hx - (right ? Hown : Hnb)) * RR(P.inv_dx);
-            // y
+            const RR Hx = face_H<RR>(xb + h * sxb, xc - h * sxc, cmx, cpx);
+            const RR Hown = face_H<RR>(xc + h * sxc, xd - h * sxd, cmr, cpr);
+            RR D = (Hx - Hown) * RR(P.inv_dx);
             const RR syb = limited<T1>(ya, yb, yc, th), syc = limited<T1>(yb, yc, yd, th),
                      syd = limited<T1>(yc, yd, ye, th);
-            D += (face_H<RR>(yb + h * syb, yc - h * syc, RR(cmy0), RR(cpy0))
-                - face_H<RR>(yc + h * syc, yd - h * syd, RR(cmy1), RR(cpy1))) * RR(P.inv_dy);
-            // eta: the bottom face is carried from the plane below except in the first plane
+            D += (face_H<RR>(yb + h * syb, yc - h * syc, cmy0, cpy0)
+                - face_H<RR>(yc + h * syc, yd - h * syd, cmy1, cpy1)) * RR(P.inv_dy);
             const RR sec = limited<T1>(eb, yc, ed, th), sed = limited<T1>(yc, ed, ee, th);
-            RR Hb0;
-            if (kk == 0) {
-                const RR ea = RR(ld(q, co + e0));
-                Hb0 = face_H<RR>(eb + h * limited<T1>(ea, eb, yc, th), yc - h * sec, RR(cmb), RR(cpb));
-            } else {
-                Hb0 = Hc[tid];
-            }
-            const RR Ht = face_H<RR>(yc + h * sec, ed - h * sed, RR(cme), RR(cpe));
-            Hc[tid] = Ht;
+            const RR Ht = face_H<RR>(yc + h * sec, ed - h * sed, cme, cpe);
             D += (Hb0 - Ht) * RR(P.inv_deta);
-            return D;
-        };
-#pragma unroll 1
-        for (int c = 0; c < PTT; ++c) {
-            const idx_t co = (idx_t)c * SS;
-            const double prev = ld(outT, co + s);    // s is a cell of the grid for every lane
-            const double D = divergence(0.0, qT, co, HbT[c]);
+            Hb0 = Ht;
             if (out_ok) {
-                const double t = prev + f * D;
-                st(outT, co + s, STAGE2 ? 0.5 * t : t);
+                const RR t = prev[kk] + RR(f) * D;
+                const idx_t kp = (idx_t)(k0 + kk) * plane;
+                st(out, co + kp + (idx_t)jc * P.nx + ic, STAGE2 ? RR(0.5) * t : t);
             }
         }
+    };
 #pragma unroll 1
-        for (int c = c0; c < c1; ++c) {
-            const idx_t co = (idx_t)(c - PTT) * SS;
-            const R prev = R(ld(outP, co + s));
-            const R D = divergence(R(0), qP, co, Hb[c - PTT]);
-            if (out_ok) {
-                const R t = prev + R(f) * D;
-                st(outP, co + s, STAGE2 ? R(0.5) * t : t);
-            }
-        }
-    }
+    for (int c = 0; c < PTT; ++c) component(0.0, qT, (idx_t)c * SS, outT);
+#pragma unroll 1
+    for (int c = c0; c < c1; ++c) component(R(0), qP, (idx_t)(c - PTT) * SS, outP);
 }
 
-template <bool STAGE2, bool T1, typename S>
+template <bool STAGE2, bool T1, typename S, int KCC>
 __global__ __launch_bounds__(256) void flux_kernel(Phys P, FaceGeo G, const double *qT, const S *qP,
-                                                   const S *vf, double *outT, S *outP, int kc)
+                                                      const S *vf, double *outT, S *outP, int tw)
 {
-    __shared__ double HbT[PTT][256];      // eta face below the current plane: T^{tau mu}
-    __shared__ S Hb[NQ - PTT][256];       // and pi, Pi
+    __shared__ FluxLds<S, KCC> Lc;
     unsigned bx, by, bz;
     xcd_block3(bx, by, bz);
-    flux_body<STAGE2, T1, S>(P, G, qT, qP, vf, outT, outP, HbT, Hb, bx, by, bz, kc);
+    flux_body<STAGE2, T1, S, KCC>(P, G, qT, qP, vf, outT, outP, Lc, bx, by, bz, tw);
 }
 
 // recovery of every cell at tau, then the regulator and the floor reset;
@@ -921,8 +934,8 @@ struct BStage {             // one event of a stage (sources + flux launches)
     double *outT;
     S *outP;
     unsigned sgx, sgy;      // sources grid (x, y); z = neta
-    unsigned fgx, fgy;      // flux grid (x, y); z = ceil(neta / kc)
-    int kc;                 // eta planes per flux block
+    unsigned fgx, fgy;      // flux grid (x, y); z = ceil(neta / KCC) (the launch's eta planes per block)
+    int tw;                 // waves per flux block along x (4, 2 or 1: 64 x 4, 32 x 8, 16 x 16 cells)
 };
 
 template <typename S>
@@ -964,20 +977,19 @@ __global__ __launch_bounds__(256) void sources_batch(const BStage<S> *__restrict
     sources_body<CART, STAGE2, S>(A.P, A.E, tau, A.F, A.qnT, A.qnP, A.outT, A.outP, bx, by, bz, T);
 }
 
-template <bool STAGE2, bool T1, typename S>
+template <bool STAGE2, bool T1, typename S, int KCC>
 __global__ __launch_bounds__(256) void flux_batch(const BStage<S> *__restrict__ tab,
                                                   const unsigned short *__restrict__ map,
                                                   const unsigned *__restrict__ first)
 {
-    __shared__ double HbT[PTT][256];
-    __shared__ S Hb[NQ - PTT][256];
+    __shared__ FluxLds<S, KCC> Lc;
     const unsigned g = xcd_block(blockIdx.x, gridDim.x);
     const int ev = map[g];
     const BStage<S> &A = tab[ev];
     const unsigned lb = g - first[ev];
     unsigned bx, by, bz;
-    tile_of_block(lb, A.fgx, A.fgy, (A.P.neta + A.kc - 1) / A.kc, bx, by, bz);
-    flux_body<STAGE2, T1, S>(A.P, A.G, A.F.qT, A.F.qP, A.F.vf, A.outT, A.outP, HbT, Hb, bx, by, bz, A.kc);
+    tile_of_block(lb, A.fgx, A.fgy, (A.P.neta + KCC - 1) / KCC, bx, by, bz);
+    flux_body<STAGE2, T1, S, KCC>(A.P, A.G, A.F.qT, A.F.qP, A.F.vf, A.outT, A.outP, Lc, bx, by, bz, A.tw);
 }
 
 template <bool CART, typename S>
@@ -1740,9 +1752,9 @@ static kt_status run_stage_t(kt_ctx *c, bool stage2, double tau, int src, int ub
     e = prof_mark(c, 0, true);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
     const bool t1 = theta_is_one(P.theta);
-    auto K = stage2 ? (t1 ? flux_kernel<true, true, S> : flux_kernel<true, false, S>)
-                    : (t1 ? flux_kernel<false, true, S> : flux_kernel<false, false, S>);
-    e = launch(K, gf, b, c->stream, P, c->G, F.qT, F.qP, F.vf, outT, outP, KC);
+    auto K = stage2 ? (t1 ? flux_kernel<true, true, S, KC> : flux_kernel<true, false, S, KC>)
+                    : (t1 ? flux_kernel<false, true, S, KC> : flux_kernel<false, false, S, KC>);
+    e = launch(K, gf, b, c->stream, P, c->G, F.qT, F.qP, F.vf, outT, outP, 4);
     if (e == hipSuccess) e = prof_mark(c, 0, false);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "flux kernel: %s", hipGetErrorString(e));
     return KT_OK;
@@ -2314,7 +2326,8 @@ struct kt_batch {
     double *tau_dev;
     char *tab;                   // device tables (see batch_tables)
     size_t tab_bytes;
-    std::vector<int> kc;         // eta planes per flux block, per event
+    int kcc;                     // eta planes per flux block (2 or 4, every event)
+    std::vector<int> tw;         // waves per flux block along x, per event
     unsigned nb_src, nb_flux, nb_rec, nb_face;
     size_t o_s1[2], o_s2[2], o_r1[2], o_r2[2], o_f1, o_f2;  // table offsets ([step parity])
     size_t o_fsrc, o_fflux, o_frec, o_fface;                // first-block arrays
@@ -2349,12 +2362,16 @@ static size_t batch_table_bytes(int n)
     return t;
 }
 
-// blocks of every launch kind of one event (flux at one eta plane per block, the most)
+// blocks of every launch kind of one event (flux at one eta plane per block and
+// the block shape with the most tiles, the most)
 static size_t event_blocks(const kt_params *p)
 {
     const size_t sg = (size_t)((p->nx + 63) / 64) * ((p->ny + 3) / 4);
+    size_t fg = 0;
+    for (int tw = 1; tw <= 4; tw *= 2)
+        fg = std::max(fg, (size_t)((p->nx + 16 * tw - 1) / (16 * tw)) * ((p->ny + 16 / tw - 1) / (16 / tw)));
     const size_t ncell = (size_t)p->nx * p->ny * p->neta;
-    return 2 * sg * p->neta + (ncell + 255) / 256 + (size_t)face_launch(face_geo(p), p->nx, p->ny).nblocks;
+    return (sg + fg) * p->neta + (ncell + 255) / 256 + (size_t)face_launch(face_geo(p), p->nx, p->ny).nblocks;
 }
 
 static size_t event_ws(const kt_params *p, const kt_eos *eos)
@@ -2412,9 +2429,9 @@ static kt_status batch_tables(kt_batch *b)
                 A.outP = (S *)c->qP[1 - src];
                 A.sgx = (P.nx + 63) / 64;
                 A.sgy = (P.ny + 3) / 4;
-                A.fgx = A.sgx;
-                A.fgy = A.sgy;
-                A.kc = b->kc[e];
+                A.tw = b->tw[e];
+                A.fgx = (P.nx + 16 * A.tw - 1) / (16 * A.tw);
+                A.fgy = (P.ny + 16 / A.tw - 1) / (16 / A.tw);
                 BRec<S> &R = st == 0 ? r1[par][e] : r2[par][e];
                 const int which = st == 0 ? 1 : 0;   // recover q* after stage 1, q after stage 2
                 R.P = P;
@@ -2441,7 +2458,7 @@ static kt_status batch_tables(kt_batch *b)
         }
         const unsigned sg = s1[0][e].sgx * s1[0][e].sgy;
         fs[e + 1] = fs[e] + sg * (unsigned)P.neta;
-        ff[e + 1] = ff[e] + sg * (unsigned)((P.neta + b->kc[e] - 1) / b->kc[e]);
+        ff[e + 1] = ff[e] + s1[0][e].fgx * s1[0][e].fgy * (unsigned)((P.neta + b->kcc - 1) / b->kcc);
         fr[e + 1] = fr[e] + (unsigned)((P.ncell + 255) / 256);
         fc[e + 1] = fc[e] + f1[e].L.nblocks;
     }
@@ -2512,9 +2529,11 @@ static hipError_t batch_step_launches(kt_batch *b, hipStream_t st, int par)
     auto M = [&](size_t o) { return (const unsigned short *)(b->tab + o); };
     hipError_t e = launch(sources_batch<CART, false, S>, dim3(b->nb_src), blk2, st,
                           (const BStage<S> *)T(b->o_s1[par]), M(b->o_msrc), F(b->o_fsrc), tau);
+    auto flux = [&](auto kern, size_t o) {
+        return launch(kern, dim3(b->nb_flux), blk2, st, (const BStage<S> *)T(o), M(b->o_mflux), F(b->o_fflux));
+    };
     if (e == hipSuccess)
-        e = launch(flux_batch<false, T1, S>, dim3(b->nb_flux), blk2, st, (const BStage<S> *)T(b->o_s1[par]),
-                   M(b->o_mflux), F(b->o_fflux));
+        e = b->kcc == 4 ? flux(flux_batch<false, T1, S, 4>, b->o_s1[par]) : flux(flux_batch<false, T1, S, 2>, b->o_s1[par]);
     if (e == hipSuccess)
         e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r1[par]),
                    M(b->o_mrec), F(b->o_frec), tau);
@@ -2525,8 +2544,7 @@ static hipError_t batch_step_launches(kt_batch *b, hipStream_t st, int par)
         e = launch(sources_batch<CART, true, S>, dim3(b->nb_src), blk2, st,
                    (const BStage<S> *)T(b->o_s2[par]), M(b->o_msrc), F(b->o_fsrc), tau);
     if (e == hipSuccess)
-        e = launch(flux_batch<true, T1, S>, dim3(b->nb_flux), blk2, st, (const BStage<S> *)T(b->o_s2[par]),
-                   M(b->o_mflux), F(b->o_fflux));
+        e = b->kcc == 4 ? flux(flux_batch<true, T1, S, 4>, b->o_s2[par]) : flux(flux_batch<true, T1, S, 2>, b->o_s2[par]);
     if (e == hipSuccess)
         e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r2[par]),
                    M(b->o_mrec), F(b->o_frec), tau);
@@ -2546,9 +2564,11 @@ static hipError_t batch_stage1_t(kt_batch *b, hipStream_t st)
     hipError_t e = launch(sources_batch<CART, false, S>, dim3(b->nb_src), dim3(64, 4), st, tab,
                           (const unsigned short *)(b->tab + b->o_msrc), (const unsigned *)(b->tab + b->o_fsrc),
                           (const double *)b->tau_dev);
+    const unsigned short *map = (const unsigned short *)(b->tab + b->o_mflux);
+    const unsigned *first = (const unsigned *)(b->tab + b->o_fflux);
     if (e == hipSuccess)
-        e = launch(flux_batch<false, T1, S>, dim3(b->nb_flux), dim3(64, 4), st, tab,
-                   (const unsigned short *)(b->tab + b->o_mflux), (const unsigned *)(b->tab + b->o_fflux));
+        e = b->kcc == 4 ? launch(flux_batch<false, T1, S, 4>, dim3(b->nb_flux), dim3(64, 4), st, tab, map, first)
+                        : launch(flux_batch<false, T1, S, 2>, dim3(b->nb_flux), dim3(64, 4), st, tab, map, first);
     return e;
 }
 
@@ -2654,7 +2674,8 @@ kt_status kt_batch_init(const kt_params *p, int32_t n_events, const kt_eos *eos,
     for (int k = 0; k < n_events; ++k) b->theta1 = b->theta1 && theta_is_one(p[k].theta);
     b->dtau = p[0].dtau;
     b->tau = p[0].tau0;
-    b->kc.assign(n_events, KC);
+    b->kcc = KC;
+    b->tw.assign(n_events, 4);
     char *base = (char *)d_ws;
     size_t off = 0;
     for (int e = 0; e < n_events; ++e) {
@@ -2748,27 +2769,42 @@ kt_status kt_batch_step(kt_batch *b, int32_t n_steps)
     return KT_OK;
 }
 
-kt_status kt_batch_tune(kt_batch *b, int32_t *kc_out)
+kt_status kt_batch_set_flux_blocks(kt_batch *b, const int32_t *kc, const int32_t *tile_x)
 {
     if (!b) return bfail(nullptr, KT_E_ARG, "null batch");
-    static const int cand[4] = {1, 2, 4, 8};
+    if (!kc || !tile_x) return bfail(b, KT_E_ARG, "null kc or tile_x");
+    for (int ev = 0; ev < b->n; ++ev) {
+        if ((kc[ev] != 2 && kc[ev] != 4) || kc[ev] != kc[0])
+            return bfail(b, KT_E_ARG, "kc[%d] = %d: every event takes the same, 2 or 4", ev, kc[ev]);
+        if (tile_x[ev] != 64 && tile_x[ev] != 32 && tile_x[ev] != 16)
+            return bfail(b, KT_E_ARG, "tile_x[%d] = %d is not 64, 32 or 16", ev, tile_x[ev]);
+    }
+    b->kcc = kc[0];
+    for (int ev = 0; ev < b->n; ++ev) b->tw[ev] = tile_x[ev] / 16;
+    return batch_build_tables(b);
+}
+
+kt_status kt_batch_tune(kt_batch *b, int32_t *kc_out, int32_t *tile_out)
+{
+    if (!b) return bfail(nullptr, KT_E_ARG, "null batch");
+    static const int cand_tw[3] = {4, 2, 1};
     hipEvent_t t0, t1;
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     if (e != hipSuccess) return bfail(b, KT_E_HIP, "tune events: %s", hipGetErrorString(e));
     // The batched stage 1 (sources, then flux: the flux kernel finds the caches as
-    // it does in a step) is timed as a whole for each candidate, the same number
-    // of eta planes per block for every event: the launch shares the chip among
-    // all events, so timing each grid shape alone would choose for a different
-    // load.  Both launches only write q*, which the next step's sources kernel
-    // overwrites, so timing them on the live state changes no result.
-    float best = 1e30f;
-    int best_kc = KC;
+    // it does in a step) is timed as a whole: the launch shares the chip among all
+    // events, so timing each grid shape alone would choose for a different load.
+    // The flux block's width (waves along x) is chosen per distinct grid shape, one
+    // shape at a time (largest total cells first) with the others held at their
+    // current choice; then the eta planes per block (2 or 4, one value for the
+    // launch) with those widths.  Both launches only write q*, which the next
+    // step's sources kernel overwrites, so timing them on the live state changes
+    // no result.
     kt_status st = KT_OK;
-    for (int ci = 0; ci < 4 && e == hipSuccess && st == KT_OK; ++ci) {
-        b->kc.assign(b->n, cand[ci]);
+    auto time_stage1 = [&](float &tot) {
         st = batch_build_tables(b);
-        float tot = 0.0f;
+        tot = 0.0f;
         for (int r = 0; r < 4 && e == hipSuccess && st == KT_OK; ++r) {
             e = hipEventRecord(t0, b->user);
             if (e == hipSuccess) e = batch_stage1(b, b->user);
@@ -2778,18 +2814,61 @@ kt_status kt_batch_tune(kt_batch *b, int32_t *kc_out)
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
             if (r > 0) tot += ms;   // the first launch warms caches
         }
-        if (e == hipSuccess && st == KT_OK && tot < best) {
-            best = tot;
-            best_kc = cand[ci];
+    };
+    // distinct shapes, largest total cells first
+    std::vector<std::vector<int>> shapes;
+    std::vector<long long> shape_cells;
+    for (int ev = 0; ev < b->n; ++ev) {
+        const Phys &P = b->ev[ev]->P;
+        int found = -1;
+        for (size_t s2 = 0; s2 < shapes.size(); ++s2) {
+            const Phys &Q = b->ev[shapes[s2][0]]->P;
+            if (Q.nx == P.nx && Q.ny == P.ny && Q.neta == P.neta) found = (int)s2;
         }
+        if (found < 0) {
+            shapes.push_back({ev});
+            shape_cells.push_back(0);
+            found = (int)shapes.size() - 1;
+        } else {
+            shapes[found].push_back(ev);
+        }
+        shape_cells[found] += (long long)P.nx * P.ny * P.neta;
+    }
+    std::vector<size_t> order(shapes.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t c2) { return shape_cells[a] > shape_cells[c2]; });
+    b->kcc = KC;
+    float best = 1e30f;
+    for (size_t oi = 0; oi < order.size() && e == hipSuccess && st == KT_OK; ++oi) {
+        const std::vector<int> &evs = shapes[order[oi]];
+        float best_s = 1e30f;
+        int best_tw = b->tw[evs[0]];
+        for (int ti = 0; ti < 3 && e == hipSuccess && st == KT_OK; ++ti) {
+            for (int ev : evs) b->tw[ev] = cand_tw[ti];
+            float tot = 0.0f;
+            time_stage1(tot);
+            if (e == hipSuccess && st == KT_OK && tot < best_s) {
+                best_s = tot;
+                best_tw = cand_tw[ti];
+            }
+        }
+        for (int ev : evs) b->tw[ev] = best_tw;
+        best = best_s;
+    }
+    if (e == hipSuccess && st == KT_OK) {
+        b->kcc = 4;
+        float tot = 0.0f;
+        time_stage1(tot);
+        if (e == hipSuccess && st == KT_OK && !(tot < best)) b->kcc = 2;
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     if (st != KT_OK) return st;
     if (e != hipSuccess) return bfail(b, KT_E_HIP, "tune: %s", hipGetErrorString(e));
-    b->kc.assign(b->n, best_kc);
-    if (kc_out)
-        for (int ev = 0; ev < b->n; ++ev) kc_out[ev] = b->kc[ev];
+    for (int ev = 0; ev < b->n; ++ev) {
+        if (kc_out) kc_out[ev] = b->kcc;
+        if (tile_out) tile_out[ev] = 16 * b->tw[ev];
+    }
     return batch_build_tables(b);
 }
 

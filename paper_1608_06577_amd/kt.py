@@ -88,7 +88,8 @@ EXPORTS = ("kt_workspace_bytes", "kt_init", "kt_step", "kt_recover", "kt_observa
            "kt_profile_enable", "kt_profile_read", "kt_destroy", "kt_last_error",
            "kt_status_string", "kt_set_inv_start", "kt_mlp_set", "kt_mlp_get", "kt_mlp_features",
            "kt_mlp_fwd", "kt_mlp_loss", "kt_mlp_bwd", "kt_mlp_adam", "kt_batch_workspace_bytes",
-           "kt_batch_init", "kt_batch_step", "kt_batch_tune", "kt_batch_observables",
+           "kt_batch_init", "kt_batch_step", "kt_batch_tune", "kt_batch_set_flux_blocks",
+           "kt_batch_observables",
            "kt_batch_destroy", "kt_batch_last_error")
 
 KT_START_WARM, KT_START_CONFORMAL, KT_START_LEARNED = 0, 1, 2
@@ -139,13 +140,15 @@ def lib():
         L.kt_batch_init.argtypes = [C.POINTER(KtParams), C.c_int32, C.POINTER(KtEos),
                                     C.POINTER(KtInitState), vp, C.c_size_t, vp, C.POINTER(vp)]
         L.kt_batch_step.argtypes = [vp, C.c_int32]
-        L.kt_batch_tune.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.kt_batch_tune.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.kt_batch_set_flux_blocks.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.kt_batch_observables.argtypes = [vp, C.c_int32, C.POINTER(KtObs), C.POINTER(KtFields)]
         L.kt_batch_destroy.argtypes = [vp]
         L.kt_batch_destroy.restype = None
         L.kt_batch_last_error.argtypes = [vp]
         L.kt_batch_last_error.restype = C.c_char_p
-        for f in ("kt_batch_init", "kt_batch_step", "kt_batch_tune", "kt_batch_observables"):
+        for f in ("kt_batch_init", "kt_batch_step", "kt_batch_tune", "kt_batch_set_flux_blocks",
+                  "kt_batch_observables"):
             getattr(L, f).restype = C.c_int
         for f in ("kt_validity", "kt_run_to_freezeout"):
             getattr(L, f).restype = C.c_int
@@ -257,13 +260,13 @@ class Solver:
         if nbytes == 0:
             _check(KT_E_ARG)
         with torch.cuda.device(self.device):
-            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-            if self.ws.data_ptr() % 256:
-                raise RuntimeError("workspace is not 256-byte aligned")
             keep = []
             st = _init_state(torch, self.device, grid, prims, q, u_prev, keep)
             stream = torch.cuda.current_stream(self.device).cuda_stream
             ctx = C.c_void_p()
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            if self.ws.data_ptr() % 256:
+                raise RuntimeError("workspace is not 256-byte aligned")
             _check(L.kt_init(C.byref(self.params), C.byref(self.eos_host.c), C.byref(st),
                              C.c_void_p(self.ws.data_ptr()), nbytes, C.c_void_p(stream),
                              C.byref(ctx)))
@@ -473,9 +476,18 @@ class Batch:
         return self
 
     def tune(self):
+        """Autotune the flux block per grid shape; returns (eta planes, block width in x)
+        per event."""
         kc = (C.c_int32 * self.n)()
-        self._check(lib().kt_batch_tune(self.b, kc))
-        return list(kc)
+        tile = (C.c_int32 * self.n)()
+        self._check(lib().kt_batch_tune(self.b, kc, tile))
+        return list(zip(kc, tile))
+
+    def set_flux_blocks(self, blocks):
+        """blocks: (eta planes, block width in x) per event, as tune() returns."""
+        kc = (C.c_int32 * self.n)(*[int(b[0]) for b in blocks])
+        tile = (C.c_int32 * self.n)(*[int(b[1]) for b in blocks])
+        self._check(lib().kt_batch_set_flux_blocks(self.b, kc, tile))
 
     def observables(self, event: int) -> dict:
         o = KtObs()

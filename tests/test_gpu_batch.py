@@ -63,14 +63,44 @@ def test_batch_tuning_keeps_results(kt):
     batch = kt.Batch(evs, eos)
     singles = [kt.Solver(g, cfg, eos, pr) for g, cfg, pr in evs]
     batch.step(2)
-    kc = batch.tune()
-    print("autotuned eta planes per flux block:", kc, flush=True)
-    assert all(k in (1, 2, 4, 8) for k in kc) and len(set(kc)) == 1
+    blocks = batch.tune()
+    print("autotuned flux blocks (eta planes, x width) per event:", blocks, flush=True)
+    assert all(k in (2, 4) and t in (64, 32, 16) for k, t in blocks) and len({k for k, _ in blocks}) == 1
     batch.step(5)
     for s in singles:
         s.step(7)
     for k, s in enumerate(singles):
         assert same(batch.fields(k), s.fields()), k
+
+
+def test_every_flux_block_gives_the_same_fields(kt):
+    """The flux block shapes (64 x 4, 32 x 8, 16 x 16 cells, set per event; 2 or
+    4 eta planes) against separate contexts: equal bit for bit."""
+    evs, eos = events()
+    singles = [kt.Solver(g, cfg, eos, pr) for g, cfg, pr in evs]
+    for s in singles:
+        s.step(3)
+    ref = [s.fields() for s in singles]
+    n = len(evs)
+    tiles = (64, 32, 16)
+    for t0 in range(3):
+        for kc in (2, 4):
+            # a different width for every event: the events' blocks interleave in each launch
+            blocks = [(kc, tiles[(t0 + e) % 3]) for e in range(n)]
+            batch = kt.Batch(evs, eos)
+            batch.set_flux_blocks(blocks)
+            batch.step(3)
+            for k in range(n):
+                assert same(batch.fields(k), ref[k]), (blocks, k)
+            batch.close()
+    batch = kt.Batch(evs, eos)
+    with pytest.raises(kt.KtError):
+        batch.set_flux_blocks([(4, 48)] * n)
+    with pytest.raises(kt.KtError):
+        batch.set_flux_blocks([(1, 64)] * n)
+    with pytest.raises(kt.KtError):
+        batch.set_flux_blocks([(2, 64)] + [(4, 64)] * (n - 1))
+    batch.close()
 
 
 def test_batch_matches_oracle(kt):
