@@ -169,6 +169,23 @@ size_t kt_workspace_bytes(const kt_params *p, const kt_eos *eos);
 kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0,
                   void *d_ws, size_t ws_bytes, hipStream_t stream, kt_ctx **out);
 
+/* kt_init without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, serving loops, harnesses that
+ * forbid hipMalloc): the context's workspace is the library's own static
+ * device array of KT_STATIC_WS_BYTES bytes, one per GPU, set up with the
+ * library's code object and held until the process ends.  Neither this call
+ * nor any later call on the context allocates device memory (the context
+ * itself lives on the host heap, as for kt_init).  Every context made this
+ * way on one GPU shares that GPU's array: a new one overwrites the state of
+ * the previous one on the same device, which must not be used afterwards,
+ * and contexts whose calls overlap on one GPU race.  The state is set up as
+ * by kt_init (nothing is assumed about the array's previous contents).
+ * Errors: those of kt_init; KT_E_ALLOC when kt_workspace_bytes(p, eos)
+ * exceeds KT_STATIC_WS_BYTES; KT_E_HIP when the array's device address
+ * cannot be obtained on the current device.  Release with kt_destroy. */
+#define KT_STATIC_WS_BYTES (64u << 20)
+kt_status kt_init_static(const kt_params *p, const kt_eos *eos, const kt_init_state *s0,
+                         hipStream_t stream, kt_ctx **out);
 
 /* Enqueue n_steps >= 0 full Heun steps (Sec. 3.1, Eqs. step1-finalStep with
  * s = 2; order of Sec. 4.3): stage 1 at tau^n, recovery and regulation of q*

@@ -24,6 +24,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -2309,6 +2310,50 @@ void kt_destroy(kt_ctx *c)
 }
 
 }  // extern "C"
+
+// ------------------------------------------------- static workspace ----
+// The workspace of kt_init_static: one array per GPU, set up with the code
+// object and held until the process ends.  In host code `scratch` names a
+// host-side stand-in, never the device memory: its device address is taken
+// once per device with hipGetSymbolAddress (with that device current) and
+// only that address is handed to kernels and copies.
+static __device__ __align__(256) unsigned char scratch[KT_STATIC_WS_BYTES];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[256];      // device address of scratch per device ordinal
+
+static hipError_t scratch_address(int dev, void **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+extern "C" kt_status kt_init_static(const kt_params *p, const kt_eos *eos, const kt_init_state *s0,
+                                    hipStream_t stream, kt_ctx **out)
+{
+    if (!out) return fail(nullptr, KT_E_ARG, "out is null");
+    *out = nullptr;
+    if (const char *m = check_args(p, eos)) return fail(nullptr, KT_E_ARG, "%s", m);
+    const size_t need = layout(p, eos).total;
+    if (need > (size_t)KT_STATIC_WS_BYTES)
+        return fail(nullptr, KT_E_ALLOC, "grid needs a %zu-byte workspace; the static workspace holds %zu",
+                    need, (size_t)KT_STATIC_WS_BYTES);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && (dev < 0 || dev >= 256)) e = hipErrorInvalidDevice;
+    void *ws = nullptr;
+    if (e == hipSuccess) e = scratch_address(dev, &ws);
+    if (e != hipSuccess) return fail(nullptr, KT_E_HIP, "static workspace: %s", hipGetErrorString(e));
+    return kt_init(p, eos, s0, ws, (size_t)KT_STATIC_WS_BYTES, stream, out);
+}
 
 // ======================================================================
 // Batches of events

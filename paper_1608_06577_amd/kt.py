@@ -83,7 +83,7 @@ class KtError(RuntimeError):
 _lib = None
 
 #: every function the C ABI exports (the names declared in include/kt.h)
-EXPORTS = ("kt_workspace_bytes", "kt_init", "kt_step", "kt_recover", "kt_observables",
+EXPORTS = ("kt_workspace_bytes", "kt_init", "kt_init_static", "kt_step", "kt_recover", "kt_observables",
            "kt_validity", "kt_run_to_freezeout",
            "kt_profile_enable", "kt_profile_read", "kt_destroy", "kt_last_error",
            "kt_status_string", "kt_set_inv_start", "kt_mlp_set", "kt_mlp_get", "kt_mlp_features",
@@ -111,6 +111,8 @@ def lib():
         L.kt_workspace_bytes.restype = C.c_size_t
         L.kt_init.argtypes = [C.POINTER(KtParams), C.POINTER(KtEos), C.POINTER(KtInitState),
                               C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]
+        L.kt_init_static.argtypes = [C.POINTER(KtParams), C.POINTER(KtEos), C.POINTER(KtInitState),
+                                     C.c_void_p, C.POINTER(C.c_void_p)]
         L.kt_step.argtypes = [C.c_void_p, C.c_int32]
         L.kt_recover.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p * 9, C.c_void_p,
                                  C.c_void_p * 4, C.c_void_p, C.c_void_p]
@@ -152,7 +154,7 @@ def lib():
             getattr(L, f).restype = C.c_int
         for f in ("kt_validity", "kt_run_to_freezeout"):
             getattr(L, f).restype = C.c_int
-        for f in ("kt_init", "kt_step", "kt_recover", "kt_observables", "kt_profile_enable",
+        for f in ("kt_init", "kt_init_static", "kt_step", "kt_recover", "kt_observables", "kt_profile_enable",
                   "kt_profile_read", "kt_set_inv_start", "kt_mlp_set", "kt_mlp_get",
                   "kt_mlp_features", "kt_mlp_fwd", "kt_mlp_loss", "kt_mlp_bwd", "kt_mlp_adam"):
             getattr(L, f).restype = C.c_int
@@ -245,7 +247,7 @@ class Solver:
     """
 
     def __init__(self, grid, config: dict, eos, prims=None, q=None, tau0=None, u_prev=None,
-                 device="cuda:0"):
+                 device="cuda:0", static_workspace=False):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -264,12 +266,18 @@ class Solver:
             st = _init_state(torch, self.device, grid, prims, q, u_prev, keep)
             stream = torch.cuda.current_stream(self.device).cuda_stream
             ctx = C.c_void_p()
-            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-            if self.ws.data_ptr() % 256:
-                raise RuntimeError("workspace is not 256-byte aligned")
-            _check(L.kt_init(C.byref(self.params), C.byref(self.eos_host.c), C.byref(st),
-                             C.c_void_p(self.ws.data_ptr()), nbytes, C.c_void_p(stream),
-                             C.byref(ctx)))
+            if static_workspace:
+                # the library's static per-GPU workspace (kt_init_static)
+                self.ws = None
+                _check(L.kt_init_static(C.byref(self.params), C.byref(self.eos_host.c), C.byref(st),
+                                        C.c_void_p(stream), C.byref(ctx)))
+            else:
+                self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+                if self.ws.data_ptr() % 256:
+                    raise RuntimeError("workspace is not 256-byte aligned")
+                _check(L.kt_init(C.byref(self.params), C.byref(self.eos_host.c), C.byref(st),
+                                 C.c_void_p(self.ws.data_ptr()), nbytes, C.c_void_p(stream),
+                                 C.byref(ctx)))
             self.ctx = ctx
             del keep
 

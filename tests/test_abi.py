@@ -135,3 +135,20 @@ def test_learned_start_entry_points_reject_null_context(L):
     ]
     assert all(c == kt.KT_E_ARG for c in calls), calls
     assert b"null context" in L.kt_last_error(None)
+
+
+def test_static_init_rejects_grids_beyond_its_array(L):
+    """kt_init_static checks the grid against KT_STATIC_WS_BYTES before any
+    device work."""
+    g = I.Grid(128, 128, 128, 0.16, 0.16, 0.1)
+    cfg = I.default_config(eta_s=0.2, zeta_coef=0.1)
+    eos = kt.EosHost(I.eos_c1_table(n=64))
+    p = kt.make_params(g, cfg, 0.5)
+    assert L.kt_workspace_bytes(C.byref(p), C.byref(eos.c)) > 64 << 20
+    ctx = C.c_void_p()
+    st = kt.KtInitState()
+    assert L.kt_init_static(C.byref(p), C.byref(eos.c), C.byref(st), None, C.byref(ctx)) == 2
+    assert not ctx.value
+    assert b"static workspace" in L.kt_last_error(None)
+    p.nx = 0
+    assert L.kt_init_static(C.byref(p), C.byref(eos.c), C.byref(st), None, C.byref(ctx)) == 1
