@@ -251,6 +251,15 @@ kt_status kt_mlp_features(kt_ctx *c, int64_t n, double tau, const double *const 
  * pre-activations for kt_mlp_bwd. */
 kt_status kt_mlp_fwd(kt_ctx *c, int64_t n, const float *x, float *y, float *act);
 
+/* The start factor y_0 (the network's first output) of n feature vectors x
+ * (11 x n, as for kt_mlp_fwd) computed as the recoveries compute it for
+ * KT_START_LEARNED: on the matrix cores, with the features, W1, W2 and the
+ * first hidden layer's activations rounded to FP16, FP32 accumulation, FP32
+ * biases and output layer, GELU through an erf approximation of absolute
+ * error below 1.5e-7 (Abramowitz & Stegun 7.1.26).  y0[n] (device, FP32).
+ * KT_E_STATE before kt_mlp_set. */
+kt_status kt_mlp_y0(kt_ctx *c, int64_t n, const float *x, float *y0);
+
 /* Weighted mean squared error over the 4 x n outputs,
  * L = sum_{o,i} w_o (y - t)^2 / (4 n) with w (host array of 4, nullable =
  * all 1, each >= 0): dy = 2 w_o (y - t) / (4 n) (nullable) and L into *loss

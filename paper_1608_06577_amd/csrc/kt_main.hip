@@ -72,16 +72,22 @@ struct FaceGeo {
 // lane.
 typedef uint32_t idx_t;
 
+// The pointers are global memory: the batched kernels read them from a device
+// table, where the compiler cannot see their address space and would emit flat
+// accesses, which also count against the LDS wait counter and so hold up the
+// kernels' LDS exchanges; the cast keeps every access a global one.
+#define KT_GLOBAL __attribute__((address_space(1)))
+
 template <typename T>
 __device__ __forceinline__ T ld(const T *base, idx_t i)
 {
-    return *(const T *)((const char *)base + (size_t)(i * (idx_t)sizeof(T)));
+    return *(const KT_GLOBAL T *)((const KT_GLOBAL char *)base + (size_t)(i * (idx_t)sizeof(T)));
 }
 
 template <typename T>
 __device__ __forceinline__ void st(T *base, idx_t i, T v)
 {
-    *(T *)((char *)base + (size_t)(i * (idx_t)sizeof(T))) = v;
+    *(KT_GLOBAL T *)((KT_GLOBAL char *)base + (size_t)(i * (idx_t)sizeof(T))) = v;
 }
 
 // component c (0..14) of q given as its FP64 part qT (0..3) and qP (4..14)
@@ -1124,6 +1130,22 @@ __global__ __launch_bounds__(256) void recover_standalone_kernel(Phys P, Eos E, 
 // sum of the counter slots: per-block partial sums, then one block adds them
 // (integer sums, so the result does not depend on the order)
 constexpr int SLOT_BLOCKS = 256;
+
+// the network's start y_0 of n feature vectors (feature-major x[f n + i]) by the
+// matrix-core inference the recoveries use (kt_mlp.hpp); lanes past n take part
+// with zero features and store nothing
+__global__ __launch_bounds__(256) void mlp_y0_kernel(long long n, const float *__restrict__ x, float *y0,
+                                                     const ktm::MlpPacked *__restrict__ K)
+{
+    __shared__ _Float16 xs[256][ktm::XS_K];
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = s < n;
+    float f[ktm::NI];
+#pragma unroll
+    for (int k = 0; k < ktm::NI; ++k) f[k] = valid ? x[k * n + s] : 0.0f;
+    const float y = ktm::forward_y0_mfma(K, f, xs + (threadIdx.x & ~63u));
+    if (valid) y0[s] = y;
+}
 
 __global__ __launch_bounds__(256) void slots_partial_kernel(const unsigned long long *slots,
                                                             long long nwaves,
@@ -2218,6 +2240,21 @@ kt_status kt_mlp_fwd(kt_ctx *c, int64_t n, const float *x, float *y, float *act)
     hipError_t e = launch(ktm::forward_kernel, linear_grid(n), dim3(256), c->stream, (long long)n,
                           (const float *)c->mlp_w, x, y, act);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "forward kernel: %s", hipGetErrorString(e));
+    return KT_OK;
+}
+
+kt_status kt_mlp_y0(kt_ctx *c, int64_t n, const float *x, float *y0)
+{
+    if (!c) return fail(nullptr, KT_E_ARG, "null context");
+    if (n < 0) return fail(c, KT_E_ARG, "n must be >= 0");
+    if (!c->mlp_ready) return fail(c, KT_E_STATE, "no parameters set");
+    if (n == 0) return KT_OK;
+    if (!x || !y0) return fail(c, KT_E_ARG, "null input or output");
+    hipError_t e = ensure_packed(c);
+    if (e == hipSuccess)
+        e = launch(mlp_y0_kernel, linear_grid(n), dim3(256), c->stream, (long long)n, x, y0,
+                   (const ktm::MlpPacked *)c->mlp_pk);
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "start inference: %s", hipGetErrorString(e));
     return KT_OK;
 }
 

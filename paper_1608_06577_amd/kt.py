@@ -87,7 +87,7 @@ EXPORTS = ("kt_workspace_bytes", "kt_init", "kt_init_static", "kt_step", "kt_rec
            "kt_validity", "kt_run_to_freezeout",
            "kt_profile_enable", "kt_profile_read", "kt_destroy", "kt_last_error",
            "kt_status_string", "kt_set_inv_start", "kt_mlp_set", "kt_mlp_get", "kt_mlp_features",
-           "kt_mlp_fwd", "kt_mlp_loss", "kt_mlp_bwd", "kt_mlp_adam", "kt_batch_workspace_bytes",
+           "kt_mlp_fwd", "kt_mlp_y0", "kt_mlp_loss", "kt_mlp_bwd", "kt_mlp_adam", "kt_batch_workspace_bytes",
            "kt_batch_init", "kt_batch_step", "kt_batch_tune", "kt_batch_set_flux_blocks",
            "kt_batch_observables",
            "kt_batch_destroy", "kt_batch_last_error")
@@ -134,6 +134,7 @@ def lib():
         L.kt_mlp_get.argtypes = [vp, vp, C.c_int32]
         L.kt_mlp_features.argtypes = [vp, C.c_int64, C.c_double, vp * 9, vp, vp, vp, vp]
         L.kt_mlp_fwd.argtypes = [vp, C.c_int64, vp, vp, vp]
+        L.kt_mlp_y0.argtypes = [vp, C.c_int64, vp, vp]
         L.kt_mlp_loss.argtypes = [vp, C.c_int64, vp, vp, C.POINTER(C.c_float), vp, vp]
         L.kt_mlp_bwd.argtypes = [vp, C.c_int64, vp, vp, vp, vp]
         L.kt_mlp_adam.argtypes = [vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32]
@@ -156,7 +157,7 @@ def lib():
             getattr(L, f).restype = C.c_int
         for f in ("kt_init", "kt_init_static", "kt_step", "kt_recover", "kt_observables", "kt_profile_enable",
                   "kt_profile_read", "kt_set_inv_start", "kt_mlp_set", "kt_mlp_get",
-                  "kt_mlp_features", "kt_mlp_fwd", "kt_mlp_loss", "kt_mlp_bwd", "kt_mlp_adam"):
+                  "kt_mlp_features", "kt_mlp_fwd", "kt_mlp_y0", "kt_mlp_loss", "kt_mlp_bwd", "kt_mlp_adam"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -385,6 +386,14 @@ class Solver:
         act = torch.empty((128, n), dtype=torch.float32, device=self.device) if keep_act else None
         _check(lib().kt_mlp_fwd(self.ctx, n, _ptr(x.contiguous()), _ptr(y), _ptr(act)), self.ctx)
         return (y, act) if keep_act else y
+
+    def mlp_y0(self, x):
+        """x (11, n) float32 -> y_0 (n,): the matrix-core inference of the recoveries."""
+        torch = self.torch
+        n = x.shape[1]
+        y0 = torch.empty((n,), dtype=torch.float32, device=self.device)
+        _check(lib().kt_mlp_y0(self.ctx, n, _ptr(x.contiguous()), _ptr(y0)), self.ctx)
+        return y0
 
     def mlp_loss(self, y, t, w=None):
         """-> (loss device float64 scalar tensor, dy (4, n)); w: 4 output weights."""

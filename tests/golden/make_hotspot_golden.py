@@ -15,7 +15,7 @@ at 200 steps are set from it.
 The file records the SHA-256 of the oracle source that defines the step
 (``oracle_sha``: the source above its diagnostics marker); the GPU test
 refuses samples made with another oracle.
-Usage (about 40 minutes on 8 cores):
+Usage (about an hour on 8 cores):
 
     python tests/golden/make_hotspot_golden.py [out.npz]
 """

@@ -101,37 +101,29 @@ def test_mixed_one_step_matches_fp64_closely(kt):
 
 
 def test_mixed_hotspot_128_errors(kt):
-    """The 128^3 event in mixed precision against the oracle samples: errors at
-    50/100/200 steps, reported.  The event amplifies perturbations over 200
-    steps (the FP64 path's last-bit differences from the oracle grow to 2e-9 in
-    the dense cells, about 1e7 times); from FP32 rounding the same growth gives
-    about 1e-3 at step 200.  Required: median cells within 1e-6 at every step,
-    dense cells (e > 1e-3 e_max) within 1e-5 up to 100 steps."""
-    path = os.path.join(ROOT, "tests", "golden", "hotspot_128_fp64.npz")
-    if not os.path.exists(path):
-        pytest.skip("oracle samples not generated")
-    gold = np.load(path)
-    w = I.workload_hotspot()
+    """The 128^3 event in mixed precision against the FP64 oracle samples at
+    50/100/200 steps.  The event amplifies perturbations: the oracle against
+    itself with the initial e perturbed by 2^-24 (one FP32 rounding) differs by
+    9.7e-8 in the dense cells (e > 1e-3 e_max) at 100 steps and by 5.3e-3 at
+    200, median 5.4e-8 (the spread the sample file records).  The mixed state
+    rounds eleven components to FP32 at every step, so the bars are ten times
+    that spread: dense cells and the median cell at every snapshot (at least
+    1e-5 for the dense cells and 1e-6 for the median up to 100 steps)."""
+    from tests.test_gpu_parity import golden_samples, sample_errors
+    gold, w, spread = golden_samples()
     gpu = kt.Solver(w.grid, mixed(w.config), w.eos, w.prims)
     idx = gold["idx"]
     done = 0
     for s in (50, 100, 200):
         gpu.step(s - done)
         done = s
-        f = gpu.fields(("e", "u", "q"))
-        e = f["e"].reshape(-1)[idx].cpu().numpy()
-        u = f["u"].reshape(4, -1)[:, idx].cpu().numpy()
-        er, ur = gold["e_%d" % s], gold["u_%d" % s].T
-        tau, emax = float(gold["tau_%d" % s]), float(gold["emax_%d" % s])
-        de = np.abs(e - er) / np.maximum(er, 1e-6 * emax)
-        du = np.max(np.abs(u - ur) * np.array([1, 1, 1, tau])[:, None] / ur[0:1], axis=0)
-        hot = er > 1e-3 * emax
-        print("mixed hotspot128 step %d: e %.2e u %.2e | dense cells e %.2e u %.2e | median e %.1e u %.1e"
-              % (s, de.max(), du.max(), de[hot].max(), du[hot].max(), np.median(de), np.median(du)),
-              flush=True)
-        assert np.median(de) <= 1e-6 and np.median(du) <= 1e-6
-        if s <= 100:
-            assert de[hot].max() <= 1e-5 and du[hot].max() <= 1e-5
+        d, hot = sample_errors(gpu.fields(("e", "u")), gold, s, idx)
+        fp32 = spread[str(s)]["fp32"]
+        print("mixed hotspot128 step %d: max %.2e | dense %.2e | median %.1e | FP32 spread of the oracle: "
+              "dense %.2e median %.1e" % (s, d.max(), d[hot].max(), np.median(d), fp32["dense_max"],
+                                          fp32["median"]), flush=True)
+        assert d[hot].max() <= max(1e-5 if s <= 100 else 0.0, 10 * fp32["dense_max"]), (s, d[hot].max())
+        assert np.median(d) <= max(1e-6 if s <= 100 else 0.0, 10 * fp32["median"]), (s, np.median(d))
     assert gpu.observables()["n_nan"] == 0
 
 

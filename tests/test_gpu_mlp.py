@@ -78,6 +78,37 @@ def test_forward_matches_oracle(kt):
     assert np.array_equal(gpu.mlp_get().cpu().numpy(), theta)
 
 
+def test_matrix_core_start_matches_oracle(kt):
+    """y_0 from the recoveries' matrix-core inference (kt_mlp_y0) against the
+    oracle network.  The inference rounds the features, W1, W2 and the first
+    hidden layer's activations to FP16 (unit roundoff 2^-11): against the
+    oracle evaluated with the same roundings the remaining differences are FP32
+    accumulation, the erf approximation (< 1.5e-7) and the occasional FP16
+    rounding of a first-layer activation that falls the other way (one unit
+    changes y_0 by |W3 W2| 2^-11 ~ 1e-4), bar 1e-3; against the exact FP64
+    network the FP16 roundings themselves, bar 2e-2 (both absolute, y_0 ~ 1)."""
+    gpu, _ = tiny_solver(kt)
+    theta = I.mlp_init_params(7)
+    gpu.mlp_set(dev(theta))
+    rng = np.random.default_rng(4)
+    n = 3000
+    x = rng.uniform(-1.5, 1.5, (n, 11)).astype(np.float32)
+    y0 = gpu.mlp_y0(dev(x.T)).cpu().numpy().astype(np.float64)
+    y_exact = M.forward(theta.astype(np.float64), x.astype(np.float64))[0][:, 0]
+    P = M.unpack(theta.astype(np.float64))
+    h16 = lambda a: np.asarray(a, np.float16).astype(np.float64)
+    a1 = h16(x) @ h16(P["W1"]).T + P["b1"]
+    a2 = h16(M.gelu(a1)) @ h16(P["W2"]).T + P["b2"]
+    y_half = M.gelu(a2) @ P["W3"][0] + P["b3"][0]
+    d_half, d_exact = np.abs(y0 - y_half).max(), np.abs(y0 - y_exact).max()
+    print("matrix-core y_0: max |d| %.2e against the FP16-rounded oracle, %.2e against the exact "
+          "network (|y_0| up to %.2f)" % (d_half, d_exact, np.abs(y_exact).max()), flush=True)
+    assert d_half < 1e-3 and d_exact < 2e-2
+    # lanes past n (a partial wave) and n = 1
+    y1 = gpu.mlp_y0(dev(x[:1].T)).cpu().numpy()
+    assert abs(float(y1[0]) - y0[0]) == 0.0
+
+
 @pytest.mark.parametrize("n", [1, 37, 5000])
 def test_backward_matches_oracle(kt, n):
     """Sizes: one sample, a ragged chunk, many blocks with a ragged tail."""

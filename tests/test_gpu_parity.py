@@ -383,50 +383,71 @@ def test_run_to_freezeout_matches_oracle_loop(kt):
     assert gpu.run_to_freezeout(T_f, 300, 5) == 0      # already below T_f
 
 
-def test_hotspot_128_against_oracle_samples(kt):
-    """The full 128^3 event: GPU fields after 50/100/200 steps against oracle
-    samples written by tests/golden/make_hotspot_golden.py.  The FP64 bar
-    (1e-9) holds at 50 and 100 steps; at 200 steps the dense cells
-    (e > 1e-3 e_max) must agree to 1e-7 and the median cell to 1e-13."""
+def golden_samples():
+    """The oracle samples of the 128^3 event (tests/golden/make_hotspot_golden.py),
+    checked to come from the oracle step as it is now: the file records the
+    SHA-256 of the oracle source above its diagnostics marker."""
+    import importlib.util
     path = os.path.join(ROOT, "tests", "golden", "hotspot_128_fp64.npz")
     if not os.path.exists(path):
         pytest.skip("oracle samples not generated")
     gold = np.load(path)
+    spec = importlib.util.spec_from_file_location(
+        "make_hotspot_golden", os.path.join(ROOT, "tests", "golden", "make_hotspot_golden.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    assert "oracle_sha" in gold.files and np.array_equal(gold["oracle_sha"], mk.oracle_sha()), \
+        "the oracle step changed since the samples were written: run tests/golden/make_hotspot_golden.py"
     w = I.workload_hotspot()
     import hashlib
     sha = hashlib.sha256(np.ascontiguousarray(w.prims.e).tobytes()).digest()
     assert np.array_equal(np.frombuffer(sha, np.uint8), gold["input_sha"])
+    import json
+    spread = json.loads(bytes(gold["spread_json"]).decode())
+    return gold, w, spread
+
+
+def sample_errors(f, gold, s, idx):
+    e = f["e"].reshape(-1)[idx].cpu().numpy()
+    u = f["u"].reshape(4, -1)[:, idx].cpu().numpy()
+    er, ur = gold["e_%d" % s], gold["u_%d" % s].T
+    tau, emax = float(gold["tau_%d" % s]), float(gold["emax_%d" % s])
+    de = np.abs(e - er) / np.maximum(er, 1e-6 * emax)
+    du = np.max(np.abs(u - ur) * np.array([1, 1, 1, tau])[:, None] / ur[0:1], axis=0)
+    return np.maximum(de, du), er > 1e-3 * emax
+
+
+def test_hotspot_128_against_oracle_samples(kt):
+    """The full 128^3 event: GPU fields after 50/100/200 steps against oracle
+    samples (2048 cells).  To 100 steps every sampled cell is within the FP64
+    bar of 1e-9.  At 200 steps the event amplifies last-bit differences: the
+    oracle against itself with the initial e perturbed by one ulp differs by
+    1.7e-6 in the dense cells (e > 1e-3 e_max) and by 8.5e-3 in the worst cell,
+    with 5% of the cells above 1e-9 (the spread the sample file records).  The
+    GPU rounds differently from the oracle at every step, so the bars at 200
+    steps are ten times that spread for the largest differences (all cells and
+    dense cells) and twice it for the fraction above 1e-9; the median cell
+    stays within 1e-13."""
+    gold, w, spread = golden_samples()
     gpu = kt.Solver(w.grid, w.config, w.eos, w.prims)
     idx = gold["idx"]
     done = 0
     for s in (50, 100, 200):
         gpu.step(s - done)
         done = s
-        f = gpu.fields(("e", "u", "q"))
-        e = f["e"].reshape(-1)[idx].cpu().numpy()
-        u = f["u"].reshape(4, -1)[:, idx].cpu().numpy()
-        er = gold["e_%d" % s]
-        ur = gold["u_%d" % s].T
-        tau = float(gold["tau_%d" % s])
-        emax = float(gold["emax_%d" % s])
-        de = np.abs(e - er) / np.maximum(er, 1e-6 * emax)
-        du = np.max(np.abs(u - ur) * np.array([1, 1, 1, tau])[:, None] / ur[0:1], axis=0)
-        hot = er > 1e-3 * emax
-        print("hotspot128 step %d: e %.2e u %.2e | e>1e-3 emax (%d cells): e %.2e u %.2e | "
-              "median e %.1e u %.1e | max u^tau %.3g" % (
-                  s, de.max(), du.max(), hot.sum(), de[hot].max(), du[hot].max(),
-                  np.median(de), np.median(du), ur[0].max()), flush=True)
+        d, hot = sample_errors(gpu.fields(("e", "u")), gold, s, idx)
+        ulp = spread[str(s)]["ulp"]
+        print("hotspot128 step %d: max %.2e | dense (%d cells) %.2e | median %.1e | above 1e-9 %.3f "
+              "| one-ulp spread of the oracle: max %.2e dense %.2e above 1e-9 %.3f" % (
+                  s, d.max(), hot.sum(), d[hot].max(), np.median(d), np.mean(d > 1e-9),
+                  ulp["max"], ulp["dense_max"], ulp["frac_above_1e9"]), flush=True)
         if s <= 100:
-            assert de.max() <= 1e-9 and du.max() <= 1e-9, (s, de.max(), du.max())
+            assert d.max() <= 1e-9, (s, d.max())
         else:
-            # beyond 100 steps rounding differences grow in the dilute edge: the floor
-            # reset and the M^2 clamp are discontinuous, so a last-bit difference can
-            # switch a near-floor cell one way on one side and the other way on the
-            # other.  The dense fireball and the bulk of the cells stay close.
-            print("  fraction of sampled cells above 1e-9: %.3f" %
-                  np.mean((de > 1e-9) | (du > 1e-9)), flush=True)
-            assert de[hot].max() <= 1e-7 and du[hot].max() <= 1e-7, (s, de[hot].max(), du[hot].max())
-            assert np.median(de) <= 1e-13 and np.median(du) <= 1e-13
+            assert d.max() <= max(1e-9, 10 * ulp["max"]), (s, d.max())
+            assert d[hot].max() <= max(1e-9, 10 * ulp["dense_max"]), (s, d[hot].max())
+            assert np.mean(d > 1e-9) <= max(0.01, 2 * ulp["frac_above_1e9"])
+            assert np.median(d) <= 1e-13
 
 
 # --------------------------------------------------------------- properties --
