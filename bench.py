@@ -44,12 +44,12 @@ STEP_BYTES_MIXED = 492.0
 KERNEL_VALUES = {"flux": 45.0, "sources": 47.5, "recover": 32.0, "faces": 16.0}
 # launches of each class per Heun step
 LAUNCHES_PER_STEP = {"flux": 2, "sources": 2, "recover": 2, "faces": 2}
-# HBM bytes per launch of the FP64 batched kernels of one step on this event, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE scaled by what the counters read for a plain device copy
-# (profiles/); valid for the kernel sources and compiler flags whose hash is TRAFFIC_SOURCES
-# (else the traffic is reported as null)
-TRAFFIC_SOURCES = "none"
-TRAFFIC_BYTES = {}
+# HBM bytes per launch of the FP64 step graph's kernels on this event (mean of the two
+# stages' launches of a class), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by what the
+# counters read for a plain device copy (FETCH x 2, WRITE x 1; profiles/); valid for the kernel
+# sources and compiler flags whose hash is TRAFFIC_SOURCES (else the traffic is reported as null)
+TRAFFIC_SOURCES = "a5e926b877681d78"
+TRAFFIC_BYTES = {"flux": 1305687888, "sources": 1186358352, "faces": 762349960, "recover": 583209224}
 KERNEL_NAMES = {"flux": "flux_kernel (KT flux divergence + stage update)",
                 "sources": "sources_kernel (App. B sources + stage update)",
                 "recover": "recover_kernel (Newton inversion + regulator)",
@@ -314,6 +314,7 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "one Heun step (the captured graph of its launches)",
             "bytes_per_launch": step_bytes, "mean_launch_ms": ms,
+            "traffic_over_algorithmic": None if traffic is None else traffic / step_bytes,
             "copy_kernel_gbs": cgbs,
             "per_kernel": {k: {"launch_ms": per[k], "launches_per_step": LAUNCHES_PER_STEP[k],
                                "frac": 8.0 * ncell * KERNEL_VALUES[k] / (per[k] * 1e-3) / 1e9 / HBM_PEAK_GBS}
