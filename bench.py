@@ -69,6 +69,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-events leg")
     ap.add_argument("--no-lattice", action="store_true", help="skip the lattice-QCD EOS and zeta/s(T) leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start leg")
+    ap.add_argument("--no-reduced", action="store_true", help="skip the reduced-state leg")
     ap.add_argument("--learn-steps", type=int, default=3000, help="Adam steps of the start network")
     return ap.parse_args()
 
@@ -251,6 +252,45 @@ def lattice_leg(args, rec, w, ncell, torch, kt, I):
     print("bench: lattice-QCD EOS and zeta/s(T) %.3f ms/step" % ms_l, file=sys.stderr, flush=True)
 
 
+# algorithmic values per cell and Heun step of the reduced state (T^{tau mu}, five pi
+# components and Pi evolved, 3 u components stored, u^tau from u.u = 1; Sec. 2.4):
+#   stage 1 reads q^n (10), u^n (3), u^{n-1} (3), e^n (1), writes q* (10), u* (3), e* (1)    = 31
+#   stage 2 reads q* (10), u* (3), e* (1), u^n (3), q^n (10), writes q^{n+1} (10), u (3), e (1) = 41
+STEP_VALUES_REDUCED = 72
+
+
+def reduced_leg(args, rec, w, ncell, torch, kt):
+    """The headline event and step count with the reduced state (kt_params.reduced):
+    the recovery solves for (e, u) and the five dependent pi components by a fixed
+    point (one inversion per pass); the flux and stage updates skip those five.
+    Replayed from the step graph; per-kernel eager launch times beside it."""
+    out = {}
+    for mixed in (False, True):
+        cfg = dict(w.config, reduced=True, mixed=mixed)
+        b = kt.Batch([(w.grid, cfg, w.prims)], w.eos, device="cuda:0")
+        b.tune()
+        o0 = b.observables(0)
+        ms = time_graph_steps(torch, b, args.warmup, args.steps)
+        o1 = b.observables(0)
+        b.close()
+        per, ms_eager, _ = eager_kernel_times(kt, torch, w, cfg, min(args.steps, 10))
+        nrec = max(1, o1["n_recover_cells"] - o0["n_recover_cells"])
+        out["mixed" if mixed else "fp64"] = {
+            "ms_per_step": ms, "value": ncell / (ms * 1e-3),
+            "state": "T^{tau mu} and u FP64; pi, Pi, e, p FP32" if mixed else "FP64",
+            "step_hbm_frac_of_reduced_balg": (None if mixed else
+                                              STEP_VALUES_REDUCED * 8.0 * ncell / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)),
+            "fixed_point_passes_per_recovery": (o1["fp_passes"] - o0["fp_passes"]) / nrec,
+            "newton_iters_per_recovery": (o1["newton_iters_cells"] - o0["newton_iters_cells"]) / nrec,
+            "recoveries_not_converged": o1["fp_not_converged"] - o0["fp_not_converged"],
+            "eager_ms_per_step": ms_eager, "per_kernel_launch_ms": per, "n_nan": o1["n_nan"]}
+        print("bench: reduced state%s %.3f ms/step, %.2f fixed-point passes per recovery" % (
+            " (mixed)" if mixed else "", ms, out["mixed" if mixed else "fp64"]["fixed_point_passes_per_recovery"]),
+            file=sys.stderr, flush=True)
+    out["algorithmic_values_per_cell_step"] = STEP_VALUES_REDUCED
+    rec["variants"]["reduced_state"] = out
+
+
 def eager_kernel_times(kt, torch, w, cfg, n_steps):
     """Per-launch times of the four kernel classes of the eager step (HIP events
     around each launch on the library's stream; outside the timed region), and
@@ -357,6 +397,8 @@ def main():
     # the same event and step count, FP64, with the lattice-QCD EOS table (Sec. 2)
     if not args.no_lattice:
         lattice_leg(args, rec, w, ncell, torch, kt, I)
+    if not args.no_reduced:
+        reduced_leg(args, rec, w, ncell, torch, kt)
     if not args.no_batch:
         # 48 hot-spot events on uneven grids, FP32 state, one launch per kernel for all
         # events, one step replayed as a hipGraph, tiling autotuned

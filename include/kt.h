@@ -111,6 +111,18 @@ typedef struct {
                                     * 15 (1/3 - c_s^2)^2 T / (zeta/s) */
     double zeta_tc;                /* T_c of KT_ZETA_PAPER (> 0), in the EOS's temperature unit;
                                     * ignored by KT_ZETA_LINEAR */
+    int32_t reduced;               /* 0, or 1: reduced state (Sec. 2.4 and Sec. 4.2).  The step
+                                    * evolves T^{tau mu}, pi^{xx}, pi^{xy}, pi^{x eta}, pi^{yy},
+                                    * pi^{y eta} and Pi; pi^{tau mu} and pi^{eta eta} follow from
+                                    * u_mu pi^{mu nu} = 0 and pi^mu_mu = 0 (Eqs. pi_tautau ..
+                                    * pi_etaeta).  Each recovery solves for (e, u) and those five
+                                    * together (a fixed point over u, started from the flow before
+                                    * the stage, to 1e-14 u^tau, at most 100 passes) and stores
+                                    * them beside the five, so the face and source kernels read the
+                                    * whole tensor; the flux and stage updates skip them.  The
+                                    * initial state's pi^{tau mu} and pi^{eta eta} are not read.
+                                    * Newton starts from the conformal closed form only
+                                    * (kt_set_inv_start: KT_E_UNSUPPORTED for another start). */
 } kt_params;
 
 /* Initial data on the device.  Either q[0..14] (conserved form; all 15
@@ -153,6 +165,11 @@ typedef struct {
     int64_t newton_iters_faces, n_recover_faces;
     int64_t n_floor, n_clamp, n_fallback;   /* cells */
     int64_t n_fallback_faces;               /* face states solved by bisection */
+    /* reduced state (kt_params.reduced): passes of the recoveries' fixed point
+     * (each one inversion; newton_iters_cells sums the iterations of every
+     * pass) and cell recoveries that reached the pass limit without meeting
+     * the tolerance; 0 otherwise */
+    int64_t fp_passes, fp_not_converged;
 } kt_obs;
 
 /* Device workspace needed for p and eos (bytes, multiple of 256), 0 if the

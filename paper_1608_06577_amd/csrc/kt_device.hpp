@@ -27,7 +27,9 @@ enum : int { F_FLOOR = 1, F_CLAMP = 2, F_FALLBACK = 4 };
 // counters, one slot row per wavefront
 enum : int {
     C_ITERS_CELLS = 0, C_REC_CELLS, C_ITERS_FACES, C_REC_FACES, C_FLOOR, C_CLAMP, C_FALLBACK,
-    C_FALLBACK_FACES, C_COUNT
+    C_FALLBACK_FACES,
+    C_FP_PASSES, C_FP_NOCONV,   // reduced state: fixed-point passes of the recoveries, cells not converged
+    C_COUNT
 };
 
 // EOS node layout: p/e, T/e^{1/4}, c_s^2, 1/e_i
@@ -56,6 +58,7 @@ struct Phys {
     double xi0, rho_max;
     double e_floor, p_floor, m2_delta, newton_tol;
     int newton_max;
+    int reduced;         // evolve the five independent pi components only (Sec. 2.4)
 };
 
 __host__ __device__ __forceinline__ int pi_index(int m, int n)
@@ -364,6 +367,45 @@ __device__ __forceinline__ double regulate(const Phys &P, double tau, double q[N
     for (int c = PTT; c <= PEE; ++c) q[c] *= fac;
     if (P.regulate_bulk) q[BPI] *= fac;
     return fac;
+}
+
+// ------------------------------------------------------ reduced state ---
+// Sec. 2.4: u_mu pi^{mu nu} = 0 and g_{mu nu} pi^{mu nu} = 0 leave five
+// components of pi independent.  Given pi^{xx}, pi^{xy}, pi^{x eta}, pi^{yy},
+// pi^{y eta} and the flow (v^i = u^i / u^tau, g33 = tau^2 or 1):
+//   each row of the orthogonality relation, pi^{m tau} = pi^{m x} v^x +
+//   pi^{m y} v^y + g33 pi^{m eta} v^eta (m = x, y, eta, then tau), and the
+//   trace pi^{tau tau} = pi^{xx} + pi^{yy} + g33 pi^{eta eta} fix pi^{eta eta}
+//   first (Eq. pi_etaeta): inserting the rows into the trace gives
+//   g33 (1 - g33 v_eta^2) pi^{eta eta} = pi^{xx}(v_x^2 - 1) + pi^{yy}(v_y^2 - 1)
+//     + 2 pi^{xy} v_x v_y + 2 g33 v_eta (pi^{x eta} v_x + pi^{y eta} v_y),
+//   then pi^{tau eta}, pi^{tau y}, pi^{tau x} and pi^{tau tau} (Eq. pi_tautau
+//   and the relations after it).
+// q holds the ten pi components at PTT..PEE; the five dependent ones are written.
+template <bool CART>
+__device__ __forceinline__ void pi_dependent_of(double tau, const double u[4], double q[NQ])
+{
+    const double g33 = CART ? 1.0 : tau * tau;
+    const double iut = 1.0 / u[0];
+    const double vx = u[1] * iut, vy = u[2] * iut, ve = u[3] * iut;
+    const double a = q[PXX], b = q[PXY], c = q[PXE], d = q[PYY], f = q[PYE];
+    const double rhs = a * (vx * vx - 1.0) + d * (vy * vy - 1.0) + 2.0 * b * vx * vy
+                       + 2.0 * g33 * ve * (c * vx + f * vy);
+    const double pee = rhs / (g33 * (1.0 - g33 * ve * ve));
+    const double pte = c * vx + f * vy + g33 * pee * ve;
+    const double pty = b * vx + d * vy + g33 * f * ve;
+    const double ptx = a * vx + b * vy + g33 * c * ve;
+    q[PEE] = pee;
+    q[PTE] = pte;
+    q[PTY] = pty;
+    q[PTX] = ptx;
+    q[PTT] = ptx * vx + pty * vy + g33 * pte * ve;
+}
+
+// components of q that the reduced state does not evolve
+__host__ __device__ __forceinline__ bool pi_is_dependent(int c)
+{
+    return (c >= PTT && c <= PTE) || c == PEE;
 }
 
 // ---------------------------------------------------------------- minmod --

@@ -538,7 +538,8 @@ __device__ __forceinline__ void sources_body(const Phys &P, const Eos &E, double
 #pragma unroll
         for (int c = 0; c < PTT; ++c) qn4[c] = ld(qnT, (idx_t)c * SS + s);
 #pragma unroll
-        for (int c = 0; c < NQ - PTT; ++c) qn11[c] = ld(qnP, (idx_t)c * SS + s);
+        for (int c = 0; c < NQ - PTT; ++c)
+            qn11[c] = P.reduced && pi_is_dependent(c + PTT) ? S(0) : ld(qnP, (idx_t)c * SS + s);
     }
     // T^{tau mu}: FP64 value, source and accumulation
     auto emitT = [&](int c, double qc, double Jc) {
@@ -546,7 +547,10 @@ __device__ __forceinline__ void sources_body(const Phys &P, const Eos &E, double
         const double t = qc + dt * Jc;
         st(outT, o, STAGE2 ? qn4[c] + t : t);
     };
+    // (a reduced state evolves five of the ten pi components; the recovery
+    // rebuilds the others)
     auto emitP = [&](int c, R qc, R Jc) {
+        if (P.reduced && pi_is_dependent(c)) return;
         const idx_t o = (idx_t)(c - PTT) * SS + s;
         const R t = qc + R(dt) * Jc;
         st(outP, o, STAGE2 ? R(qn11[c - PTT]) + t : t);
@@ -807,7 +811,8 @@ __device__ __forceinline__ void flux_body(const Phys &P, const FaceGeo &G, const
 #pragma unroll 1
     for (int c = 0; c < PTT; ++c) component(0.0, qT, (idx_t)c * SS, outT);
 #pragma unroll 1
-    for (int c = c0; c < c1; ++c) component(R(0), qP, (idx_t)(c - PTT) * SS, outP);
+    for (int c = c0; c < c1; ++c)
+        if (!(P.reduced && pi_is_dependent(c))) component(R(0), qP, (idx_t)(c - PTT) * SS, outP);
 }
 
 template <bool STAGE2, bool T1, typename S, int KCC>
@@ -910,6 +915,101 @@ __device__ __forceinline__ void recover_body(const Phys &P, const Eos &E, double
     slot_add(slots, wave, C_FALLBACK, (fl & F_FALLBACK) ? 1 : 0);
 }
 
+// Recovery of a reduced state (Sec. 2.4; the state evolves T^{tau mu}, the
+// five independent pi components and Pi): pi^{tau mu}, which the inversion
+// needs, depends on the velocity being recovered, so (e, u) and the dependent
+// components are solved together by the fixed point
+//   u_{k+1} = inversion of (T^{tau mu}, pi^{tau mu}(five, u_k), Pi),
+// started from us (the cell's flow before the stage, u^tau renormalised at
+// tau; null: at rest), each inversion from the conformal closed form, stopped
+// when no component of u moves by more than FP_TOL u^tau (the eta component
+// times sqrt(g33)), on the floor state, without shear (one pass), or after
+// FP_MAX passes (counted as not converged).  The dependent components of the
+// final u are stored with the five, then the floor reset and the regulator act
+// as in recover_body (the regulator on the whole tensor).
+constexpr double FP_TOL = 1e-14;
+constexpr int FP_MAX = 100;
+
+template <bool CART, typename S>
+__device__ __forceinline__ void recover_reduced_body(const Phys &P, const Eos &E, double tau, double *qT,
+                                                     S *qP, S *e_out, S *p_out, double *u_out,
+                                                     const double *us, int do_regulate,
+                                                     unsigned long long *slots, idx_t s)
+{
+    const long long wave = s >> 6;
+    const idx_t SS = (idx_t)P.stride;
+    const double g33 = CART ? 1.0 : tau * tau;
+    int it = 0, fl = 0, passes = 0, noconv = 0;
+    const bool valid = (long long)s < P.ncell;
+    if (valid) {
+        double qc[NQ];
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) qc[c] = pi_is_dependent(c) ? 0.0 : ldq(qT, qP, c, SS, s);
+        const double Pi = P.bulk ? qc[BPI] : 0.0;
+        double u[4] = {1.0, 0.0, 0.0, 0.0};
+        if (us) {
+#pragma unroll
+            for (int m = 1; m < 4; ++m) u[m] = ld(us, (idx_t)m * SS + s);
+            u[0] = sqrt(1.0 + u[1] * u[1] + u[2] * u[2] + g33 * u[3] * u[3]);
+        }
+        double e = 0.0, p0 = 0.0;
+        bool conv = false;
+        const double sg = sqrt(g33);
+        while (passes < FP_MAX) {
+            if (P.shear) pi_dependent_of<CART>(tau, u, qc);
+            double un[4];
+            int its = 0;
+            fl = recover<CART>(P, E, tau, qc[TT], qc[TX], qc[TY], qc[TE], qc[PTT], qc[PTX], qc[PTY],
+                               qc[PTE], Pi, -1.0, e, p0, un, its);
+            it += its;
+            ++passes;
+            double dmax = 0.0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                dmax = fmax(dmax, fabs(un[m] - u[m]) * (m == 3 ? sg : 1.0) / un[0]);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) u[m] = un[m];
+            if ((fl & F_FLOOR) || !P.shear || dmax <= FP_TOL) {
+                conv = true;
+                break;
+            }
+        }
+        noconv = conv ? 0 : 1;
+        st(e_out, s, (S)e);
+        st(p_out, s, (S)p0);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) st(u_out, (idx_t)(m) * SS + s, u[m]);
+        if ((fl & F_FLOOR) && P.floor_reset) {
+#pragma unroll
+            for (int c = 0; c < PTT; ++c) st(qT, (idx_t)c * SS + s, c == TT ? P.e_floor : 0.0);
+#pragma unroll
+            for (int c = PTT; c < NQ; ++c) st(qP, (idx_t)(c - PTT) * SS + s, (S)0);
+        } else if (P.shear) {
+            pi_dependent_of<CART>(tau, u, qc);
+            if (do_regulate && P.regulate) regulate<CART>(P, tau, qc, e, p0, u);
+#pragma unroll
+            for (int c = PTT; c < NQ; ++c) st(qP, (idx_t)(c - PTT) * SS + s, (S)qc[c]);
+        }
+    }
+    slot_add(slots, wave, C_ITERS_CELLS, it, 16);     // summed over at most FP_MAX passes
+    slot_add(slots, wave, C_REC_CELLS, valid ? 1 : 0);
+    slot_add(slots, wave, C_FLOOR, (fl & F_FLOOR) ? 1 : 0);
+    slot_add(slots, wave, C_CLAMP, (fl & F_CLAMP) ? 1 : 0);
+    slot_add(slots, wave, C_FALLBACK, (fl & F_FALLBACK) ? 1 : 0);
+    slot_add(slots, wave, C_FP_PASSES, passes, 32 - __clz(FP_MAX));
+    slot_add(slots, wave, C_FP_NOCONV, noconv);
+}
+
+template <bool CART, typename S>
+__global__ __launch_bounds__(256) void recover_reduced_kernel(Phys P, Eos E, double tau, double *qT, S *qP,
+                                                              S *e_out, S *p_out, double *u_out,
+                                                              const double *us, int do_regulate,
+                                                              unsigned long long *slots)
+{
+    recover_reduced_body<CART, S>(P, E, tau, qT, qP, e_out, p_out, u_out, us, do_regulate, slots,
+                                  (idx_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 template <bool CART, bool LEARNED, typename S>
 __global__ __launch_bounds__(256) void recover_kernel(Phys P, Eos E, double tau, double *qT, S *qP,
                                                       S *e_io, S *p_out, double *u_out,
@@ -952,6 +1052,7 @@ struct BRec {               // one event of a recovery launch
     double *qT;
     S *qP, *e, *p;
     double *u;
+    const double *us;       // flow before the stage (start of a reduced state's fixed point)
     unsigned long long *slots;
 };
 
@@ -999,7 +1100,7 @@ __global__ __launch_bounds__(256) void flux_batch(const BStage<S> *__restrict__ 
     flux_body<STAGE2, T1, S, KCC>(A.P, A.G, A.F.qT, A.F.qP, A.F.vf, A.outT, A.outP, Lc, bx, by, bz, A.tw);
 }
 
-template <bool CART, typename S>
+template <bool CART, typename S, bool RED>
 __global__ __launch_bounds__(256) void recover_batch(const BRec<S> *__restrict__ tab,
                                                      const unsigned short *__restrict__ map,
                                                      const unsigned *__restrict__ first,
@@ -1009,10 +1110,13 @@ __global__ __launch_bounds__(256) void recover_batch(const BRec<S> *__restrict__
     const int ev = map[g];
     const BRec<S> &A = tab[ev];
     const double tau = tau_dev[0] + A.P.dtau;
+    const idx_t s = (idx_t)(g - first[ev]) * 256 + threadIdx.x;
     // events of a batch keep the library's default Newton start (KT_START_CONFORMAL:
     // warm = 0), as a single context does
-    recover_body<CART, false, S>(A.P, A.E, tau, A.qT, A.qP, A.e, A.p, A.u, 1, 0, nullptr, nullptr, A.slots,
-                                 (idx_t)(g - first[ev]) * 256 + threadIdx.x);
+    if (RED)
+        recover_reduced_body<CART, S>(A.P, A.E, tau, A.qT, A.qP, A.e, A.p, A.u, A.us, 1, A.slots, s);
+    else
+        recover_body<CART, false, S>(A.P, A.E, tau, A.qT, A.qP, A.e, A.p, A.u, 1, 0, nullptr, nullptr, A.slots, s);
 }
 
 template <bool CART, bool T1, typename S>
@@ -1609,6 +1713,7 @@ static const char *check_args(const kt_params *p, const kt_eos *eos)
     if (!(p->m2_delta > 0 && p->m2_delta < 1)) return "m2_delta must lie in (0, 1)";
     if (!(p->newton_tol > 0) || p->newton_max < 1) return "Newton tolerance and iteration limit must be positive";
     if (p->precision != KT_FP64 && p->precision != KT_MIXED) return "precision must be KT_FP64 or KT_MIXED";
+    if (p->reduced != 0 && p->reduced != 1) return "reduced must be 0 or 1";
     if (eos->conformal) {
         if (!(eos->a_sb > 0)) return "conformal EOS needs a_sb > 0";
     } else {
@@ -1660,6 +1765,7 @@ static void fill_phys(const kt_params *p, Phys &P)
     P.xi0 = p->xi0; P.rho_max = p->rho_max;
     P.e_floor = p->e_floor; P.m2_delta = p->m2_delta; P.newton_tol = p->newton_tol;
     P.newton_max = p->newton_max;
+    P.reduced = p->reduced;
 }
 
 template <typename K, typename... A>
@@ -1683,11 +1789,28 @@ static hipError_t ensure_packed(kt_ctx *c)
 
 // warm != 0: a step's recovery, whose start follows the context's choice
 // (previous e, conformal closed form, or the network); warm == 0: conformal.
-// which: 0 = q, 1 = q*; ub: u buffer receiving u.
+// which: 0 = q, 1 = q*; ub: u buffer receiving u; us: u buffer holding the
+// flow before the stage, where a reduced state's fixed point starts (-1: at rest).
 template <typename S>
-static kt_status run_recover_t(kt_ctx *c, double tau, int which, int ub, int regulate, int warm)
+static kt_status run_recover_t(kt_ctx *c, double tau, int which, int ub, int regulate, int warm, int us)
 {
     const bool cart = c->prm.coords == KT_CARTESIAN;
+    if (c->P.reduced) {
+        hipError_t e = prof_mark(c, 1, true);
+        if (e != hipSuccess) return fail(c, KT_E_HIP, "profiling event: %s", hipGetErrorString(e));
+        const double *u0 = us >= 0 ? (const double *)c->u[us] : nullptr;
+        double *qT = c->qT[which];
+        S *qP = (S *)c->qP[which], *ee = (S *)c->e, *pp = (S *)c->p;
+        double *uu = (double *)c->u[ub];
+        const dim3 g = linear_grid(c->P.ncell), b(256);
+        e = cart ? launch(recover_reduced_kernel<true, S>, g, b, c->stream, c->P, c->E, tau, qT, qP, ee, pp, uu,
+                          u0, regulate, c->slots)
+                 : launch(recover_reduced_kernel<false, S>, g, b, c->stream, c->P, c->E, tau, qT, qP, ee, pp, uu,
+                          u0, regulate, c->slots);
+        if (e == hipSuccess) e = prof_mark(c, 1, false);
+        if (e != hipSuccess) return fail(c, KT_E_HIP, "recover kernel: %s", hipGetErrorString(e));
+        return KT_OK;
+    }
     const bool learned = warm && c->inv_start == KT_START_LEARNED;
     if (warm && c->inv_start == KT_START_CONFORMAL) warm = 0;
     if (learned) warm = 0;
@@ -1715,10 +1838,10 @@ static kt_status run_recover_t(kt_ctx *c, double tau, int which, int ub, int reg
     return KT_OK;
 }
 
-static kt_status run_recover(kt_ctx *c, double tau, int which, int ub, int regulate, int warm)
+static kt_status run_recover(kt_ctx *c, double tau, int which, int ub, int regulate, int warm, int us)
 {
-    return c->mixed ? run_recover_t<float>(c, tau, which, ub, regulate, warm)
-                    : run_recover_t<double>(c, tau, which, ub, regulate, warm);
+    return c->mixed ? run_recover_t<float>(c, tau, which, ub, regulate, warm, us)
+                    : run_recover_t<double>(c, tau, which, ub, regulate, warm, us);
 }
 
 template <typename S>
@@ -1942,7 +2065,7 @@ kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0
     }
     if (he != hipSuccess) { kt_destroy(c); return fail(nullptr, KT_E_HIP, "initial state: %s", hipGetErrorString(he)); }
     // (e^0, u^0) and u^{-1}
-    kt_status st = run_recover(c, c->tau, 0, c->ucur, 0, 0);
+    kt_status st = run_recover(c, c->tau, 0, c->ucur, 0, 0, -1);
     if (st == KT_OK) st = run_faces(c, c->tau, 0);
     if (st != KT_OK) { kt_status r = fail(nullptr, st, "%s", c->err); kt_destroy(c); return r; }
     for (int m = 0; m < 4 && he == hipSuccess; ++m)
@@ -1963,14 +2086,14 @@ kt_status kt_step(kt_ctx *c, int32_t n_steps)
         // face speeds of q^n are current (computed after the previous recovery)
         kt_status st = run_stage(c, false, tau0, 0, c->ucur, c->uprev);
         if (st != KT_OK) return st;
-        st = run_recover(c, tau1, 1, c->ustar, 1, 1);
+        st = run_recover(c, tau1, 1, c->ustar, 1, 1, c->ucur);
         if (st == KT_OK) st = run_faces(c, tau1, 1);
         if (st != KT_OK) return st;
         st = run_stage(c, true, tau1, 1, c->ustar, c->ucur);
         if (st != KT_OK) return st;
         // u^{n-1} <- u^n; (e, u)^{n+1} into the freed buffer
         const int freed = c->uprev;
-        st = run_recover(c, tau1, 0, freed, 1, 1);
+        st = run_recover(c, tau1, 0, freed, 1, 1, c->ustar);
         if (st == KT_OK) st = run_faces(c, tau1, 0);
         if (st != KT_OK) return st;
         c->uprev = c->ucur;
@@ -2090,6 +2213,8 @@ kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out)
         host_out->n_clamp = (int64_t)ctr[C_CLAMP];
         host_out->n_fallback = (int64_t)ctr[C_FALLBACK];
         host_out->n_fallback_faces = (int64_t)ctr[C_FALLBACK_FACES];
+        host_out->fp_passes = (int64_t)ctr[C_FP_PASSES];
+        host_out->fp_not_converged = (int64_t)ctr[C_FP_NOCONV];
     }
     return KT_OK;
 }
@@ -2179,6 +2304,8 @@ kt_status kt_set_inv_start(kt_ctx *c, int32_t start)
         return fail(c, KT_E_ARG, "unknown start %d", start);
     if (start == KT_START_LEARNED && !c->mlp_ready)
         return fail(c, KT_E_STATE, "the learned start needs parameters (kt_mlp_set)");
+    if (c->P.reduced && start != KT_START_CONFORMAL)
+        return fail(c, KT_E_UNSUPPORTED, "a reduced state starts every inversion from the conformal closed form");
     c->inv_start = start;
     return KT_OK;
 }
@@ -2403,6 +2530,7 @@ struct kt_batch {
     hipStream_t cap;             // stream the step graph is captured on and replayed on
     hipEvent_t fork_ev, join_ev;
     bool mixed, cart;
+    bool reduced;                // reduced states (kt_params.reduced)
     bool theta1;                 // every event limits with theta = 1
     double dtau;
     double *tau_dev;
@@ -2523,6 +2651,7 @@ static kt_status batch_tables(kt_batch *b)
                 R.e = (S *)c->e;
                 R.p = (S *)c->p;
                 R.u = uu(st == 0 ? 2 : prev);
+                R.us = uu(st == 0 ? cur : 2);
                 R.slots = c->slots;
             }
         }
@@ -2616,9 +2745,13 @@ static hipError_t batch_step_launches(kt_batch *b, hipStream_t st, int par)
     };
     if (e == hipSuccess)
         e = b->kcc == 4 ? flux(flux_batch<false, T1, S, 4>, b->o_s1[par]) : flux(flux_batch<false, T1, S, 2>, b->o_s1[par]);
-    if (e == hipSuccess)
-        e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r1[par]),
-                   M(b->o_mrec), F(b->o_frec), tau);
+    auto recover = [&](size_t o) {
+        return b->reduced ? launch(recover_batch<CART, S, true>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(o),
+                                   M(b->o_mrec), F(b->o_frec), tau)
+                          : launch(recover_batch<CART, S, false>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(o),
+                                   M(b->o_mrec), F(b->o_frec), tau);
+    };
+    if (e == hipSuccess) e = recover(b->o_r1[par]);
     if (e == hipSuccess)
         e = launch(faces_batch<CART, T1, S>, dim3(b->nb_face), dim3(FACE_BLOCK), st, (const BFace<S> *)T(b->o_f1),
                    M(b->o_mface), F(b->o_fface), tau);
@@ -2627,9 +2760,7 @@ static hipError_t batch_step_launches(kt_batch *b, hipStream_t st, int par)
                    (const BStage<S> *)T(b->o_s2[par]), M(b->o_msrc), F(b->o_fsrc), tau);
     if (e == hipSuccess)
         e = b->kcc == 4 ? flux(flux_batch<true, T1, S, 4>, b->o_s2[par]) : flux(flux_batch<true, T1, S, 2>, b->o_s2[par]);
-    if (e == hipSuccess)
-        e = launch(recover_batch<CART, S>, dim3(b->nb_rec), blk, st, (const BRec<S> *)T(b->o_r2[par]),
-                   M(b->o_mrec), F(b->o_frec), tau);
+    if (e == hipSuccess) e = recover(b->o_r2[par]);
     if (e == hipSuccess)
         e = launch(faces_batch<CART, T1, S>, dim3(b->nb_face), dim3(FACE_BLOCK), st, (const BFace<S> *)T(b->o_f2),
                    M(b->o_mface), F(b->o_fface), tau);
@@ -2741,8 +2872,9 @@ kt_status kt_batch_init(const kt_params *p, int32_t n_events, const kt_eos *eos,
     for (int e = 0; e < n_events; ++e) {
         if (const char *m = check_args(&p[e], eos)) return bfail(nullptr, KT_E_ARG, "event %d: %s", e, m);
         if (p[e].coords != p[0].coords || p[e].precision != p[0].precision || p[e].dtau != p[0].dtau ||
-            p[e].tau0 != p[0].tau0)
-            return bfail(nullptr, KT_E_ARG, "event %d: coords, precision, tau0 and dtau must match event 0", e);
+            p[e].tau0 != p[0].tau0 || p[e].reduced != p[0].reduced)
+            return bfail(nullptr, KT_E_ARG,
+                         "event %d: coords, precision, reduced, tau0 and dtau must match event 0", e);
     }
     const size_t need = kt_batch_workspace_bytes(p, n_events, eos);
     if (ws_bytes < need) return bfail(nullptr, KT_E_ALLOC, "workspace has %zu bytes, needs %zu", ws_bytes, need);
@@ -2752,6 +2884,7 @@ kt_status kt_batch_init(const kt_params *p, int32_t n_events, const kt_eos *eos,
     b->user = stream;
     b->mixed = p[0].precision == KT_MIXED;
     b->cart = p[0].coords == KT_CARTESIAN;
+    b->reduced = p[0].reduced != 0;
     b->theta1 = true;
     for (int k = 0; k < n_events; ++k) b->theta1 = b->theta1 && theta_is_one(p[k].theta);
     b->dtau = p[0].dtau;

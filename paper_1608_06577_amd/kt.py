@@ -39,7 +39,7 @@ class KtParams(C.Structure):
                 ("regulate_bulk", C.c_int32), ("xi0", C.c_double), ("rho_max", C.c_double),
                 ("e_floor", C.c_double), ("m2_delta", C.c_double), ("floor_resets_q", C.c_int32),
                 ("newton_tol", C.c_double), ("newton_max", C.c_int32), ("precision", C.c_int32),
-                ("zeta_model", C.c_int32), ("zeta_tc", C.c_double)]
+                ("zeta_model", C.c_int32), ("zeta_tc", C.c_double), ("reduced", C.c_int32)]
 
 
 class KtInitState(C.Structure):
@@ -60,7 +60,8 @@ class KtObs(C.Structure):
                 ("newton_iters_cells", C.c_int64), ("n_recover_cells", C.c_int64),
                 ("newton_iters_faces", C.c_int64), ("n_recover_faces", C.c_int64),
                 ("n_floor", C.c_int64), ("n_clamp", C.c_int64), ("n_fallback", C.c_int64),
-                ("n_fallback_faces", C.c_int64)]
+                ("n_fallback_faces", C.c_int64), ("fp_passes", C.c_int64),
+                ("fp_not_converged", C.c_int64)]
 
     def as_dict(self):
         d = {}
@@ -181,7 +182,8 @@ def make_params(grid, config: dict, tau0: float) -> KtParams:
         config.get("rho_max", 1.0), config["e_floor"], config.get("m2_delta", 1e-3),
         int(config.get("floor_resets_q", True)), config.get("newton_tol", 1e-12),
         int(config.get("newton_max", 50)), KT_MIXED if config.get("mixed", False) else KT_FP64,
-        int(config.get("zeta_model", 0)), config.get("zeta_tc", 0.2 / 0.1973269804))
+        int(config.get("zeta_model", 0)), config.get("zeta_tc", 0.2 / 0.1973269804),
+        int(config.get("reduced", False)))
 
 
 class EosHost:

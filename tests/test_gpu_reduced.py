@@ -1,0 +1,152 @@
+"""The reduced state on the GPU (kt_params.reduced; Sec. 2.4 and Sec. 4.2):
+T^{tau mu}, the five independent pi components and Pi evolve, pi^{tau mu} and
+pi^{eta eta} are rebuilt with the flow by the coupled recovery.  Parity with
+the oracle's reduced mode (oracle.ReducedSimulation) through the C ABI, with
+the error measures of test_gpu_parity; the FP64 bar after 100 steps is 1e-9
+in e and u, as for the ten-component state.  Batches of reduced events equal
+separate contexts bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_06577_amd import inputs as I
+
+from tests.test_gpu_parity import e_err, q_err, u_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kt():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1608_06577_amd import kt as K
+    K.lib()
+    return K
+
+
+def run_reduced(kt, w, nsteps, report, **extra):
+    cfg = dict(w.config, reduced=True, **extra)
+    phys = oracle.Physics.from_config(w.grid, cfg)
+    sim = oracle.ReducedSimulation.from_primitives(phys, w.eos, w.prims)
+    gpu = kt.Solver(w.grid, cfg, w.eos, w.prims)
+    obs0 = gpu.observables()       # counters of the initial recovery, which the oracle does not count
+    if nsteps:
+        sim.step(nsteps)
+        gpu.step(nsteps)
+    f = {k: v.cpu().numpy() for k, v in gpu.fields().items()}
+    r = sim.fields()
+    errs = dict(e=e_err(f["e"], r["e"]), u=u_err(f["u"], r["u"], sim.tau),
+                q=q_err(f["q"], r["q"]).max(), up=u_err(f["u_prev"], r["up"], sim.tau))
+    obs = gpu.observables()
+    for k in ("fp_passes", "fp_not_converged", "n_recover_cells"):
+        obs["step_" + k] = obs[k] - obs0[k]
+    print(report, nsteps, "steps:", {k: "%.2e" % v for k, v in errs.items()},
+          "passes per recovery gpu %.3f oracle %.3f, not converged gpu %d oracle %d" % (
+              obs["step_fp_passes"] / max(1, obs["step_n_recover_cells"]),
+              sim.fp[0] / max(1, sim.stats.n_recover), obs["step_fp_not_converged"], sim.fp[1]), flush=True)
+    return errs, gpu, sim, f, r, obs
+
+
+def test_reduced_initial_recovery(kt):
+    """The coupled recovery of the initial state (viscous Gubser flow, whose pi
+    is not zero): e, u and the rebuilt pi^{tau mu}, pi^{eta eta} against the
+    oracle, and the rebuilt tensor against the one the initial data gave."""
+    w = I.workload_gubser_viscous(n=24, n_steps=0)
+    errs, gpu, sim, f, r, obs = run_reduced(kt, w, 0, "gubser24 init")
+    assert errs["e"] <= 1e-13 and errs["u"] <= 1e-13 and errs["q"] <= 1e-12, errs
+    # the initial data are transverse and traceless, so the rebuilt components
+    # are the given ones
+    full = oracle.Simulation.from_primitives(oracle.Physics.from_config(w.grid, w.config), w.eos, w.prims)
+    qf = full.fields()["q"]
+    for c in (4, 5, 6, 7, 13):
+        m = np.abs(qf[8]).max()
+        assert np.max(np.abs(f["q"][c] - qf[c])) <= 1e-11 * m, c
+    assert obs["fp_passes"] > obs["n_recover_cells"] and obs["fp_not_converged"] == 0
+
+
+def test_reduced_gubser_viscous_100_steps(kt):
+    """Conformal viscous Gubser flow on the 32^3 grid (theta = 1.8, eta/s = 0.2,
+    periodic in eta): 100 Heun steps of the reduced state."""
+    w = I.workload_gubser_viscous(n=32, n_steps=100)
+    errs, gpu, sim, f, r, obs = run_reduced(kt, w, 100, "gubser32 reduced")
+    assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9 and errs["q"] <= 1e-9 and errs["up"] <= 1e-9, errs
+    assert obs["n_nan"] == 0 and abs(obs["tau"] - sim.tau) < 1e-12
+    # pass counts: the same fixed point from the same start; the last pass of a
+    # cell can fall on either side of the tolerance by rounding
+    assert abs(obs["step_fp_passes"] - sim.fp[0]) <= 1e-3 * sim.fp[0]
+    assert obs["step_fp_not_converged"] == sim.fp[1] == 0
+    # the rebuilt tensor is transverse and traceless
+    assert obs["pi_transverse"] < 1e-10 and obs["pi_trace"] < 1e-10, obs
+
+
+def test_reduced_hotspot_small_grid_50_steps(kt):
+    """The non-conformal viscous hot-spot event (shear + bulk, tabulated EOS,
+    regulator, floor and clamp) on the 56x52x24 grid, reduced state, 50 steps."""
+    w = I.workload_hotspot(nx=56, ny=52, neta=24, dx=0.4, deta=0.5, n_hot=60, seed=3)
+    errs, gpu, sim, f, r, obs = run_reduced(kt, w, 50, "hotspot56 reduced")
+    assert obs["n_floor"] > 0 and obs["n_nan"] == 0
+    assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9, errs
+    assert abs(obs["step_fp_passes"] - sim.fp[0]) <= 1e-3 * sim.fp[0]
+
+
+def test_reduced_bjorken_lattice_eos_2plus1d(kt):
+    """Bjorken flow on the lattice-QCD EOS with zeta/s(T) (Sec. 5.5) on a 2+1d
+    grid, reduced state, 200 steps: GPU against the oracle, and the rebuilt
+    tau^2 pi^{eta eta} = -(pi^{xx} + pi^{yy}) of a flow at rest."""
+    from tests.test_oracle_flows import e_of_T
+    eos = I.eos_lattice_table()
+    tau0, tc = 0.25, 0.2 / I.HBARC
+    e0 = e_of_T(eos, 0.6 / I.HBARC)
+    P0, _, T0 = (a[0] for a in oracle.eos_eval(eos, np.array([e0])))
+    g = I.Grid(20, 12, 1, 0.1, 0.1, 0.1)
+    cfg = I.default_config(dtau=0.01, periodic=(True, True, False), eta_s=0.2, zeta_coef=1.0,
+                           zeta_model=1, zeta_tc=tc)
+    w = I.Workload("bjorken_lattice", g, tau0, 200, cfg, eos, I.bjorken_fields(g, tau0, e0, T0, 0.2, P0))
+    errs, gpu, sim, f, r, obs = run_reduced(kt, w, 200, "bjorken_lattice_2+1d reduced")
+    assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9 and errs["q"] <= 1e-9, errs
+    q = f["q"].reshape(15, -1)
+    assert np.max(np.abs(sim.tau ** 2 * q[13] + q[8] + q[11])) <= 1e-13 * np.abs(q[8]).max()
+
+
+def test_reduced_mixed_precision_gubser(kt):
+    """The reduced state with mixed-precision storage (pi, Pi, e, p in FP32)
+    against the FP64 oracle's reduced mode: viscous Gubser flow, 100 steps, the
+    whole box.  The rebuilt components come from the FP64 flow, so the error
+    stays far below the mixed ten-component state's (measured 2.0e-7 in e,
+    8.5e-8 in u; that state is held to 1e-4)."""
+    w = I.workload_gubser_viscous(n=32, n_steps=100)
+    errs, gpu, sim, f, r, obs = run_reduced(kt, w, 100, "gubser32 reduced mixed", mixed=True)
+    assert errs["e"] <= 1e-5 and errs["u"] <= 1e-5, errs
+
+
+def reduced_events(mixed=False):
+    out = []
+    for (nx, ny, ne, hot, seed) in ((40, 36, 12, 30, 11), (71, 17, 5, 40, 13)):
+        w = I.workload_hotspot(nx=nx, ny=ny, neta=ne, dx=0.5, deta=0.6, n_hot=hot, seed=seed)
+        out.append((w.grid, dict(w.config, reduced=True, mixed=mixed), w.prims))
+    return out, w.eos
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_reduced_batch_equals_separate_contexts(kt, mixed):
+    evs, eos = reduced_events(mixed)
+    batch = kt.Batch(evs, eos)
+    singles = [kt.Solver(g, cfg, eos, pr) for g, cfg, pr in evs]
+    for n in (1, 4):
+        batch.step(n)
+        for s in singles:
+            s.step(n)
+        for k, s in enumerate(singles):
+            a, b = batch.fields(k), s.fields()
+            assert all(np.array_equal(a[x].cpu().numpy(), b[x].cpu().numpy()) for x in a), (mixed, n, k)
+            ob, os_ = batch.observables(k), s.observables()
+            assert ob["fp_passes"] == os_["fp_passes"] > 0
+
+
+def test_reduced_state_rejects_other_newton_starts(kt):
+    w = I.workload_gubser_viscous(n=8, n_steps=0)
+    s = kt.Solver(w.grid, dict(w.config, reduced=True), w.eos, w.prims)
+    for start in (kt.KT_START_WARM, kt.KT_START_LEARNED):
+        with pytest.raises(kt.KtError):
+            s.set_inv_start(start)
