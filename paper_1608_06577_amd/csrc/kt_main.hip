@@ -921,7 +921,10 @@ __device__ __forceinline__ void recover_body(const Phys &P, const Eos &E, double
 // components are solved together by the fixed point
 //   u_{k+1} = inversion of (T^{tau mu}, pi^{tau mu}(five, u_k), Pi),
 // started from us (the cell's flow before the stage, u^tau renormalised at
-// tau; null: at rest), each inversion from the conformal closed form, stopped
+// tau; null: at rest), the first inversion's Newton iteration from the
+// conformal closed form and each later one from the previous pass's e (the
+// root moves little between passes; every pass converges to the same
+// tolerance whatever its start, so only the iteration counts change), stopped
 // when no component of u moves by more than FP_TOL u^tau (the eta component
 // times sqrt(g33)), on the floor state, without shear (one pass), or after
 // FP_MAX passes (counted as not converged).  The dependent components of the
@@ -960,7 +963,7 @@ __device__ __forceinline__ void recover_reduced_body(const Phys &P, const Eos &E
             double un[4];
             int its = 0;
             fl = recover<CART>(P, E, tau, qc[TT], qc[TX], qc[TY], qc[TE], qc[PTT], qc[PTX], qc[PTY],
-                               qc[PTE], Pi, -1.0, e, p0, un, its);
+                               qc[PTE], Pi, passes > 0 ? e : -1.0, e, p0, un, its);
             it += its;
             ++passes;
             double dmax = 0.0;
