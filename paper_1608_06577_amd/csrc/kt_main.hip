@@ -258,7 +258,9 @@ __device__ __forceinline__ R face_H(R qm, R qp, R cm, R cp)
 // fidx_x / fidx_y / fidx_e.
 constexpr int FACE_BLOCK = 256;   // threads per block of the face kernels
 // The face kernels are latency-bound (dependent EOS table reads inside each
-// Newton solve): they are held to 64 VGPRs, i.e. 8 waves per SIMD.
+// Newton solve): their register budget is that of 6 waves per SIMD; they
+// need 68-70 VGPRs, which gives 7 (at 64 VGPRs for 8 waves the batched
+// kernel spilled and ran 1.5% slower).
 
 struct FaceLaunch {
     unsigned first_block[3];    // first block of each segment
@@ -383,7 +385,7 @@ __device__ __forceinline__ void face_speeds_body(const Phys &P, const Eos &E, co
 }
 
 template <bool CART, bool T1, typename S>
-__global__ __launch_bounds__(FACE_BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void face_speeds_kernel(Phys P, Eos E, FaceGeo G, FaceLaunch L,
+__global__ __launch_bounds__(FACE_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void face_speeds_kernel(Phys P, Eos E, FaceGeo G, FaceLaunch L,
                                                           double tau, const double *qT, const S *qP,
                                                           S *vf, unsigned long long *slots)
 {
@@ -1123,7 +1125,7 @@ __global__ __launch_bounds__(256) void recover_batch(const BRec<S> *__restrict__
 }
 
 template <bool CART, bool T1, typename S>
-__global__ __launch_bounds__(FACE_BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void faces_batch(const BFace<S> *__restrict__ tab,
+__global__ __launch_bounds__(FACE_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void faces_batch(const BFace<S> *__restrict__ tab,
                                                    const unsigned short *__restrict__ map,
                                                    const unsigned *__restrict__ first,
                                                    const double *__restrict__ tau_dev)
