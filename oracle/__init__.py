@@ -93,7 +93,7 @@ def lib():
         L.ora_pi_dependent.argtypes = [C.c_double, C.c_int32, C.c_int64, dp, dp]
         L.ora_recover_reduced.argtypes = [P, E, C.c_double, C.c_int64, dp, dp, dp, ip, ip, ip]
         L.ora_init_reduced.argtypes = [P, E, C.c_double, dp, dp, dp, dp]
-        L.ora_step_reduced.argtypes = [P, E, dp, dp, dp, dp, dp, C.c_int32, C.POINTER(_Stats),
+        L.ora_step_reduced.argtypes = [P, E, dp, dp, dp, dp, dp, dp, C.c_int32, C.POINTER(_Stats),
                                        C.POINTER(C.c_int64)]
         L.ora_step_reduced.restype = C.c_int
         _lib = L
@@ -423,6 +423,7 @@ class ReducedSimulation:
         self.u3 = np.empty((n, 3))
         self.up3 = np.empty((n, 3))
         self.step_count = 0
+        self.tau_prev = float(tau0)           # time of u_prev's level (u^{-1} = u^0 before the first step)
         self.stats = _Stats()
         self.fp = np.zeros(2, np.int64)       # fixed-point passes, cells not converged
         self._P = phys.c()
@@ -436,13 +437,14 @@ class ReducedSimulation:
         return cls(phys, eos, prims.tau0, q)
 
     def step(self, n: int = 1):
-        tau = C.c_double(self.tau)
+        tau, tau_prev = C.c_double(self.tau), C.c_double(self.tau_prev)
         rc = lib().ora_step_reduced(C.byref(self._P), C.byref(self.eos_ref.c), C.byref(tau),
-                                    _dp(self.r), _dp(self.e), _dp(self.u3), _dp(self.up3), int(n),
+                                    C.byref(tau_prev), _dp(self.r), _dp(self.e), _dp(self.u3), _dp(self.up3), int(n),
                                     C.byref(self.stats), self.fp.ctypes.data_as(C.POINTER(C.c_int64)))
         if rc != 0:
             raise MemoryError("oracle step could not allocate its work arrays")
         self.tau = tau.value
+        self.tau_prev = tau_prev.value
         self.step_count += n
         return self
 
@@ -461,6 +463,6 @@ class ReducedSimulation:
     def fields(self):
         s = self.shape()
         q, u = self.expanded()
-        _, up = self.expanded(self.tau - self.phys.dtau, self.up3)
+        _, up = self.expanded(self.tau_prev, self.up3)
         return dict(e=self.e.reshape(s).copy(), u=u.T.reshape((4,) + s).copy(),
                     up=up.T.reshape((4,) + s).copy(), q=q.T.reshape((NQ,) + s).copy())

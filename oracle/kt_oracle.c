@@ -1201,12 +1201,14 @@ void ora_init_reduced(const ora_params *P, const ora_eos *eos, double tau0, doub
 }
 
 /* n_steps Heun steps of the reduced state in place, the step of ora_step on the
- * expanded state (the previous flow u_prev is normalised at tau - dtau, the time
- * of its level; the first step's u_prev is u^0).  The recovery of q* starts its
+ * expanded state.  The previous flow u_prev is normalised at *tau_prev_io, the
+ * time of its level: tau - dtau once a step has been taken, tau0 before the
+ * first step, whose u_prev is u^0 itself (Sec. 4.3 sets u^{-1} = u^0, the same
+ * four-vector).  The recovery of q* starts its
  * fixed point from u^n, that of q^{n+1} from u*.  fp_stats (nullable): passes
  * of the recovery's fixed point and cells where it did not converge. */
-int ora_step_reduced(const ora_params *P, const ora_eos *eos, double *tau_io, double *r,
-                     double *e, double *u3, double *up3, int32_t n_steps, ora_stats *st,
+int ora_step_reduced(const ora_params *P, const ora_eos *eos, double *tau_io, double *tau_prev_io,
+                     double *r, double *e, double *u3, double *up3, int32_t n_steps, ora_stats *st,
                      int64_t *fp_stats)
 {
     const int64_t n = (int64_t)P->nx * P->ny * P->neta;
@@ -1222,13 +1224,13 @@ int ora_step_reduced(const ora_params *P, const ora_eos *eos, double *tau_io, do
         return 1;
     }
     ora_fp_stats fs = {0, 0};
-    double tau = *tau_io;
+    double tau = *tau_io, tau_prev = *tau_prev_io;
     for (int s = 0; s < n_steps; ++s) {
         const double tau1 = tau + P->dtau;
         /* stage 1 at tau on (q^n, e^n, u^n, u^{n-1}) */
         ora_expand(P, tau, n, r, u3, qf, uf);
 #pragma omp parallel for schedule(static)
-        for (int64_t c = 0; c < n; ++c) u_full(tau - P->dtau, P->cartesian, up3 + 3 * c, upf + 4 * c);
+        for (int64_t c = 0; c < n; ++c) u_full(tau_prev, P->cartesian, up3 + 3 * c, upf + 4 * c);
         ctx_t C1 = {P, eos, tau, qf, e, uf, upf, st};
         rhs_all(&C1, rhs);
         for (int64_t c = 0; c < n; ++c)
@@ -1247,9 +1249,11 @@ int ora_step_reduced(const ora_params *P, const ora_eos *eos, double *tau_io, do
             }
         memcpy(up3, u3, sizeof(double) * 3 * n);
         recover_all_reduced(P, eos, tau1, r, us3, e, u3, st, &fs, 1);
+        tau_prev = tau;
         tau = tau1;
     }
     *tau_io = tau;
+    *tau_prev_io = tau_prev;
     if (fp_stats) {
         fp_stats[0] += fs.passes;
         fp_stats[1] += fs.not_converged;

@@ -541,7 +541,7 @@ __device__ __forceinline__ void sources_body(const Phys &P, const Eos &E, double
         for (int c = 0; c < PTT; ++c) qn4[c] = ld(qnT, (idx_t)c * SS + s);
 #pragma unroll
         for (int c = 0; c < NQ - PTT; ++c)
-            qn11[c] = P.reduced && pi_is_dependent(c + PTT) ? S(0) : ld(qnP, (idx_t)c * SS + s);
+            qn11[c] = P.reduced && P.shear && pi_is_dependent(c + PTT) ? S(0) : ld(qnP, (idx_t)c * SS + s);
     }
     // T^{tau mu}: FP64 value, source and accumulation
     auto emitT = [&](int c, double qc, double Jc) {
@@ -549,10 +549,11 @@ __device__ __forceinline__ void sources_body(const Phys &P, const Eos &E, double
         const double t = qc + dt * Jc;
         st(outT, o, STAGE2 ? qn4[c] + t : t);
     };
-    // (a reduced state evolves five of the ten pi components; the recovery
-    // rebuilds the others)
+    // (a viscous reduced state evolves five of the ten pi components; the
+    // recovery rebuilds the others.  Without shear all ten stay zero and are
+    // written as in the ten-component state.)
     auto emitP = [&](int c, R qc, R Jc) {
-        if (P.reduced && pi_is_dependent(c)) return;
+        if (P.reduced && P.shear && pi_is_dependent(c)) return;
         const idx_t o = (idx_t)(c - PTT) * SS + s;
         const R t = qc + R(dt) * Jc;
         st(outP, o, STAGE2 ? R(qn11[c - PTT]) + t : t);

@@ -65,6 +65,42 @@ def test_reduced_initial_recovery(kt):
     assert obs["fp_passes"] > obs["n_recover_cells"] and obs["fp_not_converged"] == 0
 
 
+@pytest.mark.parametrize("case", ["milne_viscous_bulk", "milne_ideal", "cartesian_viscous", "periodic_all"])
+def test_reduced_one_and_five_steps(kt, case):
+    """Ragged grid (several flux and sources tiles plus tails), smooth random
+    state with shear and bulk, in Milne and Cartesian coordinates, ideal, and
+    periodic in every axis: 1 and 5 steps of the reduced state."""
+    g = I.Grid(71, 37, 9, 0.15, 0.2, 0.12)
+    cart = case == "cartesian_viscous"
+    if case == "milne_ideal":
+        cfg = I.default_config(eta_s=0.0, periodic=(False, False, True))
+        eos = I.eos_conformal()
+    elif case == "periodic_all":
+        cfg = I.default_config(eta_s=0.2, zeta_coef=0.1, periodic=(True, True, True), theta=1.8)
+        eos = I.eos_c1_table()
+    else:
+        cfg = I.default_config(eta_s=0.2, zeta_coef=0.1, cartesian=cart, periodic=(False, False, True),
+                               theta=1.4)
+        eos = I.eos_c1_table()
+    prims = I.random_smooth_fields(g, 0.7, seed=9, cartesian=cart, e_mean=6.0,
+                                   pi_rel=0.0 if case == "milne_ideal" else 0.05,
+                                   Pi_rel=0.0 if case == "milne_ideal" else 0.02)
+    w = I.Workload(case, g, 0.7, 5, cfg, eos, prims)
+    for n in (1, 5):
+        errs, *_ = run_reduced(kt, w, n, "reduced " + case)
+        assert max(errs.values()) < 1e-12, errs
+
+
+def test_reduced_tiny_grids(kt):
+    for (nx, ny, ne) in ((1, 1, 1), (1, 5, 3), (7, 1, 1), (3, 2, 1)):
+        g = I.Grid(nx, ny, ne, 0.2, 0.2, 0.2)
+        cfg = I.default_config(eta_s=0.2, zeta_coef=0.1)
+        prims = I.random_smooth_fields(g, 1.0, seed=nx * 7 + ny, e_mean=4.0)
+        w = I.Workload("tiny", g, 1.0, 3, cfg, I.eos_c1_table(), prims)
+        errs, *_ = run_reduced(kt, w, 3, "reduced tiny %dx%dx%d" % (nx, ny, ne))
+        assert max(errs.values()) < 1e-12, (nx, ny, ne, errs)
+
+
 def test_reduced_gubser_viscous_100_steps(kt):
     """Conformal viscous Gubser flow on the 32^3 grid (theta = 1.8, eta/s = 0.2,
     periodic in eta): 100 Heun steps of the reduced state."""

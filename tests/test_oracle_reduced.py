@@ -183,3 +183,21 @@ def test_reduced_viscous_gubser_semi_analytic(oracle_lib):
     assert a[0] < 0.015 and b[0] < 0.65 * a[0]
     assert a[0] < 1.2 * full[0]
     assert b[1] < 0.01 and a[2] < 0.015 and b[2] < 0.015
+
+
+def test_reduced_first_step_previous_flow_is_the_initial_flow(oracle_lib):
+    """Sec. 4.3 sets u^{-1} = u^0: before the first step the stored previous flow
+    is the initial four-vector itself (with u^eta != 0 its u^tau depends on the
+    time it is normalised at, which is tau0), and after a step it is the flow
+    the step started from."""
+    g = I.Grid(6, 5, 4, 0.3, 0.3, 0.2)
+    cfg = I.default_config(eta_s=0.2, zeta_coef=0.1, periodic=(False, False, True))
+    prims = I.random_smooth_fields(g, 0.7, seed=4, e_mean=6.0, pi_rel=0.05, Pi_rel=0.02)
+    assert np.abs(prims.u[3]).max() > 0.05
+    sim = oracle.ReducedSimulation.from_primitives(oracle.Physics.from_config(g, cfg), I.eos_c1_table(), prims)
+    f0 = sim.fields()
+    assert np.array_equal(f0["up"], f0["u"])
+    sim.step(1)
+    f1 = sim.fields()
+    assert np.array_equal(f1["up"], f0["u"])
+    assert sim.tau_prev == 0.7 and not np.array_equal(f1["u"], f0["u"])
