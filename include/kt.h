@@ -353,7 +353,7 @@ kt_status kt_profile_read(kt_ctx *c, kt_profile *out);
 
 /* ---------------------------------------------------------------------
  * Batches of events.  n_events events (each its own grid and initial state;
- * the same coordinates, precision, tau0 and dtau) are advanced together:
+ * the same coordinates, precision, reduced flag, tau0 and dtau) are advanced together:
  * every kernel of a Heun step is one launch over the tiles of all events,
  * and one step is captured once as a hipGraph and replayed.  Results equal
  * those of separate contexts bit for bit.  Newton starts from the
