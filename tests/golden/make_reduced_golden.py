@@ -1,0 +1,98 @@
+"""Write oracle reference samples of the reduced state (Sec. 2.4: five evolved pi
+components and the flow; the oracle's reduced mode) on the 128^3 non-conformal
+viscous hot-spot event.
+
+Runs the FP64 CPU oracle (and nothing else) from the seeded initial state for
+100 Heun steps and stores e, u^mu and the expanded 15 components at the seeded
+sample of cells of the ten-component samples after 50 and 100 steps, with the
+fixed-point pass counts.  A second run from initial energy densities moved by
+one FP64 ulp (e -> nextafter(e, inf)) gives the spread of the oracle against
+itself over all cells, stored with the samples.
+
+The file records the SHA-256 of the oracle source the reduced step depends on
+(``oracle_sha``: the step above the diagnostics marker and the reduced-storage
+section); the GPU test refuses samples made with another oracle.
+Usage (about twenty minutes on 8 cores):
+
+    python tests/golden/make_reduced_golden.py [out.npz]
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_1608_06577_amd import inputs as I  # noqa: E402
+from tests.golden.make_hotspot_golden import ORACLE_SOURCE, STEP_MARKER, sample_cells  # noqa: E402
+
+SNAP_STEPS = (50, 100)
+REDUCED_MARKER = b"/* Reduced storage (Sec. 2.4"
+
+
+def oracle_sha() -> np.ndarray:
+    """SHA-256 of the oracle source above the diagnostics marker followed by its
+    reduced-storage section (from that section's marker to the end)."""
+    src = open(ORACLE_SOURCE, "rb").read()
+    cut, red = src.find(STEP_MARKER), src.find(REDUCED_MARKER)
+    assert 0 < cut < red, "oracle section markers missing"
+    return np.frombuffer(hashlib.sha256(src[:cut] + src[red:]).digest(), np.uint8)
+
+
+def spread(ref, other, tau):
+    """Relative differences of e and u between two runs over all cells (the
+    measures of the parity tests)."""
+    e, eo = ref["e"].ravel(), other["e"].ravel()
+    u, uo = ref["u"].reshape(4, -1), other["u"].reshape(4, -1)
+    emax = e.max()
+    de = np.abs(eo - e) / np.maximum(e, 1e-6 * emax)
+    du = np.max(np.abs(uo - u) * np.array([1, 1, 1, tau])[:, None] / u[:1], axis=0)
+    d = np.maximum(de, du)
+    dense = e > 1e-3 * emax
+    return dict(max=float(d.max()), dense_max=float(d[dense].max()), median=float(np.median(d)),
+                frac_above_1e9=float(np.mean(d > 1e-9)), dense_cells=int(dense.sum()))
+
+
+def main(out):
+    w = I.workload_hotspot()
+    cfg = dict(w.config, reduced=True)
+    phys = oracle.Physics.from_config(w.grid, cfg)
+    sim = oracle.ReducedSimulation.from_primitives(phys, w.eos, w.prims)
+    p = I.Primitives(w.prims.grid, w.prims.tau0, np.nextafter(w.prims.e, np.inf), w.prims.u, w.prims.pi,
+                     w.prims.Pi)
+    pert = oracle.ReducedSimulation.from_primitives(phys, w.eos, p)
+    idx = sample_cells(w.prims.e)
+    data = dict(idx=idx, input_sha=np.frombuffer(
+        hashlib.sha256(np.ascontiguousarray(w.prims.e).tobytes()).digest(), np.uint8),
+        oracle_sha=oracle_sha())
+    spreads = {}
+    t0 = time.time()
+    done = 0
+    for s in SNAP_STEPS:
+        sim.step(s - done)
+        pert.step(s - done)
+        done = s
+        f, fp = sim.fields(), pert.fields()
+        data["tau_%d" % s] = np.float64(sim.tau)
+        data["emax_%d" % s] = np.float64(f["e"].max())
+        data["e_%d" % s] = f["e"].ravel()[idx].copy()
+        data["u_%d" % s] = f["u"].reshape(4, -1)[:, idx].T.copy()
+        data["q_%d" % s] = f["q"].reshape(15, -1)[:, idx].T.copy()
+        data["fp_%d" % s] = sim.fp.copy()
+        data["n_recover_%d" % s] = np.int64(sim.stats.n_recover)
+        spreads[s] = {"ulp": spread(f, fp, sim.tau)}
+        print("step %d tau %.3f emax %.6g  %.0fs  passes/recovery %.3f not converged %d  spread %s" % (
+            s, sim.tau, f["e"].max(), time.time() - t0, sim.fp[0] / max(1, sim.stats.n_recover), sim.fp[1],
+            json.dumps(spreads[s])), flush=True)
+    data["spread_json"] = np.frombuffer(json.dumps(spreads).encode(), np.uint8)
+    np.savez_compressed(out, **data)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else os.path.join(os.path.dirname(__file__),
+                                                            "hotspot_128_reduced_fp64.npz"))

@@ -186,3 +186,54 @@ def test_reduced_state_rejects_other_newton_starts(kt):
     for start in (kt.KT_START_WARM, kt.KT_START_LEARNED):
         with pytest.raises(kt.KtError):
             s.set_inv_start(start)
+
+
+def test_reduced_hotspot_128_against_oracle_samples(kt):
+    """The full 128^3 hot-spot event with the reduced state: GPU fields after
+    50 and 100 steps against the oracle's reduced mode at the 2048 sampled cells
+    of tests/golden/hotspot_128_reduced_fp64.npz (e, u and all fifteen
+    components, the rebuilt ones included), within the FP64 bar of 1e-9, or ten
+    times the oracle's own spread under a one-ulp change of the initial e where
+    that is larger (the file records it)."""
+    import hashlib
+    import importlib.util
+    import json
+    import os
+    from tests.test_gpu_parity import ROOT, sample_errors
+    path = os.path.join(ROOT, "tests", "golden", "hotspot_128_reduced_fp64.npz")
+    if not os.path.exists(path):
+        pytest.skip("oracle samples not generated")
+    gold = np.load(path)
+    spec = importlib.util.spec_from_file_location(
+        "make_reduced_golden", os.path.join(ROOT, "tests", "golden", "make_reduced_golden.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    assert np.array_equal(gold["oracle_sha"], mk.oracle_sha()), \
+        "the oracle changed since the samples were written: run tests/golden/make_reduced_golden.py"
+    w = I.workload_hotspot()
+    sha = hashlib.sha256(np.ascontiguousarray(w.prims.e).tobytes()).digest()
+    assert np.array_equal(np.frombuffer(sha, np.uint8), gold["input_sha"])
+    spread = json.loads(bytes(gold["spread_json"]).decode())
+    gpu = kt.Solver(w.grid, dict(w.config, reduced=True), w.eos, w.prims)
+    obs0 = gpu.observables()
+    idx = gold["idx"]
+    done = 0
+    for s in (50, 100):
+        gpu.step(s - done)
+        done = s
+        f = gpu.fields()
+        d, hot = sample_errors(f, gold, s, idx)
+        q = f["q"].reshape(15, -1)[:, idx].cpu().numpy().T
+        qr = gold["q_%d" % s]
+        dq = np.max(np.abs(q - qr) / np.maximum(np.abs(qr).max(axis=0), 1e-300))
+        obs = gpu.observables()
+        passes = obs["fp_passes"] - obs0["fp_passes"]
+        ulp = spread[str(s)]["ulp"]
+        print("reduced hotspot128 step %d: max %.2e | dense (%d cells) %.2e | median %.1e | q %.2e | "
+              "passes %d (oracle %d) | one-ulp spread of the oracle: max %.2e dense %.2e" % (
+                  s, d.max(), hot.sum(), d[hot].max(), np.median(d), dq, passes, gold["fp_%d" % s][0],
+                  ulp["max"], ulp["dense_max"]), flush=True)
+        assert d.max() <= max(1e-9, 10 * ulp["max"]), (s, d.max())
+        assert d[hot].max() <= max(1e-9, 10 * ulp["dense_max"]), (s, d[hot].max())
+        assert dq <= max(1e-9, 10 * ulp["max"]), (s, dq)
+        assert abs(passes - gold["fp_%d" % s][0]) <= 1e-3 * gold["fp_%d" % s][0]
