@@ -2548,8 +2548,8 @@ struct kt_batch {
     size_t o_s1[2], o_s2[2], o_r1[2], o_r2[2], o_f1, o_f2;  // table offsets ([step parity])
     size_t o_fsrc, o_fflux, o_frec, o_fface;                // first-block arrays
     size_t o_msrc, o_mflux, o_mrec, o_mface;                // block -> event maps
-    hipGraph_t graph[2];         // one captured step per step parity
-    hipGraphExec_t exec[2];
+    hipGraph_t graph[3];         // one captured step per step parity; [2]: two steps from an even one
+    hipGraphExec_t exec[3];
     bool have_graph;
     double tau;
     long long step;
@@ -2823,7 +2823,7 @@ static hipError_t batch_launches(kt_batch *b, hipStream_t st, int par)
 static void batch_drop_graph(kt_batch *b)
 {
     if (b->have_graph) {
-        for (int par = 0; par < 2; ++par) {
+        for (int par = 0; par < 3; ++par) {
             (void)hipGraphExecDestroy(b->exec[par]);
             (void)hipGraphDestroy(b->graph[par]);
         }
@@ -2945,12 +2945,15 @@ kt_status kt_batch_step(kt_batch *b, int32_t n_steps)
     if (n_steps == 0) return KT_OK;
     hipError_t e = hipSuccess;
     if (!b->have_graph) {
-        // the u buffers swap roles every step, so there is one graph per step parity
+        // the u buffers swap roles every step, so there is one graph per step
+        // parity, and a third of two steps (even, then odd) that halves the
+        // graph launches of longer runs
         int made = 0;
-        for (int par = 0; par < 2 && e == hipSuccess; ++par) {
+        for (int par = 0; par < 3 && e == hipSuccess; ++par) {
             e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                hipError_t le = batch_launches(b, b->cap, par);
+                hipError_t le = batch_launches(b, b->cap, par & 1);
+                if (par == 2 && le == hipSuccess) le = batch_launches(b, b->cap, 1);
                 e = hipStreamEndCapture(b->cap, &b->graph[par]);
                 if (le != hipSuccess && e == hipSuccess) {
                     (void)hipGraphDestroy(b->graph[par]);
@@ -2973,7 +2976,12 @@ kt_status kt_batch_step(kt_batch *b, int32_t n_steps)
     }
     e = hipEventRecord(b->fork_ev, b->user);
     if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->fork_ev, 0);
-    for (int s = 0; s < n_steps && e == hipSuccess; ++s) e = hipGraphLaunch(b->exec[(b->step + s) & 1], b->cap);
+    for (int s = 0; s < n_steps && e == hipSuccess;) {
+        const int par = (int)((b->step + s) & 1);
+        const bool two = par == 0 && n_steps - s >= 2;
+        e = hipGraphLaunch(b->exec[two ? 2 : par], b->cap);
+        s += two ? 2 : 1;
+    }
     if (e == hipSuccess) e = hipEventRecord(b->join_ev, b->cap);
     if (e == hipSuccess) e = hipStreamWaitEvent(b->user, b->join_ev, 0);
     if (e != hipSuccess) return bfail(b, KT_E_HIP, "batch step: %s", hipGetErrorString(e));
