@@ -1016,8 +1016,12 @@ __global__ __launch_bounds__(256) void recover_reduced_kernel(Phys P, Eos E, dou
                                   (idx_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// (the register budget of 4 waves per SIMD: without it the network's
+// instantiation held its matrix-core accumulators in 36 AGPRs beside 112
+// VGPRs, 3 waves; within 128 it needs no spill and the learned step is 0.07 ms
+// faster; the other instantiations use 118-120 either way)
 template <bool CART, bool LEARNED, typename S>
-__global__ __launch_bounds__(256) void recover_kernel(Phys P, Eos E, double tau, double *qT, S *qP,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void recover_kernel(Phys P, Eos E, double tau, double *qT, S *qP,
                                                       S *e_io, S *p_out, double *u_out,
                                                       int do_regulate, int warm,
                                                       const ktm::MlpPacked *__restrict__ K,
