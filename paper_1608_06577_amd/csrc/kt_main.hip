@@ -1006,8 +1006,10 @@ __device__ __forceinline__ void recover_reduced_body(const Phys &P, const Eos &E
     slot_add(slots, wave, C_FP_NOCONV, noconv);
 }
 
+// (4 waves per SIMD: 128 VGPRs and a few spilled values instead of 136-148
+// VGPRs and 3 waves; measured 1% faster on the reduced step)
 template <bool CART, typename S>
-__global__ __launch_bounds__(256) void recover_reduced_kernel(Phys P, Eos E, double tau, double *qT, S *qP,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void recover_reduced_kernel(Phys P, Eos E, double tau, double *qT, S *qP,
                                                               S *e_out, S *p_out, double *u_out,
                                                               const double *us, int do_regulate,
                                                               unsigned long long *slots)
@@ -1111,7 +1113,7 @@ __global__ __launch_bounds__(256) void flux_batch(const BStage<S> *__restrict__ 
 }
 
 template <bool CART, typename S, bool RED>
-__global__ __launch_bounds__(256) void recover_batch(const BRec<S> *__restrict__ tab,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void recover_batch(const BRec<S> *__restrict__ tab,
                                                      const unsigned short *__restrict__ map,
                                                      const unsigned *__restrict__ first,
                                                      const double *__restrict__ tau_dev)
