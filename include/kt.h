@@ -221,6 +221,28 @@ kt_status kt_recover(kt_ctx *c, int64_t n, double tau, const double *const in[9]
                      double *e_out, double *const u_out[4], int32_t *iters_out,
                      int32_t *flags_out);
 
+/* Standalone coupled recovery of n reduced states at time tau (Sec. 2.4; the
+ * recovery of a kt_params.reduced step without its regulator and floor
+ * reset): in[0..9] = device arrays T^{tau tau}, T^{tau x}, T^{tau y},
+ * T^{tau eta}, pi^{xx}, pi^{xy}, pi^{x eta}, pi^{yy}, pi^{y eta}, Pi (Pi may be
+ * null = 0).  pi^{tau mu} and pi^{eta eta} follow from u_mu pi^{mu nu} = 0 and
+ * pi^mu_mu = 0 with the flow, so (e, u) and they are solved together: a fixed
+ * point over u started at rest, each pass one inversion (the first from the
+ * conformal closed form, later ones from the previous pass's e), stopped when
+ * no component of u moves by more than 1e-14 u^tau (the eta component times
+ * sqrt(g33)), on the floor state, without shear (eta_over_s = 0: one pass), or
+ * after 100 passes.  Outputs e_out[n], u_out[4][n]; pi_out (nullable; else
+ * five non-null arrays) receives pi^{tau tau}, pi^{tau x}, pi^{tau y},
+ * pi^{tau eta}, pi^{eta eta} of the final flow; passes_out (nullable) the
+ * passes, negative when the limit ended them; flags_out (nullable) the last
+ * inversion's flags (bit 1 floor, 2 clamp, 4 bisection fallback).  Uses the
+ * context's EOS, guards and transport switches whatever its kt_params.reduced.
+ * KT_E_ARG for n < 0, null required arrays or tau <= 0 in Milne coordinates.
+ * Asynchronous. */
+kt_status kt_recover_reduced(kt_ctx *c, int64_t n, double tau, const double *const in[10],
+                             double *e_out, double *const u_out[4], double *const pi_out[5],
+                             int32_t *passes_out, int32_t *flags_out);
+
 /* ---------------------------------------------------------------------
  * Learned start of the cell inversion.  Newton's method (Sec. 3.2) needs a
  * starting e; the paper leaves it open.  A network 11 -> 64 -> 64 -> 4 with

@@ -936,6 +936,45 @@ __device__ __forceinline__ void recover_body(const Phys &P, const Eos &E, double
 constexpr double FP_TOL = 1e-14;
 constexpr int FP_MAX = 100;
 
+// The fixed point itself: qc holds T^{tau mu}, the five pi components and Pi
+// (its dependent slots are overwritten pass by pass), u the normalised start;
+// u receives the flow, e and p0 the last inversion's e and p(e), it the summed
+// Newton iterations, passes the passes taken, conv whether the tolerance (or
+// the floor, or the absence of shear) ended them.  Returns the last flags.
+template <bool CART>
+__device__ __forceinline__ int reduced_fixed_point(const Phys &P, const Eos &E, double tau, double qc[NQ],
+                                                   double u[4], double &e, double &p0, int &it, int &passes,
+                                                   bool &conv)
+{
+    const double g33 = CART ? 1.0 : tau * tau;
+    const double sg = sqrt(g33);
+    const double Pi = P.bulk ? qc[BPI] : 0.0;
+    int fl = 0;
+    it = 0;
+    passes = 0;
+    conv = false;
+    while (passes < FP_MAX) {
+        if (P.shear) pi_dependent_of<CART>(tau, u, qc);
+        double un[4];
+        int its = 0;
+        fl = recover<CART>(P, E, tau, qc[TT], qc[TX], qc[TY], qc[TE], qc[PTT], qc[PTX], qc[PTY],
+                           qc[PTE], Pi, passes > 0 ? e : -1.0, e, p0, un, its);
+        it += its;
+        ++passes;
+        double dmax = 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            dmax = fmax(dmax, fabs(un[m] - u[m]) * (m == 3 ? sg : 1.0) / un[0]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) u[m] = un[m];
+        if ((fl & F_FLOOR) || !P.shear || dmax <= FP_TOL) {
+            conv = true;
+            break;
+        }
+    }
+    return fl;
+}
+
 template <bool CART, typename S>
 __device__ __forceinline__ void recover_reduced_body(const Phys &P, const Eos &E, double tau, double *qT,
                                                      S *qP, S *e_out, S *p_out, double *u_out,
@@ -951,13 +990,15 @@ __device__ __forceinline__ void recover_reduced_body(const Phys &P, const Eos &E
         double qc[NQ];
 #pragma unroll
         for (int c = 0; c < NQ; ++c) qc[c] = pi_is_dependent(c) ? 0.0 : ldq(qT, qP, c, SS, s);
-        const double Pi = P.bulk ? qc[BPI] : 0.0;
         double u[4] = {1.0, 0.0, 0.0, 0.0};
         if (us) {
 #pragma unroll
             for (int m = 1; m < 4; ++m) u[m] = ld(us, (idx_t)m * SS + s);
             u[0] = sqrt(1.0 + u[1] * u[1] + u[2] * u[2] + g33 * u[3] * u[3]);
         }
+        // (the loop of reduced_fixed_point written out: calling it here costs this
+        // kernel 12-17 more spilled registers and 5% of the reduced step)
+        const double Pi = P.bulk ? qc[BPI] : 0.0;
         double e = 0.0, p0 = 0.0;
         bool conv = false;
         const double sg = sqrt(g33);
@@ -1240,6 +1281,56 @@ __global__ __launch_bounds__(256) void recover_standalone_kernel(Phys P, Eos E, 
 #pragma unroll
     for (int m = 0; m < 4; ++m) R.u[m][s] = u[m];
     if (R.iters) R.iters[s] = it;
+    if (R.flags) R.flags[s] = fl;
+}
+
+// kt_recover_reduced: the reduced state's coupled recovery of n separate states
+// (T^{tau mu}, the five pi components, Pi), started at rest, without regulator
+// or floor reset; the dependent components of the final flow are returned.
+struct RecRedIn {
+    const double *in[10];
+    double *e;
+    double *u[4];
+    double *pi[5];       // pi^{tau tau}, pi^{tau x}, pi^{tau y}, pi^{tau eta}, pi^{eta eta}; nullable
+    int *passes;         // negative when the pass limit ended the fixed point; nullable
+    int *flags;          // nullable
+};
+
+template <bool CART>
+__global__ __launch_bounds__(256) void recover_reduced_standalone_kernel(Phys P, Eos E, double tau, long long n,
+                                                                         RecRedIn R)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    double qc[NQ];
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) qc[c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) qc[c] = R.in[c][s];
+    qc[PXX] = R.in[4][s];
+    qc[PXY] = R.in[5][s];
+    qc[PXE] = R.in[6][s];
+    qc[PYY] = R.in[7][s];
+    qc[PYE] = R.in[8][s];
+    qc[BPI] = R.in[9] ? R.in[9][s] : 0.0;
+    double u[4] = {1.0, 0.0, 0.0, 0.0}, e = 0.0, p0 = 0.0;
+    int it = 0, passes = 0;
+    bool conv = false;
+    const int fl = reduced_fixed_point<CART>(P, E, tau, qc, u, e, p0, it, passes, conv);
+    R.e[s] = e;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) R.u[m][s] = u[m];
+    if (R.pi[0]) {
+        if (P.shear) {
+            pi_dependent_of<CART>(tau, u, qc);
+        } else {
+            qc[PTT] = qc[PTX] = qc[PTY] = qc[PTE] = qc[PEE] = 0.0;
+        }
+        const int dep[5] = {PTT, PTX, PTY, PTE, PEE};
+#pragma unroll
+        for (int k = 0; k < 5; ++k) R.pi[k][s] = qc[dep[k]];
+    }
+    if (R.passes) R.passes[s] = conv ? passes : -passes;
     if (R.flags) R.flags[s] = fl;
 }
 
@@ -2144,6 +2235,38 @@ kt_status kt_recover(kt_ctx *c, int64_t n, double tau, const double *const in[9]
     else
         e = learned ? launch(recover_standalone_kernel<false, true>, linear_grid(n), dim3(256), c->stream, c->P, c->E, tau, (long long)n, R, w)
                     : launch(recover_standalone_kernel<false, false>, linear_grid(n), dim3(256), c->stream, c->P, c->E, tau, (long long)n, R, w);
+    if (e != hipSuccess) return fail(c, KT_E_HIP, "recover kernel: %s", hipGetErrorString(e));
+    return KT_OK;
+}
+
+kt_status kt_recover_reduced(kt_ctx *c, int64_t n, double tau, const double *const in[10], double *e_out,
+                             double *const u_out[4], double *const pi_out[5], int32_t *passes_out,
+                             int32_t *flags_out)
+{
+    if (!c) return fail(nullptr, KT_E_ARG, "null context");
+    if (n < 0) return fail(c, KT_E_ARG, "n must be >= 0");
+    if (n == 0) return KT_OK;
+    if (!in || !e_out || !u_out) return fail(c, KT_E_ARG, "null input or output arrays");
+    for (int k = 0; k < 9; ++k)
+        if (!in[k]) return fail(c, KT_E_ARG, "input %d is null", k);
+    for (int m = 0; m < 4; ++m)
+        if (!u_out[m]) return fail(c, KT_E_ARG, "u_out[%d] is null", m);
+    if (pi_out)
+        for (int k = 0; k < 5; ++k)
+            if (!pi_out[k]) return fail(c, KT_E_ARG, "pi_out[%d] is null", k);
+    if (c->prm.coords == KT_MILNE && !(tau > 0)) return fail(c, KT_E_ARG, "tau must be > 0");
+    RecRedIn R;
+    for (int k = 0; k < 10; ++k) R.in[k] = in[k];
+    R.e = e_out;
+    for (int m = 0; m < 4; ++m) R.u[m] = u_out[m];
+    for (int k = 0; k < 5; ++k) R.pi[k] = pi_out ? pi_out[k] : nullptr;
+    R.passes = passes_out;
+    R.flags = flags_out;
+    const hipError_t e = c->prm.coords == KT_CARTESIAN
+        ? launch(recover_reduced_standalone_kernel<true>, linear_grid(n), dim3(256), c->stream, c->P, c->E, tau,
+                 (long long)n, R)
+        : launch(recover_reduced_standalone_kernel<false>, linear_grid(n), dim3(256), c->stream, c->P, c->E, tau,
+                 (long long)n, R);
     if (e != hipSuccess) return fail(c, KT_E_HIP, "recover kernel: %s", hipGetErrorString(e));
     return KT_OK;
 }

@@ -84,7 +84,8 @@ class KtError(RuntimeError):
 _lib = None
 
 #: every function the C ABI exports (the names declared in include/kt.h)
-EXPORTS = ("kt_workspace_bytes", "kt_init", "kt_init_static", "kt_step", "kt_recover", "kt_observables",
+EXPORTS = ("kt_workspace_bytes", "kt_init", "kt_init_static", "kt_step", "kt_recover", "kt_recover_reduced",
+           "kt_observables",
            "kt_validity", "kt_run_to_freezeout",
            "kt_profile_enable", "kt_profile_read", "kt_destroy", "kt_last_error",
            "kt_status_string", "kt_set_inv_start", "kt_mlp_set", "kt_mlp_get", "kt_mlp_features",
@@ -117,6 +118,8 @@ def lib():
         L.kt_step.argtypes = [C.c_void_p, C.c_int32]
         L.kt_recover.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p * 9, C.c_void_p,
                                  C.c_void_p * 4, C.c_void_p, C.c_void_p]
+        L.kt_recover_reduced.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p * 10, C.c_void_p,
+                                         C.c_void_p * 4, C.POINTER(C.c_void_p * 5), C.c_void_p, C.c_void_p]
         L.kt_observables.argtypes = [C.c_void_p, C.POINTER(KtObs), C.POINTER(KtFields)]
         L.kt_validity.argtypes = [C.c_void_p] + [C.c_void_p] * 8
         L.kt_run_to_freezeout.argtypes = [C.c_void_p, C.c_double, C.c_int32, C.c_int32,
@@ -156,7 +159,7 @@ def lib():
             getattr(L, f).restype = C.c_int
         for f in ("kt_validity", "kt_run_to_freezeout"):
             getattr(L, f).restype = C.c_int
-        for f in ("kt_init", "kt_init_static", "kt_step", "kt_recover", "kt_observables", "kt_profile_enable",
+        for f in ("kt_init", "kt_init_static", "kt_step", "kt_recover", "kt_recover_reduced", "kt_observables", "kt_profile_enable",
                   "kt_profile_read", "kt_set_inv_start", "kt_mlp_set", "kt_mlp_get",
                   "kt_mlp_features", "kt_mlp_fwd", "kt_mlp_y0", "kt_mlp_loss", "kt_mlp_bwd", "kt_mlp_adam"):
             getattr(L, f).restype = C.c_int
@@ -350,6 +353,24 @@ class Solver:
         _check(lib().kt_recover(self.ctx, n, float(tau), arr, C.c_void_p(e.data_ptr()), uarr,
                                 _ptr(it), _ptr(fl)), self.ctx)
         return e, u, it, fl
+
+    def recover_reduced(self, ins, tau: float, with_pi=True):
+        """ins: 10 device tensors (T^{tau mu}, pi^{xx}, pi^{xy}, pi^{x eta},
+        pi^{yy}, pi^{y eta}, Pi or None) of equal length n.  Returns e, u (4, n),
+        the five rebuilt components (5, n) or None, passes, flags."""
+        torch = self.torch
+        n = ins[0].numel()
+        arr = (C.c_void_p * 10)(*[t.data_ptr() if t is not None else None for t in ins])
+        e = torch.empty(n, dtype=torch.float64, device=self.device)
+        u = torch.empty((4, n), dtype=torch.float64, device=self.device)
+        pi = torch.empty((5, n), dtype=torch.float64, device=self.device) if with_pi else None
+        ps = torch.empty(n, dtype=torch.int32, device=self.device)
+        fl = torch.empty(n, dtype=torch.int32, device=self.device)
+        uarr = (C.c_void_p * 4)(*[u[m].data_ptr() for m in range(4)])
+        parr = C.pointer((C.c_void_p * 5)(*[pi[k].data_ptr() for k in range(5)])) if with_pi else None
+        _check(lib().kt_recover_reduced(self.ctx, n, float(tau), arr, C.c_void_p(e.data_ptr()), uarr, parr,
+                                        _ptr(ps), _ptr(fl)), self.ctx)
+        return e, u, pi, ps, fl
 
     # ---------------------------------------------- learned inversion start
     def set_inv_start(self, start: int):
