@@ -3,16 +3,16 @@ components and the flow; the oracle's reduced mode) on the 128^3 non-conformal
 viscous hot-spot event.
 
 Runs the FP64 CPU oracle (and nothing else) from the seeded initial state for
-100 Heun steps and stores e, u^mu and the expanded 15 components at the seeded
-sample of cells of the ten-component samples after 50 and 100 steps, with the
-fixed-point pass counts.  A second run from initial energy densities moved by
+200 Heun steps and stores e, u^mu and the expanded 15 components at the seeded
+sample of cells of the ten-component samples after 50, 100 and 200 steps, with
+the fixed-point pass counts.  A second run from initial energy densities moved by
 one FP64 ulp (e -> nextafter(e, inf)) gives the spread of the oracle against
 itself over all cells, stored with the samples.
 
 The file records the SHA-256 of the oracle source the reduced step depends on
 (``oracle_sha``: the step above the diagnostics marker and the reduced-storage
 section); the GPU test refuses samples made with another oracle.
-Usage (about twenty minutes on 8 cores):
+Usage (about forty minutes on 8 cores):
 
     python tests/golden/make_reduced_golden.py [out.npz]
 """
@@ -31,7 +31,7 @@ import oracle  # noqa: E402
 from paper_1608_06577_amd import inputs as I  # noqa: E402
 from tests.golden.make_hotspot_golden import ORACLE_SOURCE, STEP_MARKER, sample_cells  # noqa: E402
 
-SNAP_STEPS = (50, 100)
+SNAP_STEPS = (50, 100, 200)
 REDUCED_MARKER = b"/* Reduced storage (Sec. 2.4"
 
 

@@ -48,7 +48,8 @@ def test_workspace_bytes_and_validation(L):
     n = L.kt_workspace_bytes(C.byref(p), C.byref(eos.c))
     assert n > 43 * 8 * g.ncells and n % 256 == 0
     bad = [("nx", 0), ("dx", 0.0), ("dtau", -1.0), ("theta", 2.5), ("theta", 0.9), ("tau0", 0.0),
-           ("e_floor", 0.0), ("m2_delta", 1.0), ("newton_max", 0), ("coords", 7), ("zeta_model", 2)]
+           ("e_floor", 0.0), ("m2_delta", 1.0), ("newton_max", 0), ("coords", 7), ("zeta_model", 2),
+           ("reduced", 2), ("reduced", -1)]
     for field, val in bad:
         q = kt.make_params(g, cfg, 0.5)
         setattr(q, field, val)
@@ -114,9 +115,9 @@ def test_init_rejects_bad_arguments_without_device_work(L):
 
 
 def test_learned_start_entry_points_reject_null_context(L):
-    """Argument marshalling of every learned-start entry point, nullable
-    arguments given as null: each rejects the null context before any device
-    work."""
+    """Argument marshalling of every learned-start entry point and of the
+    reduced recovery, nullable arguments given as null: each rejects the null
+    context before any device work."""
     vp = C.c_void_p
     arr9 = (vp * 9)()
     u4 = C.cast((vp * 4)(), vp)
@@ -132,6 +133,7 @@ def test_learned_start_entry_points_reject_null_context(L):
         L.kt_mlp_loss(None, 4, None, None, w4, None, None),
         L.kt_mlp_bwd(None, 4, None, None, None, None),
         L.kt_mlp_adam(None, None, 1e-3, 0.9, 0.999, 1e-8, 1),
+        L.kt_recover_reduced(None, 4, 1.0, (vp * 10)(), None, (vp * 4)(), None, None, None),
     ]
     assert all(c == kt.KT_E_ARG for c in calls), calls
     assert b"null context" in L.kt_last_error(None)
