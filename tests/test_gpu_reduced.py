@@ -213,6 +213,28 @@ def test_reduced_bjorken_lattice_eos_2plus1d(kt):
     assert np.max(np.abs(sim.tau ** 2 * q[13] + q[8] + q[11])) <= 1e-13 * np.abs(q[8]).max()
 
 
+def test_reduced_hotspot_lattice_eos_and_validity_maps(kt):
+    """The reduced state with the paper's lattice-QCD EOS and zeta/s(T) on the
+    hot-spot event (56x52x24, 30 steps) against the oracle's reduced mode, and
+    the validity maps of Sec. 7 (T, inverse Reynolds numbers) of its stored
+    state, the rebuilt components included, against the oracle's maps of the
+    expanded oracle state."""
+    w = I.workload_hotspot(nx=56, ny=52, neta=24, dx=0.4, deta=0.5, n_hot=60, seed=3,
+                           eos=I.eos_lattice_table())
+    w = I.Workload(w.name, w.grid, w.tau0, 30, dict(w.config, zeta_model=1, zeta_coef=1.0,
+                                                   zeta_tc=0.2 / I.HBARC), w.eos, w.prims)
+    errs, gpu, sim, f, r, obs = run_reduced(kt, w, 30, "hotspot56 lattice reduced")
+    assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9 and errs["q"] <= 1e-9, errs
+    m = {k: v.cpu().numpy() for k, v in gpu.validity().items()}
+    T, rpi, rPi = oracle.validity_maps(w.eos, sim.tau, False, r["e"], r["q"][4:14], r["q"][14])
+    dense = r["e"] > 1e-3 * r["e"].max()
+    assert np.max(np.abs(m["T"] - T) / T) <= 1e-9
+    for got, ref in ((m["rinv_pi"], rpi), (m["rinv_Pi"], rPi)):
+        assert np.max(np.abs(got - ref)[dense]) <= 1e-9 * np.max(np.abs(ref[dense]))
+        assert np.all(np.isfinite(got))
+    assert np.max(rpi[dense]) > 0 and np.max(rPi[dense]) > 0
+
+
 def test_reduced_mixed_precision_gubser(kt):
     """The reduced state with mixed-precision storage (pi, Pi, e, p in FP32)
     against the FP64 oracle's reduced mode: viscous Gubser flow, 100 steps, the
