@@ -125,11 +125,18 @@ typedef struct {
                                     * (kt_set_inv_start: KT_E_UNSUPPORTED for another start). */
 } kt_params;
 
-/* Initial data on the device.  Either q[0..14] (conserved form; all 15
- * non-null) or the primitives e, u[4], pi[10] and Pi (all non-null) are
- * given; from primitives the library forms T^{tau mu} with Eqs. Ttt, Tti of
- * Sec. 2.4.  u_prev (nullable) is the previous-step flow for resuming a run;
- * when null u^{-1} = u^0 (Sec. 4.3). */
+/* Initial data on the device, in one of three forms:
+ *   - q[0..14] (conserved form; all 15 non-null), e null: (e, u) are
+ *     recovered from q (Sec. 2.4);
+ *   - the primitives e, u[4], pi[10] and Pi (all non-null), q null: the library
+ *     forms T^{tau mu} with Eqs. Ttt, Tti of Sec. 2.4, then recovers (e, u);
+ *   - resume: q[0..14], e and u[4] (all non-null), as kt_observables exports
+ *     them (kt_fields), taken as they are, with p (nullable; p(e) of the EOS
+ *     when null) and u_prev: no recovery runs, so a run continued from an
+ *     exported state (q, e, p, u, u_prev at the exported tau as tau0) is bit
+ *     for bit the uninterrupted one.
+ * u_prev (nullable) is the previous-step flow; when null u^{-1} = u^0
+ * (Sec. 4.3).  pi and Pi are not read in the other two forms. */
 typedef struct {
     const double *q[15];
     const double *e;
@@ -137,14 +144,17 @@ typedef struct {
     const double *pi[10];
     const double *Pi;
     const double *u_prev[4];
+    const double *p;
 } kt_init_state;
 
-/* Device destinations for kt_observables; every entry may be null. */
+/* Device destinations for kt_observables; every entry may be null.  p is the
+ * equilibrium pressure p(e) the step uses. */
 typedef struct {
     double *e;
     double *u[4];
     double *q[15];
     double *u_prev[4];
+    double *p;
 } kt_fields;
 
 /* Diagnostics of the current state (all reductions are deterministic). */

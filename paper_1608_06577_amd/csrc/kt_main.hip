@@ -1202,6 +1202,17 @@ struct PrimPtrs {
     const double *Pi;
 };
 
+// p = p(e) of the equilibrium EOS for every cell (a resumed state given without p)
+template <typename S>
+__global__ __launch_bounds__(256) void pressure_kernel(Eos E, long long n, const S *e, S *p)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    double pe, cs2;
+    eos_pc(E, (double)e[s], pe, cs2);
+    p[s] = (S)pe;
+}
+
 template <typename S>
 __global__ __launch_bounds__(256) void tmunu_kernel(Phys P, Eos E, PrimPtrs in, double *qT, S *qP)
 {
@@ -2064,9 +2075,14 @@ kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0
     if (!s0 || !d_ws) return fail(nullptr, KT_E_ARG, "null initial state or workspace");
     if (((uintptr_t)d_ws) % 256) return fail(nullptr, KT_E_ARG, "workspace must be 256-byte aligned");
     const bool have_q = s0->q[0] != nullptr;
+    // q with e and u: a state exported by kt_observables, taken as it is (resume)
+    const bool resume = have_q && s0->e != nullptr;
     if (have_q) {
         for (int c = 0; c < 15; ++c)
             if (!s0->q[c]) return fail(nullptr, KT_E_ARG, "initial q[%d] is null", c);
+        if (resume)
+            for (int m = 0; m < 4; ++m)
+                if (!s0->u[m]) return fail(nullptr, KT_E_ARG, "resume: initial u[%d] is null", m);
     } else {
         if (!s0->e || !s0->Pi) return fail(nullptr, KT_E_ARG, "give either q or (e, u, pi, Pi)");
         for (int m = 0; m < 4; ++m)
@@ -2167,8 +2183,26 @@ kt_status kt_init(const kt_params *p, const kt_eos *eos, const kt_init_state *s0
                                c->qT[0], (double *)c->qP[0]);
     }
     if (he != hipSuccess) { kt_destroy(c); return fail(nullptr, KT_E_HIP, "initial state: %s", hipGetErrorString(he)); }
-    // (e^0, u^0) and u^{-1}
-    kt_status st = run_recover(c, c->tau, 0, c->ucur, 0, 0, -1);
+    // (e^0, u^0) and u^{-1}: recovered from q, or (resume) taken as given with
+    // p = p(e) when p is not given
+    kt_status st = KT_OK;
+    if (resume) {
+        he = store_from_double(c, c->e, s0->e, c->P.ncell);
+        for (int m = 0; m < 4 && he == hipSuccess; ++m)
+            he = hipMemcpyAsync(c->u[c->ucur] + m * S8, s0->u[m], bytes, hipMemcpyDeviceToDevice, stream);
+        if (he == hipSuccess)
+            he = s0->p ? store_from_double(c, c->p, s0->p, c->P.ncell)
+                       : (c->mixed ? launch(pressure_kernel<float>, linear_grid(c->P.ncell), dim3(256), stream, c->E,
+                                            (long long)c->P.ncell, (const float *)c->e, (float *)c->p)
+                                   : launch(pressure_kernel<double>, linear_grid(c->P.ncell), dim3(256), stream,
+                                            c->E, (long long)c->P.ncell, (const double *)c->e, (double *)c->p));
+        if (he != hipSuccess) {
+            kt_destroy(c);
+            return fail(nullptr, KT_E_HIP, "resumed state: %s", hipGetErrorString(he));
+        }
+    } else {
+        st = run_recover(c, c->tau, 0, c->ucur, 0, 0, -1);
+    }
     if (st == KT_OK) st = run_faces(c, c->tau, 0);
     if (st != KT_OK) { kt_status r = fail(nullptr, st, "%s", c->err); kt_destroy(c); return r; }
     for (int m = 0; m < 4 && he == hipSuccess; ++m)
@@ -2280,6 +2314,7 @@ kt_status kt_observables(kt_ctx *c, kt_obs *host_out, const kt_fields *dev_out)
     hipError_t e = hipSuccess;
     if (dev_out) {
         if (dev_out->e) e = store_to_double(c, dev_out->e, c->e, n);
+        if (e == hipSuccess && dev_out->p) e = store_to_double(c, dev_out->p, c->p, n);
         for (int m = 0; m < 4 && e == hipSuccess; ++m) {
             if (dev_out->u[m])
                 e = hipMemcpyAsync(dev_out->u[m], (const double *)c->u[c->ucur] + m * S, bytes, hipMemcpyDeviceToDevice,

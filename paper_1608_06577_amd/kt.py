@@ -44,12 +44,13 @@ class KtParams(C.Structure):
 
 class KtInitState(C.Structure):
     _fields_ = [("q", C.c_void_p * 15), ("e", C.c_void_p), ("u", C.c_void_p * 4),
-                ("pi", C.c_void_p * 10), ("Pi", C.c_void_p), ("u_prev", C.c_void_p * 4)]
+                ("pi", C.c_void_p * 10), ("Pi", C.c_void_p), ("u_prev", C.c_void_p * 4),
+                ("p", C.c_void_p)]
 
 
 class KtFields(C.Structure):
     _fields_ = [("e", C.c_void_p), ("u", C.c_void_p * 4), ("q", C.c_void_p * 15),
-                ("u_prev", C.c_void_p * 4)]
+                ("u_prev", C.c_void_p * 4), ("p", C.c_void_p)]
 
 
 class KtObs(C.Structure):
@@ -212,8 +213,9 @@ def workspace_bytes(grid, config, eos, tau0=1.0) -> int:
     return int(lib().kt_workspace_bytes(C.byref(p), C.byref(e.c)))
 
 
-def _init_state(torch, device, grid, prims, q, u_prev, keep) -> KtInitState:
-    """Device arrays of an initial state (kept alive in keep) as a KtInitState."""
+def _init_state(torch, device, grid, prims, q, u_prev, keep, resume=None) -> KtInitState:
+    """Device arrays of an initial state (kept alive in keep) as a KtInitState.
+    resume: dict with e, u and optionally p (with q: the state taken as given)."""
     st = KtInitState()
     shape = grid.shape
 
@@ -237,6 +239,14 @@ def _init_state(torch, device, grid, prims, q, u_prev, keep) -> KtInitState:
             st.u[m] = u[m].data_ptr()
         for c in range(10):
             st.pi[c] = pi[c].data_ptr()
+    if resume is not None:
+        assert q is not None, "resuming needs q"
+        ed, ud = dev(resume["e"]), dev(resume["u"])
+        st.e = ed.data_ptr()
+        for m in range(4):
+            st.u[m] = ud[m].data_ptr()
+        if resume.get("p") is not None:
+            st.p = dev(resume["p"]).data_ptr()
     if u_prev is not None:
         upd = dev(u_prev)
         for m in range(4):
@@ -249,11 +259,13 @@ class Solver:
 
     prims: ``inputs.Primitives`` (numpy, component-first) or a dict of device
     tensors ``e, u, pi, Pi``; alternatively ``q`` = (15, neta, ny, nx) device
-    tensor of conserved components.
+    tensor of conserved components, recovered, or with ``resume`` = dict(e, u,
+    p) of an exported state (``fields(("e", "p", "u", "q", "u_prev"))``) taken
+    as it is, so that the run continues bit for bit at ``tau0``.
     """
 
     def __init__(self, grid, config: dict, eos, prims=None, q=None, tau0=None, u_prev=None,
-                 device="cuda:0", static_workspace=False):
+                 device="cuda:0", static_workspace=False, resume=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -269,7 +281,7 @@ class Solver:
             _check(KT_E_ARG)
         with torch.cuda.device(self.device):
             keep = []
-            st = _init_state(torch, self.device, grid, prims, q, u_prev, keep)
+            st = _init_state(torch, self.device, grid, prims, q, u_prev, keep, resume)
             stream = torch.cuda.current_stream(self.device).cuda_stream
             ctx = C.c_void_p()
             if static_workspace:
@@ -325,6 +337,9 @@ class Solver:
             if "e" in which:
                 out["e"] = torch.empty(shape, dtype=torch.float64, device=self.device)
                 f.e = out["e"].data_ptr()
+            if "p" in which:
+                out["p"] = torch.empty(shape, dtype=torch.float64, device=self.device)
+                f.p = out["p"].data_ptr()
             if "u" in which:
                 out["u"] = torch.empty((4,) + shape, dtype=torch.float64, device=self.device)
                 for m in range(4):

@@ -93,6 +93,12 @@ def test_init_rejects_bad_arguments_without_device_work(L):
         st.q[c] = 4096
     assert L.kt_init(C.byref(p), C.byref(eos.c), C.byref(st), C.c_void_p(4096), 1024, None,
                      C.byref(ctx)) == kt.KT_E_ALLOC
+    # a resumed state (q and e) needs u
+    st.e = 4096
+    assert L.kt_init(C.byref(p), C.byref(eos.c), C.byref(st), C.c_void_p(4096), 1 << 30, None,
+                     C.byref(ctx)) == kt.KT_E_ARG
+    assert b"resume" in L.kt_last_error(None)
+    st.e = None
     # unknown precision
     q = kt.make_params(g, cfg, 0.5)
     q.precision = 7
