@@ -48,8 +48,8 @@ LAUNCHES_PER_STEP = {"flux": 2, "sources": 2, "recover": 2, "faces": 2}
 # stages' launches of a class), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by what the
 # counters read for a plain device copy (FETCH x 2, WRITE x 1; profiles/); valid for the kernel
 # sources and compiler flags whose hash is TRAFFIC_SOURCES (else the traffic is reported as null)
-TRAFFIC_SOURCES = "48dbd249ef628fae"
-TRAFFIC_BYTES = {"flux": 1311905504, "sources": 1189001952, "faces": 695140848, "recover": 584331096}
+TRAFFIC_SOURCES = "d0220b81f1badc35"
+TRAFFIC_BYTES = {"flux": 1308115968, "sources": 1188899312, "faces": 694927112, "recover": 584245904}
 KERNEL_NAMES = {"flux": "flux_kernel (KT flux divergence + stage update)",
                 "sources": "sources_kernel (App. B sources + stage update)",
                 "recover": "recover_kernel (Newton inversion + regulator)",
