@@ -265,7 +265,7 @@ class Solver:
     """
 
     def __init__(self, grid, config: dict, eos, prims=None, q=None, tau0=None, u_prev=None,
-                 device="cuda:0", static_workspace=False, resume=None):
+                 device="cuda:0", static_workspace=False, resume=None, workspace=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -290,7 +290,13 @@ class Solver:
                 _check(L.kt_init_static(C.byref(self.params), C.byref(self.eos_host.c), C.byref(st),
                                         C.c_void_p(stream), C.byref(ctx)))
             else:
-                self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+                # workspace: a caller's uint8 device tensor of at least kt_workspace_bytes
+                # (its contents are not assumed), else a new one
+                if workspace is not None:
+                    assert workspace.dtype == torch.uint8 and workspace.numel() >= nbytes
+                    self.ws = workspace
+                else:
+                    self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
                 if self.ws.data_ptr() % 256:
                     raise RuntimeError("workspace is not 256-byte aligned")
                 _check(L.kt_init(C.byref(self.params), C.byref(self.eos_host.c), C.byref(st),

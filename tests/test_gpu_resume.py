@@ -45,3 +45,44 @@ def test_resumed_run_is_the_uninterrupted_run(kt, mode):
     for k in fa:
         d = (fn[k] - fa[k]).abs().max().item() / max(fa[k].abs().max().item(), 1e-300)
         assert d < (1e-6 if mode == "mixed" else 1e-12), (mode, k, d)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed", "reduced"])
+def test_no_kernel_reads_unwritten_workspace(kt, mode):
+    """A workspace filled with 0xFF bytes (NaN in every floating-point view)
+    before kt_init gives the same fields and counters, bit for bit, as a
+    zero-filled one after several steps: no kernel reads a location that the
+    initialisation or an earlier kernel has not written."""
+    import ctypes as C
+    import torch
+    w = I.workload_hotspot(nx=40, ny=36, neta=12, dx=0.5, deta=0.6, n_hot=30, seed=13)
+    cfg = dict(w.config, mixed=mode == "mixed", reduced=mode == "reduced")
+    p = kt.make_params(w.grid, cfg, w.tau0)
+    nbytes = int(kt.lib().kt_workspace_bytes(C.byref(p), C.byref(kt.EosHost(w.eos).c)))
+    runs = []
+    for fill in (0x00, 0xFF):
+        ws = torch.full((nbytes,), fill, dtype=torch.uint8, device="cuda")
+        s = kt.Solver(w.grid, cfg, w.eos, w.prims, workspace=ws)
+        s.step(6)
+        runs.append((s.fields(("e", "p", "u", "q", "u_prev")), s.observables()))
+    (fa, oa), (fb, ob) = runs
+    for k in fa:
+        assert torch.equal(fa[k], fb[k]), (mode, k)
+    for k in ("newton_iters_cells", "newton_iters_faces", "n_floor", "n_clamp", "fp_passes", "energy", "e_max"):
+        assert oa[k] == ob[k], (mode, k)
+    assert oa["n_nan"] == 0
+
+
+def test_runs_are_bitwise_reproducible(kt):
+    """The same event run twice: equal fields and reductions (no floating-point
+    atomics in the step; the observables reduce in a fixed two-level order)."""
+    import torch
+    w = I.workload_hotspot(nx=40, ny=36, neta=12, dx=0.5, deta=0.6, n_hot=30, seed=14)
+    out = []
+    for _ in range(2):
+        s = kt.Solver(w.grid, w.config, w.eos, w.prims)
+        s.step(10)
+        out.append((s.fields(), s.observables()))
+    (fa, oa), (fb, ob) = out
+    assert all(torch.equal(fa[k], fb[k]) for k in fa)
+    assert oa == ob
