@@ -499,7 +499,7 @@ class Batch:
     precision, tau0 and dtau.
     """
 
-    def __init__(self, events, eos, tau0=None, device="cuda:0"):
+    def __init__(self, events, eos, tau0=None, device="cuda:0", workspace=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -514,7 +514,13 @@ class Batch:
         if nbytes == 0:
             raise KtError(KT_E_ARG, "invalid batch parameters")
         with torch.cuda.device(self.device):
-            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            # workspace: a caller's uint8 device tensor of at least kt_batch_workspace_bytes
+            # (its contents are not assumed), else a new one
+            if workspace is not None:
+                assert workspace.dtype == torch.uint8 and workspace.numel() >= nbytes
+                self.ws = workspace
+            else:
+                self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             keep = []
             states = (KtInitState * n)(*[_init_state(torch, self.device, g, pr, None, None, keep)
                                          for g, _, pr in events])

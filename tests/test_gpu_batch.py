@@ -153,3 +153,23 @@ def test_two_events_of_the_48_event_set_against_oracle(kt):
             else:
                 assert de.max() <= 1e-9 and du.max() <= 1e-9
         batch.close()
+
+
+def test_batch_with_poisoned_workspace(kt):
+    """A batch workspace filled with 0xFF bytes (NaN in every floating-point
+    view) gives the fields of a zero-filled one, bit for bit, after replays of
+    the step graph: no batched kernel reads unwritten memory."""
+    import ctypes as C
+    import torch
+    evs, eos = events(mixed=True)
+    n = len(evs)
+    params = (kt.KtParams * n)(*[kt.make_params(g, cfg, evs[0][2].tau0) for g, cfg, _ in evs])
+    nbytes = int(kt.lib().kt_batch_workspace_bytes(params, n, C.byref(kt.EosHost(eos).c)))
+    runs = []
+    for fill in (0x00, 0xFF):
+        b = kt.Batch(evs, eos, workspace=torch.full((nbytes,), fill, dtype=torch.uint8, device="cuda"))
+        b.step(5)
+        runs.append([b.fields(k) for k in range(n)])
+        b.close()
+    for k in range(n):
+        assert same(runs[0][k], runs[1][k]), k
