@@ -310,9 +310,20 @@ static double regulate_cell(const ora_params *P, const ora_eos *eos, double tau,
     for (int m = 0; m < 4; ++m)
         for (int n = 0; n < 4; ++n)
             B[m][n] = Pi * ((m == n ? ghi[m] : 0.0) - u[m] * u[n]) + pi[m][n];
+    /* |Pi^{mu nu}|: the Frobenius norm in the fluid rest frame,
+       sqrt(h_{mu a} h_{nu b} B^{mu nu} B^{a b}) with h_{mu a} = 2 u_mu u_a - g_{mu a}
+       (the unit matrix in that frame).  For B transverse to u it is
+       sqrt(B^{mu nu} B_{mu nu}), the paper's norm; the evolved pi is transverse
+       only to truncation error, and there B:B can vanish or be negative. */
+    double h[4][4];
+    for (int m = 0; m < 4; ++m)
+        for (int a = 0; a < 4; ++a)
+            h[m][a] = 2.0 * glo[m] * u[m] * glo[a] * u[a] - (m == a ? glo[m] : 0.0);
     double BB = 0.0;
     for (int m = 0; m < 4; ++m)
-        for (int n = 0; n < 4; ++n) BB += B[m][n] * B[m][n] * glo[m] * glo[n];
+        for (int n = 0; n < 4; ++n)
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) BB += h[m][a] * h[n][b] * B[m][n] * B[a][b];
     double nB = sqrt(fmax(BB, 0.0));
     double rho = nB / (P->rho_max * sqrt(e * e + 3.0 * Pcal * Pcal));
     if (nB > 0.0) {

@@ -321,7 +321,12 @@ __device__ __forceinline__ int recover(const Phys &P, const Eos &E, double tau, 
 // Sec. 3.2: rho = max( |Pi^{mu nu}| / (rho_max sqrt(e^2 + 3 P^2)),
 //                      |pi^mu_mu| / (xi0 rho_max |Pi^{mu nu}|),
 //                      max_l |pi^{l mu} u_mu| / (xi0 rho_max |Pi^{mu nu}|) ),
-// |X| = sqrt(X^{mu nu} X_{mu nu}), Pi^{mu nu} = Pi Delta^{mu nu} + pi^{mu nu},
+// Pi^{mu nu} = Pi Delta^{mu nu} + pi^{mu nu} and |X| its norm in the fluid rest
+// frame, sqrt(h_{mu a} h_{nu b} X^{mu nu} X^{a b}) with h = 2 u u - g: equal to
+// sqrt(X^{mu nu} X_{mu nu}) for a tensor transverse to u, and positive where
+// the evolved pi is not (X:X alone can vanish or turn negative there).  With
+// w^l = pi^{l m} u_m (the bulk part is transverse), |X|^2 = X:X - 4 w.w +
+// 4 (u.w)^2;
 // P = P0 + Pi (the shorthand of Sec. 2.4 that Eq. rho uses),
 // the eta row of pi.u taken in the tetrad (times sqrt(g33)); pi (and Pi
 // when regulate_bulk) are multiplied by tanh(rho)/rho.
@@ -342,24 +347,26 @@ __device__ __forceinline__ double regulate(const Phys &P, double tau, double q[N
             BB += (m == n ? 1.0 : 2.0) * glo[m] * glo[n] * B * B;
         }
     }
-    const double nB = sqrt(fmax(BB, 0.0));
+    const double ul[4] = {u[0], -u[1], -u[2], -g33 * u[3]};
+    double w[4], ww = 0.0, uw = 0.0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        w[l] = 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) w[l] += q[pi_index(l, m)] * ul[m];
+        ww += glo[l] * w[l] * w[l];
+        uw += ul[l] * w[l];
+    }
+    const double nB = sqrt(fmax(BB - 4.0 * ww + 4.0 * uw * uw, 0.0));
     const double Pc = p0 + Pi;
     double rho = nB / (P.rho_max * sqrt(e * e + 3.0 * Pc * Pc));
     if (nB > 0.0) {
         const double tr = q[PTT] - q[PXX] - q[PYY] - g33 * q[PEE];
         const double lim = 1.0 / (P.xi0 * P.rho_max * nB);
         rho = fmax(rho, fabs(tr) * lim);
-        const double ul[4] = {u[0], -u[1], -u[2], -g33 * u[3]};
         double r3 = 0.0;
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            double w = 0.0;
-#pragma unroll
-            for (int m = 0; m < 4; ++m) w += q[pi_index(l, m)] * ul[m];
-            w = fabs(w);
-            if (l == 3) w *= sqrt(g33);
-            r3 = fmax(r3, w);
-        }
+        for (int l = 0; l < 4; ++l) r3 = fmax(r3, fabs(w[l]) * (l == 3 ? sqrt(g33) : 1.0));
         rho = fmax(rho, r3 * lim);
     }
     const double fac = rho > 0.0 ? tanh(rho) / rho : 1.0;

@@ -12,6 +12,8 @@ number below:
 * traceless pi with a component along u (Milne, tau = 2): the third ratio
   decides, its eta row multiplied by tau;
 * a moving fluid with pi^{tau tau} only: the third ratio carries u_tau = gamma;
+* pi off the transverse space with X:X < 0, and a boosted tensor with parts
+  along u: the norm is the Frobenius norm of the rest-frame components;
 * guards of the inversion: floor state and reset of q, and the M^2 clamp.
 """
 import math
@@ -85,33 +87,100 @@ def test_traceful_pi_with_bulk_trace_ratio_decides():
 
 def test_pi_along_u_third_ratio_in_the_orthonormal_frame():
     # Milne, tau = 2, fluid at rest: traceless pi^{xx} = -pi^{yy} = a and a
-    # coordinate component pi^{tau eta} = c, no bulk.
-    # Pi^{mu nu} Pi_{mu nu} = 2 a^2 + 2 g_tt g_ee c^2 = 2 a^2 - 2 tau^2 c^2;
-    # trace 0; pi^{lambda mu} u_mu = pi^{lambda tau}: only lambda = eta, value c,
+    # coordinate component pi^{tau eta} = c, no bulk.  In the rest frame
+    # (orthonormal, the eta row times tau) the components are a, -a and tau c
+    # (twice), so |Pi^{mu nu}|^2 = 2 a^2 + 2 tau^2 c^2 = 0.2; trace 0;
+    # pi^{lambda mu} u_mu = pi^{lambda tau}: only lambda = eta, value c,
     # which is tau c in the orthonormal frame.
     tau, e, a, c = 2.0, 3.0, 0.3, 0.05
-    nB = math.sqrt(2 * a * a - 2 * tau * tau * c * c)       # = 0.4
+    nB = math.sqrt(2 * a * a + 2 * tau * tau * c * c)
     r1 = nB / (RHO_MAX * math.sqrt(e * e + 3.0 * (e / 3.0) ** 2))
-    r3 = tau * abs(c) / (XI0 * RHO_MAX * nB)                 # = 2.5
-    assert abs(nB - 0.4) < 1e-15 and abs(r3 - 2.5) < 1e-14 and r3 > r1
+    r3 = tau * abs(c) / (XI0 * RHO_MAX * nB)                 # = sqrt(5)
+    assert abs(r3 - math.sqrt(5.0)) < 1e-14 and r3 > r1
     pi, _, fac = regulate_one(tau, e, [1, 0, 0, 0], pi10(xx=a, yy=-a, te=c), 0.0, bulk=False)
-    assert abs(fac - tanh_over(2.5)) < 1e-14
-    assert abs(pi[3] - c * tanh_over(2.5)) < 1e-16
-    # without the tau of the orthonormal eta row the ratio would be 1.25
-    assert abs(fac - tanh_over(1.25)) > 0.1
+    assert abs(fac - tanh_over(r3)) < 1e-14
+    assert abs(pi[3] - c * tanh_over(r3)) < 1e-16
+    # without the tau of the orthonormal eta row the ratio would be sqrt(5)/2;
+    # with the norm sqrt(X:X) = sqrt(2 a^2 - 2 tau^2 c^2) = 0.4 it would be 2.5
+    assert abs(fac - tanh_over(math.sqrt(5.0) / 2)) > 0.1 and abs(fac - tanh_over(2.5)) > 0.01
+
+
+def test_norm_stays_positive_where_the_square_is_negative():
+    # Milne, tau = 2, fluid at rest, pi^{xx} = -pi^{yy} = a and pi^{tau eta} = c
+    # with tau |c| > |a|: not transverse to u, and
+    # Pi^{mu nu} Pi_{mu nu} = 2 a^2 - 2 tau^2 c^2 = 0.02 - 0.08 < 0.
+    # The rest-frame norm is sqrt(2 a^2 + 2 tau^2 c^2) = sqrt(0.1); the third
+    # ratio tau |c| / (xi0 nB) decides.  Clipping X:X at zero would give rho = 0
+    # and leave pi as it is.
+    tau, e, a, c = 2.0, 3.0, 0.1, 0.1
+    nB = math.sqrt(2 * a * a + 2 * tau * tau * c * c)
+    r1 = nB / (RHO_MAX * math.sqrt(e * e + 3.0 * (e / 3.0) ** 2))
+    r3 = tau * abs(c) / (XI0 * RHO_MAX * nB)                 # = 2 sqrt(10)
+    assert r3 > r1 and abs(r3 - 2.0 * math.sqrt(10.0)) < 1e-13
+    pi, _, fac = regulate_one(tau, e, [1, 0, 0, 0], pi10(xx=a, yy=-a, te=c), 0.0, bulk=False)
+    assert abs(fac - tanh_over(r3)) < 1e-14 and fac < 0.16
+    assert abs(pi[3] - c * tanh_over(r3)) < 1e-16 and abs(pi[4] - a * tanh_over(r3)) < 1e-16
+
+
+def test_norm_is_the_rest_frame_frobenius_norm_of_a_boosted_tensor():
+    # A tensor given in the fluid rest frame (a traceless spatial part plus
+    # components along u, d0 and d_i), boosted to a fluid moving in x, y and
+    # eta, written in Milne coordinates at tau = 2 (eta row divided by tau).
+    # With e small the first ratio decides, so the factor tanh(r1)/r1 with
+    # r1 = |X| / (rho_max e sqrt(4/3)) measures |X|, which must be the plain
+    # Frobenius norm of the rest-frame components (sqrt(X:X) differs by the
+    # 4 sum d_i^2 of the parts along u).
+    rng = np.random.default_rng(5)
+    tau, e = 2.0, 0.01
+    S = rng.normal(size=(3, 3))
+    S = 0.5 * (S + S.T)
+    S -= np.trace(S) / 3.0 * np.eye(3)
+    Xr = np.zeros((4, 4))
+    Xr[1:, 1:] = S
+    Xr[0, 0] = 0.01
+    Xr[0, 1:] = Xr[1:, 0] = [0.02, -0.015, 0.01]
+    beta = np.array([0.3, -0.4, 0.5])
+    g = 1.0 / math.sqrt(1.0 - beta @ beta)
+    L = np.eye(4)                                      # pure boost, rest frame -> lab
+    L[0, 0] = g
+    L[0, 1:] = L[1:, 0] = g * beta
+    L[1:, 1:] += (g - 1.0) * np.outer(beta, beta) / (beta @ beta)
+    Xt = L @ Xr @ L.T                                  # orthonormal lab components
+    sc = np.array([1.0, 1.0, 1.0, 1.0 / tau])          # to Milne coordinates
+    X = Xt * np.outer(sc, sc)
+    u = g * np.array([1.0, *beta]) * sc
+    assert abs(u[0] ** 2 - u[1] ** 2 - u[2] ** 2 - tau ** 2 * u[3] ** 2 - 1.0) < 1e-14
+    n_rest = math.sqrt(np.sum(Xr * Xr))
+    gm = np.diag([1.0, -1.0, -1.0, -tau * tau])
+    xx = np.sum(X * (gm @ X @ gm))
+    assert abs(math.sqrt(xx) - n_rest) > 4e-4 * n_rest           # the two norms differ here
+    r1 = n_rest / (RHO_MAX * e * math.sqrt(4.0 / 3.0))
+    names = ("tt", "tx", "ty", "te", "xx", "xy", "xe", "yy", "ye", "ee")
+    ij = ((0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (1, 3), (2, 2), (2, 3), (3, 3))
+    pi, _, fac = regulate_one(tau, e, u, pi10(**{n: X[i, j] for n, (i, j) in zip(names, ij)}), 0.0,
+                              bulk=False)
+    # the other two ratios are below 1 here (trace 0.01, |pi.u| about 0.05), the first above 100
+    assert r1 > 100.0
+    assert abs(fac - tanh_over(r1)) < 1e-13 * tanh_over(r1)
 
 
 def test_moving_fluid_third_ratio_uses_lowered_u():
-    # Cartesian, u = (gamma, gamma beta, 0, 0), pi^{tau tau} = s only, no bulk:
-    # Pi^{mu nu} Pi_{mu nu} = s^2; trace g_{mu nu} pi^{mu nu} = s;
+    # Cartesian, u = (gamma, gamma beta, 0, 0), pi^{tau tau} = s only, no bulk.
+    # In the rest frame the components are gamma^2 s (tt), -gamma^2 beta s (tx,
+    # twice) and gamma^2 beta^2 s (xx), so |Pi^{mu nu}| = gamma^2 (1 + beta^2) |s|
+    # = 2.125 |s| for beta = 0.6; trace g_{mu nu} pi^{mu nu} = s;
     # pi^{lambda mu} u_mu: lambda = tau gives s u_tau = s gamma, the others 0.
-    # Ratios: r1 = |s| / (e sqrt(4/3)), r2 = 1/xi0 = 10, r3 = 10 gamma.
+    # Ratios: r1 = 2.125 |s| / (e sqrt(4/3)), r2 = 1/(2.125 xi0),
+    # r3 = gamma/(2.125 xi0) = 5.88.
     beta, e, s = 0.6, 2.0, 0.05
     g = 1.0 / math.sqrt(1.0 - beta * beta)                  # 1.25
+    nB = g * g * (1.0 + beta * beta) * s
+    r3 = s * g / (XI0 * RHO_MAX * nB)
+    assert abs(r3 - 1.25 / 0.2125) < 1e-13
     pi, _, fac = regulate_one(1.0, e, [g, g * beta, 0, 0], pi10(tt=s), 0.0,
                               cartesian=True, bulk=False)
-    assert abs(fac - tanh_over(10.0 * g)) < 1e-14
-    assert abs(pi[0] - s * tanh_over(12.5)) < 1e-16
+    assert abs(fac - tanh_over(r3)) < 1e-14
+    assert abs(pi[0] - s * tanh_over(r3)) < 1e-16
 
 
 def test_floor_state_resets_q():
