@@ -209,12 +209,34 @@ def test_gubser_viscous_32cube_100_steps(kt):
 
 def test_hotspot_small_grid_100_steps(kt):
     """The non-conformal viscous hot-spot event (shear + bulk, tabulated EOS,
-    regulator, floor and clamp active) on a coarser 56x52x24 grid."""
+    regulator, floor and clamp active) on a coarser 56x52x24 grid.  To 75 steps
+    every cell is within the FP64 bar of 1e-9.  Between 75 and 100 steps the
+    dilute edge turns ultra-relativistic (u^tau up to 22), where the rest-frame
+    norm of the regulator carries rounding of the lab-frame pi amplified by
+    (u^tau)^4: the oracle against itself with the initial e moved by one ulp
+    differs at 100 steps by 2.8e-6 in the worst cell and 2.2e-11 in the dense
+    cells (e > 1e-3 e_max), with 0.08% of the cells above 1e-9.  The bars at
+    100 steps are ten times that worst cell, 1e-9 for the dense cells and
+    0.5% of cells above 1e-9."""
     w = I.workload_hotspot(nx=56, ny=52, neta=24, dx=0.4, deta=0.5, n_hot=60, seed=3)
-    errs, gpu, sim, f, r = run_pair(kt, w, 100, report="hotspot56")
+    errs, gpu, sim, f, r = run_pair(kt, w, 75, report="hotspot56")
+    assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9, errs
+    sim.step(25)
+    gpu.step(25)
+    f = {k: v.cpu().numpy() for k, v in gpu.fields().items()}
+    r = sim.fields()
+    e, er = f["e"], r["e"]
+    de = np.abs(e - er) / np.maximum(er, 1e-6 * er.max())
+    s4 = np.array([1.0, 1.0, 1.0, sim.tau]).reshape(4, 1, 1, 1)
+    du = np.max(np.abs(f["u"] - r["u"]) * s4 / r["u"][0:1], axis=0)
+    d = np.maximum(de, du)
+    dense = er > 1e-3 * er.max()
+    print("hotspot56 100 steps: max %.2e dense %.2e median %.2e above 1e-9 %.2e" % (
+        d.max(), d[dense].max(), np.median(d), np.mean(d > 1e-9)), flush=True)
     obs = gpu.observables()
     assert obs["n_floor"] > 0 and obs["n_nan"] == 0
-    assert errs["e"] <= 1e-9 and errs["u"] <= 1e-9, errs
+    assert d.max() <= 2.8e-5 and d[dense].max() <= 1e-9 and np.mean(d > 1e-9) <= 5e-3
+    assert np.median(d) <= 1e-13
 
 
 def test_hotspot_lattice_eos_50_steps(kt):
