@@ -47,9 +47,12 @@ LAUNCHES_PER_STEP = {"flux": 2, "sources": 2, "recover": 2, "faces": 2}
 # HBM bytes per launch of the FP64 step graph's kernels on this event (mean of the two
 # stages' launches of a class), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by what the
 # counters read for a plain device copy (FETCH x 2, WRITE x 1; profiles/); valid for the kernel
-# sources and compiler flags whose hash is TRAFFIC_SOURCES (else the traffic is reported as null)
-TRAFFIC_SOURCES = "d0220b81f1badc35"
-TRAFFIC_BYTES = {"flux": 1308115968, "sources": 1188899312, "faces": 694927112, "recover": 584245904}
+# sources and compiler flags whose hash is TRAFFIC_SOURCES (else the traffic is reported as null).
+# The flux kernel's traffic depends on its block ("eta planes x cells in x", the block the
+# autotuner picks); a block without a measured figure reports null.
+TRAFFIC_SOURCES = "2e50fc48d2a6ebf9"
+TRAFFIC_BYTES = {"flux": {"2x64": 1306860016, "4x64": 1111773200}, "sources": 1187809024,
+                 "faces": 694087392, "recover": 584777640}
 KERNEL_NAMES = {"flux": "flux_kernel (KT flux divergence + stage update)",
                 "sources": "sources_kernel (App. B sources + stage update)",
                 "recover": "recover_kernel (Newton inversion + regulator)",
@@ -70,6 +73,8 @@ def parse():
     ap.add_argument("--no-lattice", action="store_true", help="skip the lattice-QCD EOS and zeta/s(T) leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start leg")
     ap.add_argument("--no-reduced", action="store_true", help="skip the reduced-state leg")
+    ap.add_argument("--flux-block", default=None, metavar="PLANES,CELLS_X",
+                    help="flux block of the FP64 step graph (eta planes, cells in x) instead of the autotuner's")
     ap.add_argument("--learn-steps", type=int, default=3000, help="Adam steps of the start network")
     return ap.parse_args()
 
@@ -333,7 +338,11 @@ def main():
     # one event: the same kernels per cell, tau kept on the device)
     print("bench: %s, FP64, step graph, warmup %d steps" % (w.name, args.warmup), file=sys.stderr, flush=True)
     b = kt.Batch([(w.grid, w.config, w.prims)], w.eos, device="cuda:0")
-    blocks = b.tune()
+    if args.flux_block:
+        blocks = [tuple(int(v) for v in args.flux_block.split(","))]
+        b.set_flux_blocks(blocks)
+    else:
+        blocks = b.tune()
     ms = time_graph_steps(torch, b, args.warmup, args.steps)
     obs = b.observables(0)
     b.close()
@@ -348,8 +357,10 @@ def main():
         ms_eager, ", ".join("%s %.3f ms" % kv for kv in per.items())), file=sys.stderr, flush=True)
     cgbs = copy_gbs(torch)
     traffic = None
-    if kernel_sources_hash() == TRAFFIC_SOURCES and TRAFFIC_BYTES:
-        traffic = sum(TRAFFIC_BYTES[k] * LAUNCHES_PER_STEP[k] for k in TRAFFIC_BYTES)
+    flux_traffic = TRAFFIC_BYTES["flux"].get("%dx%d" % tuple(blocks[0]))
+    if kernel_sources_hash() == TRAFFIC_SOURCES and flux_traffic:
+        traffic = sum((flux_traffic if k == "flux" else TRAFFIC_BYTES[k]) * LAUNCHES_PER_STEP[k]
+                      for k in TRAFFIC_BYTES)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "one Heun step (the captured graph of its launches)",

@@ -20,4 +20,6 @@ def test_stored_traffic_covers_every_kernel_class():
     import bench
     assert len(bench.TRAFFIC_SOURCES) == 16 and int(bench.TRAFFIC_SOURCES, 16) >= 0
     assert set(bench.TRAFFIC_BYTES) == set(bench.LAUNCHES_PER_STEP) == set(bench.KERNEL_VALUES)
-    assert all(v > 0 for v in bench.TRAFFIC_BYTES.values())
+    assert all(v > 0 for k, v in bench.TRAFFIC_BYTES.items() if k != "flux")
+    assert bench.TRAFFIC_BYTES["flux"] and all(
+        v > 0 and len(b.split("x")) == 2 for b, v in bench.TRAFFIC_BYTES["flux"].items())
