@@ -310,20 +310,32 @@ static double regulate_cell(const ora_params *P, const ora_eos *eos, double tau,
     for (int m = 0; m < 4; ++m)
         for (int n = 0; n < 4; ++n)
             B[m][n] = Pi * ((m == n ? ghi[m] : 0.0) - u[m] * u[n]) + pi[m][n];
-    /* |Pi^{mu nu}|: the Frobenius norm in the fluid rest frame,
-       sqrt(h_{mu a} h_{nu b} B^{mu nu} B^{a b}) with h_{mu a} = 2 u_mu u_a - g_{mu a}
-       (the unit matrix in that frame).  For B transverse to u it is
-       sqrt(B^{mu nu} B_{mu nu}), the paper's norm; the evolved pi is transverse
-       only to truncation error, and there B:B can vanish or be negative. */
-    double h[4][4];
-    for (int m = 0; m < 4; ++m)
-        for (int a = 0; a < 4; ++a)
-            h[m][a] = 2.0 * glo[m] * u[m] * glo[a] * u[a] - (m == a ? glo[m] : 0.0);
+    /* |Pi^{mu nu}|: the Frobenius norm of its components in the fluid rest
+       frame.  For B transverse to u it is sqrt(B^{mu nu} B_{mu nu}), the paper's
+       norm; the evolved pi is transverse only to truncation error, and there
+       B:B can vanish or be negative.  The rest-frame components: B in the
+       orthonormal frame of the coordinates (the eta row and column times
+       sqrt(-g_33)), then the pure boost L with L u = (1, 0, 0, 0):
+       L^0_0 = gamma, L^0_i = L^i_0 = -u^i, L^i_j = delta_ij + u^i u^j / (1 + gamma). */
+    double sc[4], ut[4];
+    for (int m = 0; m < 4; ++m) {
+        sc[m] = sqrt(fabs(glo[m]));
+        ut[m] = u[m] * sc[m];
+    }
+    double L[4][4];
+    L[0][0] = ut[0];
+    for (int i = 1; i < 4; ++i) {
+        L[0][i] = L[i][0] = -ut[i];
+        for (int j = 1; j < 4; ++j) L[i][j] = (i == j ? 1.0 : 0.0) + ut[i] * ut[j] / (1.0 + ut[0]);
+    }
     double BB = 0.0;
-    for (int m = 0; m < 4; ++m)
-        for (int n = 0; n < 4; ++n)
-            for (int a = 0; a < 4; ++a)
-                for (int b = 0; b < 4; ++b) BB += h[m][a] * h[n][b] * B[m][n] * B[a][b];
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            double s = 0.0;
+            for (int m = 0; m < 4; ++m)
+                for (int n = 0; n < 4; ++n) s += L[a][m] * L[b][n] * B[m][n] * sc[m] * sc[n];
+            BB += s * s;
+        }
     double nB = sqrt(fmax(BB, 0.0));
     double rho = nB / (P->rho_max * sqrt(e * e + 3.0 * Pcal * Pcal));
     if (nB > 0.0) {
